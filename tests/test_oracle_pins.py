@@ -1,0 +1,441 @@
+"""Pins of the FP64 oracle against what the paper prints and what mathematics fixes.
+
+None of these tests re-types an oracle formula: each compares the oracle with a
+printed value (tests/golden/paper_values.json), a closed form, a conservation law or
+an independent library routine."""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.optimize as so
+import scipy.sparse as sp
+
+import workloads as W
+from oracle import fv as FV
+from oracle import gmg as G
+from oracle import krylov as KR
+from oracle import limex as LX
+from oracle import stage as ST
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+
+
+def make_scn(dim, n, extent, perm=1e-11, poro=0.3, pd=1000.0, lam=2.0, gravity=(0, 0, 0),
+             rho=(1000.0, 1000.0), mu=(1e-3, 1e-3), s_res=(0.0, 0.0), u=None, levels=1):
+    scn = W._empty("pin", dim, n, extent, gravity)
+    scn.rho, scn.mu, scn.s_res = tuple(rho), tuple(mu), tuple(s_res)
+    nc = scn.ncells
+    scn.perm = np.broadcast_to(np.asarray(perm, float), (nc,)).copy()
+    scn.poro = np.broadcast_to(np.asarray(poro, float), (nc,)).copy()
+    scn.entry_p = np.broadcast_to(np.asarray(pd, float), (nc,)).copy()
+    scn.bc_lambda = np.broadcast_to(np.asarray(lam, float), (nc,)).copy()
+    if u is not None:
+        scn.u0 = u
+    scn.levels = levels
+    return scn
+
+
+# ---------------------------------------------------------------------------------
+# Constitutive laws and the interface condition, pinned by printed numbers.
+# ---------------------------------------------------------------------------------
+def test_buckley_leverett_front_speed_matches_paper():
+    """Welge tangent construction with the oracle's Burdine k_r (lambda = 2, p_c = 0)
+    reproduces the front speed printed for Case-1."""
+    g = GOLD["bl_front_speed"]
+    p = g["params"]
+
+    def fw(sw):
+        sn = 1.0 - sw
+        kw = FV.krw_bc(sn, p["lambda"], p["swr"], p["snr"]) / p["mu_w"]
+        kn = FV.krn_bc(sn, p["lambda"], p["swr"], p["snr"]) / p["mu_n"]
+        return kw / (kw + kn)
+
+    def dfw(sw, h=1e-7):
+        return (fw(sw + h) - fw(sw - h)) / (2 * h)
+
+    # tangent from the initial state S_w = 0: f'(S_f) = f(S_f) / S_f
+    sf = so.brentq(lambda s: dfw(s) - fw(s) / s, 0.3, 0.99)
+    u_total = p["mass_flux"] / p["rho_w"]
+    v = u_total / p["phi"] * dfw(sf)
+    assert abs(v - g["value"]) / g["value"] < 0.5e-2
+    assert round(v, 8) == pytest.approx(g["value"], rel=5e-3)
+
+
+def test_barrier_threshold_matches_paper():
+    """The case-2/case-3 switch of the hat saturation for a vertex on the interface
+    of Case-4 layers 2 and 3 sits at the printed S_w* = 0.7778."""
+    g = GOLD["barrier_threshold"]
+    p = g["params"]
+    pd2 = p["pd_coef"] * p["K2"] ** p["pd_exp"]
+    pd3 = p["pd_coef"] * p["K3"] ** p["pd_exp"]
+    assert pd3 > pd2
+    swr, snr, lam = p["swr"], p["snr"], p["lambda"]
+
+    def is_barrier(sw):
+        sn = np.array([1.0 - sw])
+        sh = FV.hat_sn(sn, pd2, lam, np.array([pd3]), lam, swr, snr)
+        return sh[0] == snr
+
+    lo, hi = 0.5, 0.9  # barrier below lo? no: high S_w (low p_c) is a barrier
+    assert is_barrier(hi) and not is_barrier(lo)
+    for _ in range(60):
+        mid = 0.5 * (lo + hi)
+        if is_barrier(mid):
+            hi = mid
+        else:
+            lo = mid
+    assert round(hi, 4) == pytest.approx(g["value"], abs=1e-4)
+
+
+def test_hat_cases_and_continuity():
+    swr, snr, lam = 0.2, 0.1, 2.0
+    sn = np.linspace(0.0, 0.69, 500)
+    # case 1: the reference medium returns the vertex saturation
+    np.testing.assert_array_equal(FV.hat_sn(sn, 1000.0, lam, 1000.0, lam, swr, snr), sn)
+    # continuity of S^ across the case-2/case-3 boundary as p_d,e approaches P_i from below
+    pdmin = 1000.0
+    for s in (0.2, 0.4, 0.6):
+        P = FV.pc_bc(np.array([s]), pdmin, lam, swr, snr)[0]
+        below = FV.hat_sn(np.array([s]), pdmin, lam, np.array([P * (1 - 1e-9)]), lam, swr, snr)[0]
+        at = FV.hat_sn(np.array([s]), pdmin, lam, np.array([P]), lam, swr, snr)[0]
+        assert at == snr
+        assert abs(below - snr) < 1e-7
+    # case 3 preserves the capillary pressure: p_c,e(S^) = P_i
+    pde = 1300.0
+    s = np.array([0.5])
+    sh = FV.hat_sn(s, pdmin, lam, np.array([pde]), lam, swr, snr)
+    assert FV.pc_bc(sh, pde, lam, swr, snr)[0] == pytest.approx(FV.pc_bc(s, pdmin, lam, swr, snr)[0],
+                                                               rel=1e-13)
+
+
+def test_dof_counts_two_unknowns_per_vertex():
+    for dim, cells, dof in GOLD["dof_counts"]["rows"]:
+        assert 2 * int(np.prod([c + 1 for c in cells])) == dof
+
+
+# ---------------------------------------------------------------------------------
+# Discretisation: exactness, equilibrium and conservation.
+# ---------------------------------------------------------------------------------
+@pytest.mark.parametrize("dim", [2, 3])
+def test_linear_pressure_single_phase_exact(dim):
+    n = (9, 5, 1) if dim == 2 else (7, 5, 4)
+    ext = (2.0, 1.0, 1.0) if dim == 2 else (1.2, 0.8, 0.6)
+    scn = make_scn(dim, n, ext, perm=3e-11, pd=500.0)
+    x, y, z = scn.vertex_coords()
+    a = 250.0
+    u = np.stack([1e5 + a * x, np.zeros_like(x)], axis=1)
+    f = FV.FV(scn)
+    F = f.residual_raw(u)
+    scale = 1000.0 * 3e-11 / 1e-3 * a * np.prod(ext[1:dim])
+    interior = (x > 1e-12) & (x < ext[0] - 1e-12)
+    assert np.max(np.abs(F[interior])) < 1e-11 * scale
+    # total inflow through x = 0 equals Darcy's law times the cross-section
+    left = np.isclose(x, 0.0)
+    assert F[left, 0].sum() == pytest.approx(1000.0 * 3e-11 * a / 1e-3 * np.prod(ext[1:dim]), rel=1e-12)
+    assert np.max(np.abs(F[:, 1])) < 1e-14 * scale
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_hydrostatic_equilibrium(dim):
+    n = (6, 7, 1) if dim == 2 else (5, 4, 6)
+    ext = (1.0, 2.0, 1.0) if dim == 2 else (1.0, 1.0, 2.0)
+    gvec = [0.0, 0.0, 0.0]
+    gvec[dim - 1] = -9.81
+    rng = np.random.default_rng(0)
+    scn = make_scn(dim, n, ext, perm=np.exp(-25 + rng.standard_normal(W._empty("t", dim, n, ext, gvec).ncells)),
+                   gravity=gvec, rho=(1000.0, 1000.0))
+    coords = scn.vertex_coords()
+    zz = coords[dim - 1]
+    H = ext[dim - 1]
+    p = 1e5 + 1000.0 * 9.81 * (H - zz)
+    # single phase
+    u = np.stack([p, np.zeros_like(p)], axis=1)
+    F = FV.FV(scn).residual_raw(u)
+    assert np.max(np.abs(F)) < 1e-10 * 1000.0 * np.exp(-25) / 1e-3 * 1000 * 9.81
+    # equal densities, uniform S_n in one medium: both phases at rest
+    scn2 = make_scn(dim, n, ext, perm=1e-11, gravity=gvec, rho=(1000.0, 1000.0))
+    u2 = np.stack([p, np.full_like(p, 0.3)], axis=1)
+    F2 = FV.FV(scn2).residual_raw(u2)
+    assert np.max(np.abs(F2)) < 1e-9 * 1000.0 * 1e-11 / 1e-3 * 1000 * 9.81
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_discrete_conservation(dim):
+    scn = W.lens_2d(17, 9) if dim == 2 else W.small_cube(7, sigma=1.5, seed=3)
+    u = W.perturbed_state(scn, 7)
+    f = FV.FV(scn)
+    Fr = f.residual_raw(u)
+    flux_scale = np.abs(f.flux_divergence(u)).sum(axis=0)
+    for ph in range(2):
+        assert abs(Fr[:, ph].sum() - f.Q[:, ph].sum()) <= 1e-12 * max(flux_scale[ph], f.Q[:, ph].sum(), 1e-300)
+    # column sums of the flux Jacobian vanish
+    J = f.jacobian(u, which="residual")
+    keep = np.ones(2 * f.N)
+    keep[f.dirichlet_dofs()] = 0
+    Jr = sp.csr_matrix(J)
+    # rebuild without Dirichlet clearing: J_raw = dF_raw/du via complex step of the raw residual
+    fr = FV.FV(scn)
+    fr.dir_mask = np.zeros_like(fr.dir_mask)
+    Jraw = fr.jacobian(u)
+    colsum = np.asarray(Jraw.sum(axis=0)).ravel()
+    assert np.max(np.abs(colsum)) < 1e-12 * np.max(np.abs(Jraw).sum(axis=0))
+    assert Jr.shape == Jraw.shape
+
+
+def test_storage_total_mass_and_mass_matrix():
+    scn = make_scn(3, (5, 4, 3), (1.0, 0.6, 0.4), poro=0.25, rho=(1000.0, 1460.0))
+    f = FV.FV(scn)
+    u = np.stack([np.full(scn.nverts, 1e5), np.full(scn.nverts, 0.35)], axis=1)
+    m = f.storage(u)
+    vol = 1.0 * 0.6 * 0.4
+    assert m[:, 1].sum() == pytest.approx(0.25 * 1460.0 * 0.35 * vol, rel=1e-13)
+    assert m[:, 0].sum() == pytest.approx(0.25 * 1000.0 * 0.65 * vol, rel=1e-13)
+    M = f.mass_matrix(u).toarray()
+    assert np.all(M[:, 0::2] == 0.0)
+    # dm_n/dS_n = Phi rho_n |b_i| in one medium (case 1 everywhere)
+    dual = LX.Norms(f).dual
+    np.testing.assert_allclose(np.diag(M)[1::2], 0.25 * 1460.0 * dual, rtol=1e-13)
+
+
+def _row_1d(n, ext):
+    return make_scn(2, (n, 3, 1), (ext, 0.2, 1.0))
+
+
+def test_capillary_flux_reduces_to_two_point_form():
+    """S_n varying along x only, uniform p_w, no gravity: the non-wetting balance of an
+    interior vertex is the textbook two-point capillary diffusion."""
+    n, L = 9, 0.8
+    scn = make_scn(2, (n, 3, 1), (L, 0.2, 1.0), perm=2e-11, pd=1500.0, lam=2.5, mu=(1e-3, 9e-4),
+                   rho=(1000.0, 1460.0))
+    x, y, _ = scn.vertex_coords()
+    sn = 0.1 + 0.5 * (x / L) ** 2
+    u = np.stack([np.full_like(x, 1e5), sn], axis=1)
+    F = FV.FV(scn).residual_raw(u)
+    dx = L / (n - 1)
+    dy = 0.1
+
+    def face(s0, s1):
+        pc0 = 1500.0 * (1 - s0) ** (-1 / 2.5)
+        pc1 = 1500.0 * (1 - s1) ** (-1 / 2.5)
+        sm = 0.5 * (s0 + s1)
+        se = 1 - sm
+        krn = (1 - se) ** 2 * (1 - se ** ((2 + 2.5) / 2.5))
+        return -1460.0 * krn * 2e-11 / 9e-4 * (pc1 - pc0) / dx * dy
+
+    for i in range(1, n - 1):
+        v = i + n * 1  # middle row: full dual face of height dy
+        s_m, s_0, s_p = sn[v - 1], sn[v], sn[v + 1]
+        expect = -(face(s_0, s_p) - face(s_m, s_0))
+        assert F[v, 1] == pytest.approx(expect, rel=1e-12)
+        assert abs(F[v, 0]) < 1e-25
+
+
+def test_upwind_convective_flux_two_point_form():
+    """Linear p_w along x, p_c = 0, S_n varying along x: each interior balance is the
+    difference of fully upwinded two-point fluxes (upwind = the side the flow comes from)."""
+    n, L = 9, 0.8
+    a = -400.0  # pressure falls along +x: flow along +x, upwind = left vertex
+    scn = make_scn(2, (n, 3, 1), (L, 0.2, 1.0), perm=2e-11, pd=0.0, lam=2.0, mu=(1e-3, 5e-3))
+    x, y, _ = scn.vertex_coords()
+    sn = 0.2 + 0.5 * np.sin(3 * x) ** 2
+    u = np.stack([1e5 + a * x, sn], axis=1)
+    F = FV.FV(scn).residual_raw(u)
+    dy = 0.1
+    qw = -2e-11 / 1e-3 * a * dy
+    qn = -2e-11 / 5e-3 * a * dy
+    for i in range(1, n - 1):
+        v = i + n
+        se_l, se_c = 1 - sn[v - 1], 1 - sn[v]
+        fw_in, fw_out = 1000 * se_l ** 4 * qw, 1000 * se_c ** 4 * qw
+        fn_in = 1000 * (1 - se_l) ** 2 * (1 - se_l ** 2) * qn
+        fn_out = 1000 * (1 - se_c) ** 2 * (1 - se_c ** 2) * qn
+        assert F[v, 0] == pytest.approx(fw_in - fw_out, rel=1e-12)
+        assert F[v, 1] == pytest.approx(fn_in - fn_out, rel=1e-12)
+
+
+def test_neumann_patch_total():
+    scn = W.small_cube(9)
+    f = FV.FV(scn)
+    assert f.Q[:, 1].sum() == pytest.approx(0.075 * 0.2 * 0.2, rel=1e-13)
+    assert f.Q[:, 0].sum() == 0.0
+    scn2 = W.lens_2d()
+    f2 = FV.FV(scn2)
+    assert f2.Q[:, 1].sum() == pytest.approx(0.075 * 0.2, rel=1e-13)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_jacobian_complex_step_vs_central_differences(dim):
+    scn = W.lens_2d(9, 5) if dim == 2 else W.small_cube(4, sigma=1.0, seed=5)
+    u = W.perturbed_state(scn, 3, sn_lo=0.05, sn_hi=0.5)
+    f = FV.FV(scn)
+    J = f.jacobian(u).toarray()
+    uf = u.ravel()
+    rng = np.random.default_rng(1)
+    cols = rng.choice(2 * f.N, size=min(24, 2 * f.N), replace=False)
+    # S_n columns: second-order one-sided differences towards larger S_n, because the
+    # Dirichlet vertices sit at S_n = 0, i.e. exactly on the S_e = 1 clamp, where the
+    # derivative is the analytic (S_e <= 1) one-sided derivative.
+    cols = np.concatenate([cols, 2 * np.nonzero(f.dir_mask)[0][:4] + 1])
+    fmax = np.max(np.abs(f.residual(u)))
+    for c in cols:
+        hstep = 1e-2 if c % 2 == 0 else 1e-6
+
+        def Fat(delta):
+            uu = uf.copy()
+            uu[c] += delta
+            return f.residual(uu.reshape(-1, 2)).ravel()
+
+        if c % 2 == 0:
+            fd = (Fat(hstep) - Fat(-hstep)) / (2 * hstep)
+        else:
+            fd = (-3 * Fat(0.0) + 4 * Fat(hstep) - Fat(2 * hstep)) / (2 * hstep)
+        scale = np.max(np.abs(J[:, c])) + 1e-300
+        noise = 8 * np.finfo(float).eps * fmax / hstep
+        assert np.max(np.abs(fd - J[:, c])) <= 1e-5 * scale + noise
+
+
+# ---------------------------------------------------------------------------------
+# Multigrid, Krylov and dense-LU checks.
+# ---------------------------------------------------------------------------------
+def test_prolongation_reproduces_linear_functions():
+    n = (9, 5, 5)
+    P = G.prolongation(n, 3)
+    sizes = G.level_sizes(n, 3, 2)
+    nc = sizes[1]
+    zc, yc, xc = np.meshgrid(np.arange(nc[2]) * 2.0, np.arange(nc[1]) * 2.0, np.arange(nc[0]) * 2.0,
+                             indexing="ij")
+    zf, yf, xf = np.meshgrid(np.arange(n[2]) * 1.0, np.arange(n[1]) * 1.0, np.arange(n[0]) * 1.0,
+                             indexing="ij")
+    lin_c = np.stack([3 * xc - yc + 2 * zc + 1, xc + 5], axis=-1).ravel()
+    lin_f = np.stack([3 * xf - yf + 2 * zf + 1, xf + 5], axis=-1).ravel()
+    np.testing.assert_allclose(P @ lin_c, lin_f, rtol=0, atol=1e-13)
+
+
+def test_galerkin_and_two_grid_contraction():
+    scn = W.lens_2d(17, 9)
+    st = ST.Stage(scn, levels=2)
+    u = W.perturbed_state(scn, 2, sn_lo=0.05, sn_hi=0.3)
+    A = st.assemble(u.ravel(), 32.0)
+    H = st.H
+    P = H.P[0].toarray()
+    np.testing.assert_allclose(H.A[1].toarray(), P.T @ A.toarray() @ P,
+                               rtol=0, atol=1e-12 * np.abs(A).max())
+    # two-grid iteration with exact coarse solve contracts the error
+    xs = np.random.default_rng(0).standard_normal(A.shape[0])
+    b = A @ xs
+    x = np.zeros_like(b)
+    errs = []
+    for _ in range(10):
+        x = x + H.vcycle(b - A @ x)
+        errs.append(np.linalg.norm(x - xs))
+    assert all(errs[i + 1] < errs[i] for i in range(9))
+    assert errs[-1] < 1e-2 * errs[0]
+
+
+@pytest.mark.parametrize("case", ["2d9x5", "2d9x9", "3d5"])
+def test_bicgstab_gmg_matches_dense_lu(case):
+    if case == "2d9x5":
+        scn = W.lens_2d(9, 5); scn.levels = 2
+    elif case == "2d9x9":
+        scn = W.lens_2d(9, 9); scn.levels = 3
+    else:
+        scn = W.small_cube(5, seed=9); scn.levels = 2
+    u = W.perturbed_state(scn, 4, sn_lo=0.05, sn_hi=0.4)
+    st = ST.Stage(scn)
+    A = st.assemble(u.ravel(), 10.0)
+    F = st.residual(u.ravel())
+    x, info = st.solve(F, rtol=1e-13, maxit=200)
+    xd = np.linalg.solve(A.toarray(), F)
+    for c in range(2):
+        ref = xd[c::2]
+        assert np.linalg.norm(x[c::2] - ref) <= 1e-10 * np.linalg.norm(ref)
+    assert info["rel_res_true"] < 1e-12
+
+
+def test_bicgstab_on_nonsymmetric_matrix_vs_lu():
+    rng = np.random.default_rng(3)
+    n = 60
+    A = np.eye(n) * 4 + rng.standard_normal((n, n)) * 0.3
+    b = rng.standard_normal(n)
+    x, info = KR.bicgstab(A, b, lambda v: v, rtol=1e-14, maxit=400)
+    np.testing.assert_allclose(x, sla.lu_solve(sla.lu_factor(A), b), rtol=1e-11, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------------
+# LIMEX: closed forms on the scalar test equation, observed order, norms.
+# ---------------------------------------------------------------------------------
+def _scalar_limex(lam, H, k):
+    return LX.limex_step(np.array([1.0]), H, k, lambda v: lam * v,
+                         lambda h: (lambda f: f / (1.0 / h - lam)),
+                         lambda a, b: float(abs(a - b)[0] / abs(a)[0]), 1e9, 1.0, 1e9)
+
+
+def test_limex_scalar_closed_forms():
+    lam, H = -3.0, 0.2
+    out, acc, eps, dtn, kk = _scalar_limex(lam, H, 2)
+    T11 = 1.0 / (1.0 - H * lam)
+    T21 = (1.0 - H * lam / 2.0) ** -2
+    assert kk[0] == pytest.approx(2 * T21 - T11, rel=1e-15)
+    out3 = _scalar_limex(lam, H, 3)[4]
+    T31 = (1.0 - H * lam / 3.0) ** -3
+    T32 = T31 + (T31 - T21) / (3.0 / 2.0 - 1.0)
+    T22 = 2 * T21 - T11
+    T33 = T32 + (T32 - T22) / (3.0 - 1.0)
+    assert out3[0] == pytest.approx(T33, rel=1e-14)
+
+
+@pytest.mark.parametrize("k,order", [(2, 2), (3, 3)])
+def test_limex_observed_order(k, order):
+    lam = -2.0
+    errs = []
+    for H in (0.025, 0.0125, 0.00625):
+        kk = _scalar_limex(lam, H, k)[4][0]
+        errs.append(abs(kk - np.exp(lam * H)))
+    rates = [np.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    # local error of an order-k extrapolated linearly implicit Euler is O(H^(k+1))
+    assert min(rates) > order + 0.75
+
+
+def test_step_size_rule_by_hand():
+    assert LX.step_size(10.0, 0.001, 5e-3, 0.75, 1e9) == pytest.approx(10.0 * (3.75) ** (1 / 3), rel=1e-15)
+    assert LX.step_size(10.0, 0.0, 5e-3, 0.75, 100.0) == 100.0
+
+
+def test_norms_closed_forms():
+    scn = make_scn(3, (5, 4, 6), (1.0, 0.5, 2.0))
+    f = FV.FV(scn)
+    nm = LX.Norms(f)
+    x, y, z = scn.vertex_coords()
+    assert nm.grad_sq(2 * x - 3 * y + 0.5 * z) == pytest.approx((4 + 9 + 0.25) * 1.0, rel=1e-13)
+    # bilinear p = x*y on [0,1]x[0,0.5]x[0,2]: int (y^2 + x^2) = 2*(1/24 + 1/6)
+    assert nm.grad_sq(x * y) == pytest.approx(2.0 * (0.5 ** 3 / 3 + 0.5 / 3), rel=1e-13)
+    assert nm.sat_sq(np.full(scn.nverts, 0.7)) == pytest.approx(0.49 * 1.0, rel=1e-13)
+
+
+def test_random_field_statistics():
+    g = W.gaussian_field((64, 64, 64), 8.0, 1.5, seed=1)
+    assert abs(g.var() / 1.5 ** 2 - 1) < 0.25
+    c8 = np.mean(g[:, :, :-8] * g[:, :, 8:])
+    assert abs(c8 / (1.5 ** 2 * np.exp(-1.0)) - 1) < 0.35
+    g2 = W.gaussian_field((64, 64, 64), 8.0, 1.5, seed=1)
+    np.testing.assert_array_equal(g, g2)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_integration_point_exact_for_bilinear_pressure(dim):
+    """For p = x*y the normal derivative is linear along each SCVF, so the midpoint
+    (barycentre) rule is exact: the corner vertex balance equals the exact integral
+    of the Darcy flux over its two (three) interior faces."""
+    n = (5, 4, 1) if dim == 2 else (5, 4, 3)
+    ext = (1.0, 0.6, 1.0) if dim == 2 else (1.0, 0.6, 0.5)
+    scn = make_scn(dim, n, ext, perm=2e-11, pd=300.0)
+    x, y, z = scn.vertex_coords()
+    u = np.stack([1e5 + 1e3 * x * y, np.zeros_like(x)], axis=1)
+    F = FV.FV(scn).residual_raw(u)
+    dx, dy, dz = scn.spacing
+    depth = dz / 2 if dim == 3 else 1.0
+    # inflow into b_0 = K/mu rho * (int_{x-face} dp/dx + int_{y-face} dp/dy); z-face: dp/dz = 0
+    expect = 1000.0 * 2e-11 / 1e-3 * 1e3 * (dy ** 2 / 8 + dx ** 2 / 8) * depth
+    assert F[0, 0] == pytest.approx(expect, rel=1e-12)
