@@ -1,0 +1,228 @@
+/*
+ * tpf.h -- C ABI of the MI355X (gfx950) two-phase porous-media stage solver.
+ *
+ * The library implements, on one GPU, the hot path of a fully coupled, fully
+ * implicit two-phase (p_w, S_n) Darcy solver discretised with vertex-centred finite
+ * volumes (the box method) on structured Q1 quads/hexes:
+ *
+ *   - create_grid:    upload the scenario, pre-process p_dmin per vertex
+ *                     (interface condition, Section 3.3, Eq. pdmin) and the
+ *                     Neumann sources;
+ *   - residual:       F(u) of the semi-discrete system M(u) u' = F(u) (Section 4),
+ *                     built from the storage and SCVF flux sums (Section 3.1,
+ *                     Eqs. dsW/dpN) with upwinded mobilities (Section 3.2,
+ *                     Eqs. up_krw/up_krn) and the p_dmin saturation rule
+ *                     (Eq. hSw, krn_ip, krw_ip);
+ *   - assemble_stage: A = M(u0)/h - J(u0), the linearly implicit Euler matrix of
+ *                     Section 4 divided by the step, as 2x2-block 27-point (3D) or
+ *                     9-point (2D) stencil rows, plus the geometric-multigrid
+ *                     hierarchy (Galerkin coarse operators) used as preconditioner;
+ *   - solve_stage:    A x = f by BiCGSTAB preconditioned with one GMG V-cycle
+ *                     (the linear solver named in Section 1 and Section 5);
+ *   - limex_step:     one adaptive LIMEX step (Section 4: linearly implicit
+ *                     extrapolation, error estimate in the scaled norm Eq. norm_u,
+ *                     step-size rule with q = 2).
+ *
+ * Conventions
+ *   - Device pointers are HIP device addresses owned by the caller (e.g. from a
+ *     PyTorch CUDA/ROCm tensor).  The library never allocates device memory: all of
+ *     its device state lives in a caller-provided arena of tpf_grid_bytes() bytes.
+ *   - State/vector layout: double[2*N], interleaved (p_w [Pa], S_n [-]) per vertex,
+ *     vertex index ix + nx*(iy + ny*iz) (x fastest).  Row 2v of a residual or
+ *     matrix is the wetting-phase mass balance of vertex v, row 2v+1 the
+ *     non-wetting one (kg/s).
+ *   - Cell arrays have (nx-1)(ny-1)(nz-1) entries (2D: (nx-1)(ny-1)), x fastest.
+ *   - Every call is asynchronous on the given stream unless stated; a grid must be
+ *     used from one stream at a time.  Different grids are independent.
+ *   - Status: 0 ok, > 0 soft outcome (outputs valid, see stats), < 0 hard error
+ *     (outputs untouched); tpf_last_error() gives the message of the calling
+ *     thread's last failure.
+ */
+#ifndef TPF_H
+#define TPF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t tpf_status;
+typedef struct tpf_grid tpf_grid; /* opaque; host metadata only */
+typedef struct ihipStream_t *tpf_stream; /* hipStream_t */
+
+enum {
+  TPF_OK = 0,
+  TPF_NOT_CONVERGED = 1,  /* solve hit maxit: x holds the last iterate        */
+  TPF_STEP_REJECTED = 2,  /* limex: error > TOL, u and t unchanged, dt reduced */
+  TPF_EINVAL = -1,        /* invalid argument / descriptor                     */
+  TPF_ENOMEM = -2,        /* arena too small or misaligned                     */
+  TPF_EDEVICE = -3,       /* HIP runtime error                                 */
+  TPF_EBREAKDOWN = -4,    /* BiCGSTAB breakdown after one restart, or NaN      */
+  TPF_ESTATE = -5         /* call out of order (e.g. solve before assemble)    */
+};
+
+enum { TPF_FP64 = 0, TPF_MIXED = 1 };
+
+/* Boundary injection patch: a rectangle on one face of the box with a mass rate
+ * of one phase per unit face measure into the domain (kg/(m^2 s) in 3D,
+ * kg/(m s) in 2D).  This is the Neumann condition of Section 2 (Eqs. BsWn/BpNn)
+ * restricted to inflow patches.  lo/hi are bounds in the remaining axes in
+ * increasing axis order (2D: only lo[0], hi[0]).  The library integrates the rate
+ * exactly over each vertex's dual-box face. */
+typedef struct tpf_patch {
+  int32_t axis;    /* face normal axis 0,1,2                         */
+  int32_t side;    /* 0: coordinate 0; 1: coordinate = extent[axis] */
+  int32_t phase;   /* 0 wetting, 1 non-wetting                      */
+  int32_t reserved;
+  double lo[2], hi[2];
+  double rate;
+} tpf_patch;
+
+#define TPF_MAX_PATCHES 8
+
+/* Scenario: the problem statement of Section 2 (domain, per-element porosity,
+ * isotropic permeability and Brooks-Corey parameters, fluids, gravity, Dirichlet
+ * and Neumann data) plus the multigrid settings.  Host pointers are read during
+ * tpf_create_grid only. */
+typedef struct tpf_grid_desc {
+  int32_t dim;           /* 2 or 3                                              */
+  int32_t n[3];          /* vertices per axis; n[2] = 1 in 2D                   */
+  double extent[3];      /* m (extent[2] ignored in 2D: unit depth)             */
+  double gravity[3];     /* m/s^2                                               */
+  double rho[2];         /* kg/m^3, [wetting, non-wetting]                      */
+  double mu[2];          /* Pa s                                                */
+  double s_res[2];       /* S_wr, S_nr                                          */
+  const double *perm;    /* host, per cell, K [m^2] > 0                          */
+  const double *poro;    /* host, per cell, porosity in (0, 1]                  */
+  const double *entry_p; /* host, per cell, Brooks-Corey entry pressure >= 0 Pa */
+  const double *bc_lambda; /* host, per cell, Brooks-Corey lambda > 0           */
+  const uint8_t *dir_mask; /* host, per vertex: bit0 p_w, bit1 S_n Dirichlet    */
+  const double *dir_value; /* host, 2 per vertex (p_w, S_n); may be NULL if no mask bit set */
+  const tpf_patch *patches; /* host, n_patches entries                          */
+  int32_t n_patches;     /* 0..TPF_MAX_PATCHES                                  */
+  int32_t levels;        /* multigrid levels >= 1; each coarsening halves the cell count per axis */
+  int32_t precision;     /* TPF_FP64 or TPF_MIXED (FP32 multigrid levels)       */
+  int32_t nu_pre;        /* pre-smoothing sweeps (>= 1)                         */
+  int32_t nu_post;       /* post-smoothing sweeps (>= 0)                        */
+  int32_t limex_stages;  /* largest LIMEX stage count used with this grid (0: none) */
+  double omega;          /* block-Jacobi damping in (0, 2)                      */
+} tpf_grid_desc;
+
+typedef struct tpf_solve_stats {
+  int32_t iters;         /* BiCGSTAB iterations                                 */
+  int32_t restarts;      /* restarts (breakdown or stagnation of the true residual) */
+  double rel_res;        /* ||r_k|| / ||f|| of the recursively updated residual */
+  double rel_res_true;   /* ||f - A x|| / ||f|| recomputed in FP64 at exit      */
+  double fnorm;          /* ||f||_2                                             */
+} tpf_solve_stats;
+
+typedef struct tpf_limex_opts {
+  int32_t stages;        /* k >= 1 (k = 1 is linearly implicit Euler, no estimate) */
+  int32_t maxit;         /* BiCGSTAB iteration cap per stage solve               */
+  double tol;            /* TOL of the error estimate                            */
+  double safety;         /* rho of the step-size rule                            */
+  double dt_max;         /* largest step                                         */
+  double rtol;           /* relative residual of every stage solve               */
+} tpf_limex_opts;
+
+typedef struct tpf_limex_stats {
+  int32_t accepted;      /* 1 accepted, 0 rejected                               */
+  int32_t solves;        /* stage solves performed                              */
+  int32_t iters_total;   /* BiCGSTAB iterations summed over the solves          */
+  int32_t unconverged;   /* stage solves that hit maxit                          */
+  double eps;            /* error estimate [[eps]]                               */
+  double dt_used;        /* step attempted                                       */
+  double dt_next;        /* proposed next step                                   */
+} tpf_limex_stats;
+
+/* Message of the calling thread's last hard error ("" if none).  The pointer stays
+ * valid until the next library call on the same thread. */
+const char *tpf_last_error(void);
+
+/* Checks a descriptor on the host only (no HIP call).  TPF_OK or TPF_EINVAL. */
+tpf_status tpf_validate(const tpf_grid_desc *desc);
+
+/* Exact arena size in bytes for desc (0 if desc is invalid; see tpf_last_error).
+ * Pure host computation. */
+size_t tpf_grid_bytes(const tpf_grid_desc *desc);
+
+/* Creates a grid whose device state lives in arena (device memory, at least
+ * tpf_grid_bytes(desc) bytes, 256-byte aligned, owned by the caller and kept
+ * alive until tpf_destroy_grid).  Uploads the scenario and runs the per-vertex
+ * pre-processing (p_dmin and reference medium, Eq. pdmin; Neumann sources) on
+ * stream, then synchronises the stream so the host arrays may be freed.
+ * Errors: TPF_EINVAL (descriptor), TPF_ENOMEM (arena), TPF_EDEVICE. */
+tpf_status tpf_create_grid(const tpf_grid_desc *desc, void *arena, size_t arena_bytes,
+                           tpf_stream stream, tpf_grid **out);
+
+/* Frees the host metadata of g (the caller frees the arena afterwards). */
+void tpf_destroy_grid(tpf_grid *g);
+
+/* Writes the Dirichlet values of the descriptor into the masked components of the
+ * device state u (double[2N]). */
+tpf_status tpf_apply_dirichlet(tpf_grid *g, double *u, tpf_stream stream);
+
+/* f = F(u): the right-hand side of M(u) u' = F(u) (Section 4) -- Neumann sources
+ * minus the outward SCVF mass fluxes of both phases, Dirichlet components set to
+ * zero.  u, f: device double[2N]; may not alias. */
+tpf_status tpf_residual(tpf_grid *g, const double *u, double *f, tpf_stream stream);
+
+/* Stage matrix A = M(u0)/h - J(u0) with J = dF/du exact (upwind and interface
+ * branches frozen at u0) and unit rows at Dirichlet components (Section 4, the
+ * linearly implicit Euler step divided by tau = h); then the multigrid hierarchy:
+ * Galerkin coarse matrices, their FP32 copies in TPF_MIXED, and the inverse of the
+ * coarsest matrix from an LU factorisation with partial pivoting.  u0: device
+ * double[2N]; h > 0 seconds.  Also stores F(u0) for the first LIMEX substep. */
+tpf_status tpf_assemble_stage(tpf_grid *g, const double *u0, double h, tpf_stream stream);
+
+/* Solves A x = f (A from the last assemble_stage) with right-preconditioned
+ * BiCGSTAB, x0 = 0, one V(nu_pre, nu_post) cycle as preconditioner, until
+ * ||r|| <= rtol ||f||.  f, x: device double[2N], may not alias.  Synchronises the
+ * stream once per iteration to read the residual norm.  stats may be NULL.
+ * Returns TPF_OK, TPF_NOT_CONVERGED (x = last iterate), TPF_EBREAKDOWN,
+ * TPF_ESTATE (no assembled matrix). */
+tpf_status tpf_solve_stage(tpf_grid *g, const double *f, double *x, double rtol, int32_t maxit,
+                           tpf_solve_stats *stats, tpf_stream stream);
+
+/* One LIMEX step of size *dt from state u at time *t (Section 4): stages
+ * j = 1..k take j linearly implicit Euler substeps of *dt/j with M and J frozen
+ * at u and F re-evaluated each substep; Aitken-Neville extrapolation; error
+ * eps = |||T_kk - T_k,k-1||| / |||T_kk||| in the norm of Eq. norm_u; accept iff
+ * eps <= tol; next step min(dt_max, dt (safety tol / eps)^(1/3)).
+ * On accept u <- T_kk, *t += *dt; on reject u and *t are unchanged.  Either way
+ * *dt <- the proposed next step.  Requires opts->stages <= desc.limex_stages.
+ * Returns TPF_OK, TPF_STEP_REJECTED or an error. */
+tpf_status tpf_limex_step(tpf_grid *g, double *u, double *t, double *dt, const tpf_limex_opts *opts,
+                          tpf_limex_stats *stats, tpf_stream stream);
+
+/* ---- inspection hooks (used by the parity tests and the benchmark) ---------- */
+
+/* Number of multigrid levels and vertices per axis of a level. */
+int32_t tpf_levels(const tpf_grid *g);
+tpf_status tpf_level_dims(const tpf_grid *g, int32_t level, int32_t n_out[3]);
+
+/* Copies the level's stencil matrix into dst (device): layout
+ * [offset][vertex][4] with offset = (dx+1) + 3(dy+1) [+ 9(dz+1)], entries
+ * (row w, col p), (row w, col S), (row n, col p), (row n, col S).
+ * precision TPF_FP64 -> double, TPF_MIXED -> float (TPF_MIXED grids only). */
+tpf_status tpf_copy_matrix(tpf_grid *g, int32_t level, int32_t precision, void *dst, tpf_stream stream);
+
+/* y = A_level x with the FP64 level matrix; x, y device double[2 N_level]. */
+tpf_status tpf_spmv(tpf_grid *g, int32_t level, const double *x, double *y, tpf_stream stream);
+
+/* x = one V-cycle applied to b (the preconditioner of solve_stage). */
+tpf_status tpf_precondition(tpf_grid *g, const double *b, double *x, tpf_stream stream);
+
+/* Copies the inverse of the coarsest matrix (column-major, double[nc*nc],
+ * nc = 2 N_coarsest) to dst (device). */
+tpf_status tpf_copy_coarse_inverse(tpf_grid *g, double *dst, tpf_stream stream);
+
+/* Device buffer with p_dmin per vertex (read-only view into the arena). */
+const double *tpf_pdmin_ptr(const tpf_grid *g);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TPF_H */

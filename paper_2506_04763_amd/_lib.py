@@ -1,0 +1,120 @@
+"""ctypes declarations of the C ABI in include/tpf.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtpf.so")
+
+TPF_OK = 0
+TPF_NOT_CONVERGED = 1
+TPF_STEP_REJECTED = 2
+TPF_EINVAL = -1
+TPF_ENOMEM = -2
+TPF_EDEVICE = -3
+TPF_EBREAKDOWN = -4
+TPF_ESTATE = -5
+TPF_FP64 = 0
+TPF_MIXED = 1
+TPF_MAX_PATCHES = 8
+
+STATUS_NAMES = {0: "TPF_OK", 1: "TPF_NOT_CONVERGED", 2: "TPF_STEP_REJECTED", -1: "TPF_EINVAL",
+                -2: "TPF_ENOMEM", -3: "TPF_EDEVICE", -4: "TPF_EBREAKDOWN", -5: "TPF_ESTATE"}
+
+
+class Patch(C.Structure):
+    _fields_ = [("axis", C.c_int32), ("side", C.c_int32), ("phase", C.c_int32), ("reserved", C.c_int32),
+                ("lo", C.c_double * 2), ("hi", C.c_double * 2), ("rate", C.c_double)]
+
+
+class GridDesc(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n", C.c_int32 * 3), ("extent", C.c_double * 3),
+                ("gravity", C.c_double * 3), ("rho", C.c_double * 2), ("mu", C.c_double * 2),
+                ("s_res", C.c_double * 2), ("perm", C.POINTER(C.c_double)), ("poro", C.POINTER(C.c_double)),
+                ("entry_p", C.POINTER(C.c_double)), ("bc_lambda", C.POINTER(C.c_double)),
+                ("dir_mask", C.POINTER(C.c_uint8)), ("dir_value", C.POINTER(C.c_double)),
+                ("patches", C.POINTER(Patch)), ("n_patches", C.c_int32), ("levels", C.c_int32),
+                ("precision", C.c_int32), ("nu_pre", C.c_int32), ("nu_post", C.c_int32),
+                ("limex_stages", C.c_int32), ("omega", C.c_double)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("rel_res", C.c_double),
+                ("rel_res_true", C.c_double), ("fnorm", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class LimexOpts(C.Structure):
+    _fields_ = [("stages", C.c_int32), ("maxit", C.c_int32), ("tol", C.c_double), ("safety", C.c_double),
+                ("dt_max", C.c_double), ("rtol", C.c_double)]
+
+
+class LimexStats(C.Structure):
+    _fields_ = [("accepted", C.c_int32), ("solves", C.c_int32), ("iters_total", C.c_int32),
+                ("unconverged", C.c_int32), ("eps", C.c_double), ("dt_used", C.c_double),
+                ("dt_next", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+VP = C.c_void_p
+DP = C.c_void_p  # device pointers are passed as integers
+
+_SIGS = {
+    "tpf_last_error": (C.c_char_p, []),
+    "tpf_validate": (C.c_int32, [C.POINTER(GridDesc)]),
+    "tpf_grid_bytes": (C.c_size_t, [C.POINTER(GridDesc)]),
+    "tpf_create_grid": (C.c_int32, [C.POINTER(GridDesc), VP, C.c_size_t, VP, C.POINTER(VP)]),
+    "tpf_destroy_grid": (None, [VP]),
+    "tpf_apply_dirichlet": (C.c_int32, [VP, DP, VP]),
+    "tpf_residual": (C.c_int32, [VP, DP, DP, VP]),
+    "tpf_assemble_stage": (C.c_int32, [VP, DP, C.c_double, VP]),
+    "tpf_solve_stage": (C.c_int32, [VP, DP, DP, C.c_double, C.c_int32, C.POINTER(SolveStats), VP]),
+    "tpf_limex_step": (C.c_int32, [VP, DP, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(LimexOpts),
+                                   C.POINTER(LimexStats), VP]),
+    "tpf_levels": (C.c_int32, [VP]),
+    "tpf_level_dims": (C.c_int32, [VP, C.c_int32, C.POINTER(C.c_int32)]),
+    "tpf_copy_matrix": (C.c_int32, [VP, C.c_int32, C.c_int32, DP, VP]),
+    "tpf_spmv": (C.c_int32, [VP, C.c_int32, DP, DP, VP]),
+    "tpf_precondition": (C.c_int32, [VP, DP, DP, VP]),
+    "tpf_copy_coarse_inverse": (C.c_int32, [VP, DP, VP]),
+    "tpf_pdmin_ptr": (VP, [VP]),
+}
+
+_lib = None
+
+
+def load():
+    """Loads libtpf.so (raises if it has not been built: there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = C.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def last_error() -> str:
+    return load().tpf_last_error().decode()
+
+
+class TPFError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {last_error()}")
+
+
+def check(status, where, soft_ok=False):
+    if status < 0 or (status > 0 and not soft_ok):
+        raise TPFError(status, where)
+    return status

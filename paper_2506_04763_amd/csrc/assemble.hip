@@ -1,0 +1,379 @@
+// Box-method residual and stage-matrix assembly on structured Q1 grids (gfx950).
+//
+// One thread per vertex gathers the contributions of the 2^d cells around it (no
+// atomics, deterministic).  For every cell it evaluates, at the cell's corners, the
+// sub-control-volume saturation of the p_dmin interface condition (Eq. hSw) and the
+// element-local capillary pressure, then the fluxes through the d sub-control-volume
+// faces incident to its vertex (Section 3.1, Eqs. dsW/dpN; upwinding Section 3.2;
+// barrier on the non-wetting mobility only, Eqs. krn_ip/krw_ip) with their exact
+// derivatives.  The row is kept in registers and written once as 2x2 blocks in the
+// [offset][vertex][4] layout (coalesced 32-byte stores per lane).
+//
+// Discretisation choices (shared with the independent FP64 oracle, from the paper's
+// text): unknowns (p_w, S_n); the convective non-wetting flux is upwinded with the
+// velocity -K/mu_n (grad p_w - rho_n g) and the capillary flux -k_rn K/mu_n grad p_c
+// is central, k_rn taken at the Q1-interpolated hat saturation of the integration
+// point; Brooks-Corey p_c = p_d S_e^(-1/lam) and Burdine k_rw = S_e^((2+3 lam)/lam),
+// k_rn = (1-S_e)^2 (1 - S_e^((2+lam)/lam)), S_e clamped to [1e-6, 1]; storage of each
+// sub-control volume uses its hat saturation; SCVF oriented from lower to higher
+// vertex index with ties upwinded to the lower one; integration point at the face
+// barycentre.
+#include "tpf_internal.h"
+
+namespace tpf {
+namespace {
+
+__device__ __forceinline__ void eff_sat(double sn, const Phys &P, double &se, double &dse) {
+  const double raw = ((1.0 - sn) - P.swr) / P.D;
+  if (raw < SE_MIN) {
+    se = SE_MIN; dse = 0.0;
+  } else if (raw > 1.0) {
+    se = 1.0; dse = 0.0;
+  } else {
+    se = raw; dse = -1.0 / P.D;
+  }
+}
+
+// Burdine wetting relative permeability and its derivative w.r.t. S_n.
+__device__ __forceinline__ void krw(double sn, double lam, const Phys &P, double &k, double &dk) {
+  double se, dse;
+  eff_sat(sn, P, se, dse);
+  const double e = (2.0 + 3.0 * lam) / lam;
+  k = pow(se, e);
+  dk = e * (k / se) * dse;
+}
+
+// Burdine non-wetting relative permeability and its derivative w.r.t. S_n.
+__device__ __forceinline__ void krn(double sn, double lam, const Phys &P, double &k, double &dk) {
+  double se, dse;
+  eff_sat(sn, P, se, dse);
+  const double a = (2.0 + lam) / lam;
+  const double sa = pow(se, a);
+  const double om = 1.0 - se;
+  k = om * om * (1.0 - sa);
+  dk = (-2.0 * om * (1.0 - sa) - om * om * a * (sa / se)) * dse;
+}
+
+// ---------------------------------------------------------------------------------
+// Per-vertex pre-processing: p_dmin,i = min of the adjacent cells' entry pressures,
+// lambda of the reference medium (lowest cell index attaining the minimum) and the
+// Neumann sources integrated exactly over the dual-box face.
+// ---------------------------------------------------------------------------------
+template <int DIM>
+__global__ void __launch_bounds__(BS) k_setup(const Phys P, const double *__restrict__ pd,
+                                              const double *__restrict__ lam, const Patches pt,
+                                              double *__restrict__ pdmin, double *__restrict__ lamref,
+                                              double *__restrict__ Q) {
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= P.N) return;
+  const int ix = (int)(v % P.nx);
+  const long long t = v / P.nx;
+  const int iy = (int)(t % P.ny);
+  const int iz = (int)(t / P.ny);
+  double best = 1.0e308;
+  long long bestc = -1;
+  // visit adjacent cells in increasing cell index so ties keep the lowest index
+  for (int cz = (DIM == 3 ? -1 : 0); cz <= 0; ++cz)
+    for (int cy = -1; cy <= 0; ++cy)
+      for (int cx = -1; cx <= 0; ++cx) {
+        const int ox = ix + cx, oy = iy + cy, oz = iz + cz;
+        if (ox < 0 || oy < 0 || oz < 0 || ox >= P.ncx || oy >= P.ncy || oz >= P.ncz) continue;
+        const long long c = ox + (long long)P.ncx * (oy + (long long)P.ncy * oz);
+        const double p = pd[c];
+        if (p < best) { best = p; bestc = c; }
+      }
+  pdmin[v] = best;
+  lamref[v] = lam[bestc];
+  const double x[3] = {ix * P.h[0], iy * P.h[1], (DIM == 3 ? iz * P.h[2] : 0.0)};
+  const double ext[3] = {(P.nx - 1) * P.h[0], (P.ny - 1) * P.h[1], (P.nz - 1) * P.h[2]};
+  double q[2] = {0.0, 0.0};
+  for (int k = 0; k < pt.n; ++k) {
+    const PatchDev &pa = pt.p[k];
+    const int a = pa.axis;
+    const double face = pa.side == 0 ? 0.0 : ext[a];
+    if (fabs(x[a] - face) > 1e-9 * (ext[a] + 1.0)) continue;
+    double meas = 1.0;
+    int kk = 0;
+    for (int b = 0; b < DIM; ++b) {
+      if (b == a) continue;
+      const double lo = fmax(fmax(x[b] - 0.5 * P.h[b], 0.0), pa.lo[kk]);
+      const double hi = fmin(fmin(x[b] + 0.5 * P.h[b], ext[b]), pa.hi[kk]);
+      meas *= fmax(hi - lo, 0.0);
+      ++kk;
+    }
+    q[pa.phase] += pa.rate * meas;
+  }
+  Q[2 * v] = q[0];
+  Q[2 * v + 1] = q[1];
+}
+
+// Vertex capillary pressure in the reference medium, P_i = p_dmin,i J(S_i), and its
+// derivative w.r.t. S_n,i (an input to every hat evaluation around the vertex).
+__global__ void __launch_bounds__(BS) k_vertex_pc(const Phys P, const double *__restrict__ u,
+                                                  const double *__restrict__ pdmin,
+                                                  const double *__restrict__ lamref,
+                                                  double *__restrict__ pv) {
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= P.N) return;
+  double se, dse;
+  eff_sat(u[2 * v + 1], P, se, dse);
+  const double lr = lamref[v];
+  const double pc = pdmin[v] * pow(se, -1.0 / lr);
+  pv[2 * v] = pc;
+  pv[2 * v + 1] = pc * (-1.0 / lr) / se * dse;
+}
+
+template <int DIM>
+__device__ __forceinline__ constexpr int stencil_index(int dx, int dy, int dz) {
+  return DIM == 3 ? (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1) : (dx + 1) + 3 * (dy + 1);
+}
+
+__device__ __forceinline__ constexpr int bit(int l, int a) { return (l >> a) & 1; }
+
+// ---------------------------------------------------------------------------------
+// Residual F(u) and (WANT_A) the stage matrix A = M(u)/h - dF/du.
+// ---------------------------------------------------------------------------------
+template <int DIM, bool WANT_A, bool W32>
+__global__ void __launch_bounds__(BS)
+k_assemble(const Phys P, const double *__restrict__ u, const double *__restrict__ Kc,
+           const double *__restrict__ phic, const double *__restrict__ pdc,
+           const double *__restrict__ lamc, const double *__restrict__ pdmin,
+           const double *__restrict__ pv, const uint8_t *__restrict__ dmask,
+           const double *__restrict__ Q, const double inv_h, double *__restrict__ A64,
+           float *__restrict__ A32, double *__restrict__ F) {
+  constexpr int NC = 1 << DIM;
+  constexpr int NST = DIM == 3 ? 27 : 9;
+  constexpr int CEN = DIM == 3 ? 13 : 4;
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= P.N) return;
+  const int ix = (int)(v % P.nx);
+  const long long tq = v / P.nx;
+  const int iy = (int)(tq % P.ny);
+  const int iz = (int)(tq / P.ny);
+  const long long sy = P.nx, sz = (long long)P.nx * P.ny;
+
+  double acc[WANT_A ? NST : 1][4];
+  if (WANT_A) {
+#pragma unroll
+    for (int o = 0; o < NST; ++o)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[o][e] = 0.0;
+  }
+  double Fw = 0.0, Fn = 0.0, mwS = 0.0, mnS = 0.0;
+  const double rw = P.rho_w, rn = P.rho_n;
+
+#pragma unroll
+  for (int cc = 0; cc < NC; ++cc) {
+    // cell whose corner `cc` is this vertex: origin = vertex - bits(cc)
+    const int ox = ix - bit(cc, 0), oy = iy - bit(cc, 1), oz = (DIM == 3) ? iz - bit(cc, 2) : 0;
+    if (ox < 0 || oy < 0 || oz < 0 || ox >= P.ncx || oy >= P.ncy || oz >= P.ncz) continue;
+    const long long c = ox + (long long)P.ncx * (oy + (long long)P.ncy * oz);
+    const double Ke = Kc[c], phie = phic[c], pde = pdc[c], lame = lamc[c];
+    double p[NC], sn[NC], sh[NC], dsh[NC], pc[NC], dpc[NC];
+#pragma unroll
+    for (int l = 0; l < NC; ++l) {
+      const int dx = bit(l, 0) - bit(cc, 0), dy = bit(l, 1) - bit(cc, 1);
+      const int dz = (DIM == 3) ? bit(l, 2) - bit(cc, 2) : 0;
+      const long long vl = v + dx + sy * dy + sz * dz;
+      const double2 ul = *reinterpret_cast<const double2 *>(u + 2 * vl);
+      p[l] = ul.x;
+      sn[l] = ul.y;
+      const double pdm = pdmin[vl];
+      const double2 pvl = *reinterpret_cast<const double2 *>(pv + 2 * vl);
+      // interface condition (Eq. hSw): equal entry pressure / barrier / continuity
+      if (pde == pdm) {
+        sh[l] = sn[l]; dsh[l] = 1.0;
+      } else if (pde >= pvl.x) {
+        sh[l] = P.snr; dsh[l] = 0.0;
+      } else {
+        const double ses = pow(pvl.x / pde, -lame);
+        sh[l] = 1.0 - (P.swr + ses * P.D);
+        dsh[l] = -P.D * (-lame * ses / pvl.x * pvl.y);
+      }
+      double se, dse;
+      eff_sat(sh[l], P, se, dse);
+      pc[l] = pde * pow(se, -1.0 / lame);
+      dpc[l] = pc[l] * (-1.0 / lame) / se * dse * dsh[l];
+    }
+    // storage of the sub-control volume (vertex, cell): only dM/dS_n is non-zero
+    mwS -= phie * rw * P.scv * dsh[cc];
+    mnS += phie * rn * P.scv * dsh[cc];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+      const int cj = cc ^ (1 << a);
+      const int l0 = bit(cc, a) ? cj : cc;
+      const int l1 = bit(cc, a) ? cc : cj;
+      const double sgn = bit(cc, a) ? 1.0 : -1.0;  // F_l0 -= flux, F_l1 += flux
+      // shape functions and x_a-derivatives at the SCVF barycentre
+      double Nl[NC], Gl[NC];
+#pragma unroll
+      for (int l = 0; l < NC; ++l) {
+        double n = 1.0, gg = (bit(l, a) ? 1.0 : -1.0) / P.h[a];
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) {
+          const double xi = (b == a) ? 0.5 : (bit(cc, b) ? 0.75 : 0.25);
+          const double f = bit(l, b) ? xi : 1.0 - xi;
+          n *= f;
+          if (b != a) gg *= f;
+        }
+        Nl[l] = n;
+        Gl[l] = gg;
+      }
+      double dp = 0.0, sip = 0.0, gpc = 0.0;
+#pragma unroll
+      for (int l = 0; l < NC; ++l) {
+        dp += p[l] * Gl[l];
+        sip += Nl[l] * sh[l];
+        gpc += pc[l] * Gl[l];
+      }
+      const double area = P.area[a];
+      const double ga = P.g[a];
+      // wetting phase, upwinded plain saturation
+      const double cw = -(Ke / P.mu_w) * area;
+      const double phw = cw * (dp - rw * ga);
+      const bool upw0 = phw >= 0.0;
+      double kw, dkw;
+      krw(upw0 ? sn[l0] : sn[l1], lame, P, kw, dkw);
+      const double fw = rw * kw * phw;
+      // non-wetting phase, upwinded hat saturation
+      const double cn = -(Ke / P.mu_n) * area;
+      const double phn = cn * (dp - rn * ga);
+      const bool upn0 = phn >= 0.0;
+      double kn, dkn;
+      krn(upn0 ? sh[l0] : sh[l1], lame, P, kn, dkn);
+      const double fn = rn * kn * phn;
+      // capillary diffusion, central
+      double kip, dkip;
+      krn(sip, lame, P, kip, dkip);
+      const double cc_ = -rn * (Ke / P.mu_n) * area;
+      const double fc = cc_ * kip * gpc;
+      Fw += sgn * fw;
+      Fn += sgn * (fn + fc);
+      if (WANT_A) {
+        // A_{i,l} -= sgn * d(flux)/du_l
+#pragma unroll
+        for (int l = 0; l < NC; ++l) {
+          const int dx = bit(l, 0) - bit(cc, 0), dy = bit(l, 1) - bit(cc, 1);
+          const int dz = (DIM == 3) ? bit(l, 2) - bit(cc, 2) : 0;
+          const int o = stencil_index<DIM>(dx, dy, dz);
+          acc[o][0] -= sgn * (rw * kw * cw * Gl[l]);
+          acc[o][2] -= sgn * (rn * kn * cn * Gl[l]);
+          acc[o][3] -= sgn * (cc_ * (dkip * Nl[l] * dsh[l] * gpc + kip * Gl[l] * dpc[l]));
+        }
+        const double dfw = rw * phw * dkw;
+        const double dfn = rn * phn * dkn;
+        {
+          const int dx0 = bit(l0, 0) - bit(cc, 0), dy0 = bit(l0, 1) - bit(cc, 1);
+          const int dz0 = (DIM == 3) ? bit(l0, 2) - bit(cc, 2) : 0;
+          const int dx1 = bit(l1, 0) - bit(cc, 0), dy1 = bit(l1, 1) - bit(cc, 1);
+          const int dz1 = (DIM == 3) ? bit(l1, 2) - bit(cc, 2) : 0;
+          const int o0 = stencil_index<DIM>(dx0, dy0, dz0);
+          const int o1 = stencil_index<DIM>(dx1, dy1, dz1);
+          if (upw0) acc[o0][1] -= sgn * dfw; else acc[o1][1] -= sgn * dfw;
+          if (upn0) acc[o0][3] -= sgn * dfn * dsh[l0]; else acc[o1][3] -= sgn * dfn * dsh[l1];
+        }
+      }
+    }
+  }
+  const double2 q = *reinterpret_cast<const double2 *>(Q + 2 * v);
+  Fw += q.x;
+  Fn += q.y;
+  const uint8_t m = dmask[v];
+  if (m & 1) Fw = 0.0;
+  if (m & 2) Fn = 0.0;
+  if (F != nullptr) *reinterpret_cast<double2 *>(F + 2 * v) = make_double2(Fw, Fn);
+  if (WANT_A) {
+    acc[CEN][1] += mwS * inv_h;
+    acc[CEN][3] += mnS * inv_h;
+    if (m & 1) {
+#pragma unroll
+      for (int o = 0; o < NST; ++o) { acc[o][0] = 0.0; acc[o][1] = 0.0; }
+      acc[CEN][0] = 1.0;
+    }
+    if (m & 2) {
+#pragma unroll
+      for (int o = 0; o < NST; ++o) { acc[o][2] = 0.0; acc[o][3] = 0.0; }
+      acc[CEN][3] = 1.0;
+    }
+#pragma unroll
+    for (int o = 0; o < NST; ++o) {
+      double *dst = A64 + ((long long)o * P.N + v) * 4;
+      reinterpret_cast<double2 *>(dst)[0] = make_double2(acc[o][0], acc[o][1]);
+      reinterpret_cast<double2 *>(dst)[1] = make_double2(acc[o][2], acc[o][3]);
+      if (W32) {
+        float4 f4 = make_float4((float)acc[o][0], (float)acc[o][1], (float)acc[o][2], (float)acc[o][3]);
+        *reinterpret_cast<float4 *>(A32 + ((long long)o * P.N + v) * 4) = f4;
+      }
+    }
+  }
+}
+
+__global__ void k_apply_dirichlet(long long N, const uint8_t *__restrict__ m,
+                                  const double *__restrict__ val, double *__restrict__ u) {
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= N) return;
+  const uint8_t b = m[v];
+  if (b & 1) u[2 * v] = val[2 * v];
+  if (b & 2) u[2 * v + 1] = val[2 * v + 1];
+}
+
+}  // namespace
+
+tpf_status setup_vertices(tpf_grid *g, const Patches &pt, hipStream_t s) {
+  const unsigned nb = blocks_for(g->P.N);
+  if (g->dim == 3)
+    k_setup<3><<<nb, BS, 0, s>>>(g->P, g->pd, g->lam, pt, g->pdmin, g->lamref, g->Q);
+  else
+    k_setup<2><<<nb, BS, 0, s>>>(g->P, g->pd, g->lam, pt, g->pdmin, g->lamref, g->Q);
+  TPF_LAUNCH_CHECK();
+  return TPF_OK;
+}
+
+tpf_status launch_residual(tpf_grid *g, const double *u, double *f, hipStream_t s) {
+  const unsigned nb = blocks_for(g->P.N);
+  k_vertex_pc<<<nb, BS, 0, s>>>(g->P, u, g->pdmin, g->lamref, g->pv);
+  TPF_LAUNCH_CHECK();
+  if (g->dim == 3)
+    k_assemble<3, false, false><<<nb, BS, 0, s>>>(g->P, u, g->K, g->phi, g->pd, g->lam, g->pdmin, g->pv,
+                                                   g->dmask, g->Q, 0.0, nullptr, nullptr, f);
+  else
+    k_assemble<2, false, false><<<nb, BS, 0, s>>>(g->P, u, g->K, g->phi, g->pd, g->lam, g->pdmin, g->pv,
+                                                   g->dmask, g->Q, 0.0, nullptr, nullptr, f);
+  TPF_LAUNCH_CHECK();
+  return TPF_OK;
+}
+
+tpf_status launch_assemble(tpf_grid *g, const double *u0, double h, double *f0, hipStream_t s) {
+  const unsigned nb = blocks_for(g->P.N);
+  k_vertex_pc<<<nb, BS, 0, s>>>(g->P, u0, g->pdmin, g->lamref, g->pv);
+  TPF_LAUNCH_CHECK();
+  double *A64 = g->lv[0].A64;
+  float *A32 = g->lv[0].A32;
+  const double ih = 1.0 / h;
+  const bool w32 = g->prec == TPF_MIXED;
+  if (g->dim == 3) {
+    if (w32)
+      k_assemble<3, true, true><<<nb, BS, 0, s>>>(g->P, u0, g->K, g->phi, g->pd, g->lam, g->pdmin, g->pv,
+                                                   g->dmask, g->Q, ih, A64, A32, f0);
+    else
+      k_assemble<3, true, false><<<nb, BS, 0, s>>>(g->P, u0, g->K, g->phi, g->pd, g->lam, g->pdmin, g->pv,
+                                                    g->dmask, g->Q, ih, A64, nullptr, f0);
+  } else {
+    if (w32)
+      k_assemble<2, true, true><<<nb, BS, 0, s>>>(g->P, u0, g->K, g->phi, g->pd, g->lam, g->pdmin, g->pv,
+                                                   g->dmask, g->Q, ih, A64, A32, f0);
+    else
+      k_assemble<2, true, false><<<nb, BS, 0, s>>>(g->P, u0, g->K, g->phi, g->pd, g->lam, g->pdmin, g->pv,
+                                                    g->dmask, g->Q, ih, A64, nullptr, f0);
+  }
+  TPF_LAUNCH_CHECK();
+  return TPF_OK;
+}
+
+tpf_status launch_apply_dirichlet(tpf_grid *g, double *u, hipStream_t s) {
+  k_apply_dirichlet<<<blocks_for(g->P.N), BS, 0, s>>>(g->P.N, g->dmask, g->dval, u);
+  TPF_LAUNCH_CHECK();
+  return TPF_OK;
+}
+
+}  // namespace tpf

@@ -1,0 +1,637 @@
+// Geometric multigrid on structured vertex grids (gfx950): stencil SpMV, damped 2x2
+// block-Jacobi smoothing, residual, restriction (P^T), prolongation, Galerkin coarse
+// operators A_c = P^T A P, dense coarsest-level LU with partial pivoting and its
+// inverse, and the V(nu1, nu2) cycle used as BiCGSTAB preconditioner.
+//
+// Matrices are 27-point (3D) / 9-point (2D) stencils of 2x2 blocks stored
+// [offset][vertex][4]: for a fixed offset, consecutive lanes read consecutive 16-byte
+// (FP32) or 32-byte (FP64) blocks, so every matrix load of a wave is one contiguous
+// 1-2 KB segment.  Entries for neighbours outside the grid are stored as zeros and
+// never dereference x.  P is per-component (bi/tri)linear interpolation between
+// vertex-halved grids; on the finest level its rows at Dirichlet components are zero.
+#include "tpf_internal.h"
+
+namespace tpf {
+namespace {
+
+template <typename T> struct Vec2;
+template <> struct Vec2<double> { using type = double2; };
+template <> struct Vec2<float> { using type = float2; };
+
+template <typename T> struct Blk;
+template <> struct Blk<double> {
+  __device__ static __forceinline__ void load(const double *p, double (&b)[4]) {
+    const double2 a = reinterpret_cast<const double2 *>(p)[0];
+    const double2 c = reinterpret_cast<const double2 *>(p)[1];
+    b[0] = a.x; b[1] = a.y; b[2] = c.x; b[3] = c.y;
+  }
+};
+template <> struct Blk<float> {
+  __device__ static __forceinline__ void load(const float *p, float (&b)[4]) {
+    const float4 a = *reinterpret_cast<const float4 *>(p);
+    b[0] = a.x; b[1] = a.y; b[2] = a.z; b[3] = a.w;
+  }
+};
+
+struct Geo {
+  int nx, ny, nz;
+  long long N;
+};
+
+__device__ __forceinline__ void vcoords(long long v, const Geo &G, int &ix, int &iy, int &iz) {
+  ix = (int)(v % G.nx);
+  const long long t = v / G.nx;
+  iy = (int)(t % G.ny);
+  iz = (int)(t / G.ny);
+}
+
+// y = A x (row-block product) accumulated in the matrix type T for one vertex.
+// Returns (A x)_v; the centre block is copied out for the smoother.
+template <int DIM, typename T, typename TX>
+__device__ __forceinline__ void row_apply(const Geo &G, long long v, const T *__restrict__ A,
+                                          const TX *__restrict__ x, T &y0, T &y1, T (&dblk)[4]) {
+  constexpr int NST = DIM == 3 ? 27 : 9;
+  constexpr int CEN = DIM == 3 ? 13 : 4;
+  int ix, iy, iz;
+  vcoords(v, G, ix, iy, iz);
+  const bool xm = ix > 0, xp = ix < G.nx - 1, ym = iy > 0, yp = iy < G.ny - 1;
+  const bool zm = DIM == 3 && iz > 0, zp = DIM == 3 && iz < G.nz - 1;
+  const long long sy = G.nx, sz = (long long)G.nx * G.ny;
+  T a0 = 0, a1 = 0;
+#pragma unroll
+  for (int o = 0; o < NST; ++o) {
+    const int dx = o % 3 - 1, dy = (o / 3) % 3 - 1, dz = DIM == 3 ? o / 9 - 1 : 0;
+    T b[4];
+    Blk<T>::load(A + ((long long)o * G.N + v) * 4, b);
+    if (o == CEN) {
+      dblk[0] = b[0]; dblk[1] = b[1]; dblk[2] = b[2]; dblk[3] = b[3];
+    }
+    const bool ok = (dx < 0 ? xm : (dx > 0 ? xp : true)) && (dy < 0 ? ym : (dy > 0 ? yp : true)) &&
+                    (dz < 0 ? zm : (dz > 0 ? zp : true));
+    if (ok) {
+      const long long vn = v + dx + sy * dy + sz * dz;
+      const auto xv = *reinterpret_cast<const typename Vec2<TX>::type *>(x + 2 * vn);
+      const T x0 = (T)xv.x, x1 = (T)xv.y;
+      a0 += b[0] * x0 + b[1] * x1;
+      a1 += b[2] * x0 + b[3] * x1;
+    }
+  }
+  y0 = a0;
+  y1 = a1;
+}
+
+template <typename T>
+__device__ __forceinline__ void solve2(const T (&d)[4], T r0, T r1, T &z0, T &z1) {
+  const T det = d[0] * d[3] - d[1] * d[2];
+  z0 = (d[3] * r0 - d[1] * r1) / det;
+  z1 = (d[0] * r1 - d[2] * r0) / det;
+}
+
+// ---- block-level reduction helpers (deterministic: fixed tree) ------------------
+template <int NDOT>
+__device__ __forceinline__ void block_reduce_store(double (&val)[NDOT], double *__restrict__ part,
+                                                   unsigned blk, unsigned nblk) {
+  __shared__ double sm[NDOT][BS / 64];
+#pragma unroll
+  for (int k = 0; k < NDOT; ++k) {
+    double s = val[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if ((threadIdx.x & 63) == 0) sm[k][threadIdx.x >> 6] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < NDOT) {
+    double s = 0.0;
+#pragma unroll
+    for (int wv = 0; wv < BS / 64; ++wv) s += sm[threadIdx.x][wv];
+    part[(long long)threadIdx.x * nblk + blk] = s;
+  }
+}
+
+// y = A x (FP64); optionally partial dots (d0, y) [MODE 1], (d0,y),(y,y) [MODE 2],
+// or the residual y = b - A x with partial (y, y) [MODE 3].
+template <int DIM, int MODE>
+__global__ void __launch_bounds__(BS) k_spmv64(const Geo G, const double *__restrict__ A,
+                                               const double *__restrict__ x, double *__restrict__ y,
+                                               const double *__restrict__ d0, double *__restrict__ part) {
+  const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
+  const long long v = (long long)blk * BS + threadIdx.x;
+  double acc[MODE == 2 ? 2 : 1];
+  acc[0] = 0.0;
+  if (MODE == 2) acc[MODE == 2 ? 1 : 0] = 0.0;
+  if (v < G.N) {
+    double y0, y1, dd[4];
+    row_apply<DIM, double, double>(G, v, A, x, y0, y1, dd);
+    if (MODE == 3) {
+      const double2 bb = *reinterpret_cast<const double2 *>(d0 + 2 * v);
+      y0 = bb.x - y0;
+      y1 = bb.y - y1;
+    }
+    *reinterpret_cast<double2 *>(y + 2 * v) = make_double2(y0, y1);
+    if (MODE == 1 || MODE == 2) {
+      const double2 w = *reinterpret_cast<const double2 *>(d0 + 2 * v);
+      acc[0] = w.x * y0 + w.y * y1;
+      if (MODE == 2) acc[MODE == 2 ? 1 : 0] = y0 * y0 + y1 * y1;
+    }
+    if (MODE == 3) acc[0] = y0 * y0 + y1 * y1;
+  }
+  if (MODE != 0) block_reduce_store<MODE == 2 ? 2 : 1>(acc, part, blk, gridDim.x);
+}
+
+// Damped block Jacobi sweep: xo = xi + omega D^{-1} (b - A xi); FIRST: xi = 0.
+template <int DIM, typename T, typename TO, bool FIRST>
+__global__ void __launch_bounds__(BS) k_jacobi(const Geo G, const T *__restrict__ A,
+                                               const T *__restrict__ b, const T *__restrict__ xi,
+                                               TO *__restrict__ xo, const T omega) {
+  constexpr int CEN = DIM == 3 ? 13 : 4;
+  const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
+  const long long v = (long long)blk * BS + threadIdx.x;
+  if (v >= G.N) return;
+  const auto bb = *reinterpret_cast<const typename Vec2<T>::type *>(b + 2 * v);
+  T r0, r1, d[4], x0 = 0, x1 = 0;
+  if (FIRST) {
+    Blk<T>::load(A + ((long long)CEN * G.N + v) * 4, d);
+    r0 = bb.x;
+    r1 = bb.y;
+  } else {
+    T a0, a1;
+    row_apply<DIM, T, T>(G, v, A, xi, a0, a1, d);
+    const auto xx = *reinterpret_cast<const typename Vec2<T>::type *>(xi + 2 * v);
+    x0 = xx.x;
+    x1 = xx.y;
+    r0 = bb.x - a0;
+    r1 = bb.y - a1;
+  }
+  T z0, z1;
+  solve2<T>(d, r0, r1, z0, z1);
+  typename Vec2<TO>::type out;
+  out.x = (TO)(x0 + omega * z0);
+  out.y = (TO)(x1 + omega * z1);
+  *reinterpret_cast<typename Vec2<TO>::type *>(xo + 2 * v) = out;
+}
+
+// r = b - A x on a level.
+template <int DIM, typename T>
+__global__ void __launch_bounds__(BS) k_resid(const Geo G, const T *__restrict__ A, const T *__restrict__ b,
+                                              const T *__restrict__ x, T *__restrict__ r) {
+  const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
+  const long long v = (long long)blk * BS + threadIdx.x;
+  if (v >= G.N) return;
+  T a0, a1, d[4];
+  row_apply<DIM, T, T>(G, v, A, x, a0, a1, d);
+  const auto bb = *reinterpret_cast<const typename Vec2<T>::type *>(b + 2 * v);
+  typename Vec2<T>::type o;
+  o.x = bb.x - a0;
+  o.y = bb.y - a1;
+  *reinterpret_cast<typename Vec2<T>::type *>(r + 2 * v) = o;
+}
+
+// Restriction bc = P^T rf: gather of the 3^d fine neighbours of vertex 2I with
+// weights (1/2)^{|d|_1}; fine Dirichlet components (finest level) excluded.
+template <int DIM, typename T>
+__global__ void __launch_bounds__(BS) k_restrict(const Geo F, const Geo C, const T *__restrict__ rf,
+                                                 const uint8_t *__restrict__ fmask, T *__restrict__ bc) {
+  const long long I = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= C.N) return;
+  int cx, cy, cz;
+  vcoords(I, C, cx, cy, cz);
+  const int fx = 2 * cx, fy = 2 * cy, fz = DIM == 3 ? 2 * cz : 0;
+  T s0 = 0, s1 = 0;
+#pragma unroll
+  for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0); ++dz)
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int x = fx + dx, y = fy + dy, z = fz + dz;
+        if (x < 0 || y < 0 || z < 0 || x >= F.nx || y >= F.ny || z >= F.nz) continue;
+        const T w = (T)((dx ? 0.5 : 1.0) * (dy ? 0.5 : 1.0) * (dz ? 0.5 : 1.0));
+        const long long i = x + (long long)F.nx * (y + (long long)F.ny * z);
+        const auto rv = *reinterpret_cast<const typename Vec2<T>::type *>(rf + 2 * i);
+        T r0 = rv.x, r1 = rv.y;
+        if (fmask) {
+          const uint8_t m = fmask[i];
+          if (m & 1) r0 = 0;
+          if (m & 2) r1 = 0;
+        }
+        s0 += w * r0;
+        s1 += w * r1;
+      }
+  typename Vec2<T>::type o;
+  o.x = s0;
+  o.y = s1;
+  *reinterpret_cast<typename Vec2<T>::type *>(bc + 2 * I) = o;
+}
+
+// Prolongation and correction xf += P ec.
+template <int DIM, typename T>
+__global__ void __launch_bounds__(BS) k_prolong(const Geo F, const Geo C, const T *__restrict__ ec,
+                                                const uint8_t *__restrict__ fmask, T *__restrict__ xf) {
+  const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
+  const long long i = (long long)blk * BS + threadIdx.x;
+  if (i >= F.N) return;
+  int x, y, z;
+  vcoords(i, F, x, y, z);
+  const int xl = x >> 1, xh = (x + 1) >> 1, yl = y >> 1, yh = (y + 1) >> 1;
+  const int zl = DIM == 3 ? z >> 1 : 0, zh = DIM == 3 ? (z + 1) >> 1 : 0;
+  T s0 = 0, s1 = 0;
+#pragma unroll
+  for (int kz = 0; kz < (DIM == 3 ? 2 : 1); ++kz)
+#pragma unroll
+    for (int ky = 0; ky < 2; ++ky)
+#pragma unroll
+      for (int kx = 0; kx < 2; ++kx) {
+        const int X = kx ? xh : xl, Y = ky ? yh : yl, Z = kz ? zh : zl;
+        // each axis contributes weight 1 (even index: both picks coincide, count once) or 1/2
+        const T wx = (x & 1) ? (T)0.5 : (kx ? (T)0 : (T)1);
+        const T wy = (y & 1) ? (T)0.5 : (ky ? (T)0 : (T)1);
+        const T wz = DIM == 3 ? ((z & 1) ? (T)0.5 : (kz ? (T)0 : (T)1)) : (T)1;
+        const T w = wx * wy * wz;
+        if (w == (T)0) continue;
+        const long long J = X + (long long)C.nx * (Y + (long long)C.ny * Z);
+        const auto ev = *reinterpret_cast<const typename Vec2<T>::type *>(ec + 2 * J);
+        s0 += w * ev.x;
+        s1 += w * ev.y;
+      }
+  if (fmask) {
+    const uint8_t m = fmask[i];
+    if (m & 1) s0 = 0;
+    if (m & 2) s1 = 0;
+  }
+  auto xv = *reinterpret_cast<typename Vec2<T>::type *>(xf + 2 * i);
+  xv.x += s0;
+  xv.y += s1;
+  *reinterpret_cast<typename Vec2<T>::type *>(xf + 2 * i) = xv;
+}
+
+// Galerkin coarse operator A_c = P^T A_f P, one thread per coarse vertex I.
+// Fine row i = 2I + d, fine column j = i + o; per axis s = d + o decides the coarse
+// columns J = I + O carrying P(j, J): s even -> O = s/2 (weight 1), s odd ->
+// O = (s-1)/2 and (s+1)/2 (weight 1/2 each).  All indices are compile-time after
+// unrolling, so the 27 (9) coarse blocks stay in registers.
+template <int DIM, bool MASK>
+__global__ void __launch_bounds__(128) k_rap(const Geo F, const Geo C, const double *__restrict__ Af,
+                                             const uint8_t *__restrict__ fmask, double *__restrict__ Ac,
+                                             float *__restrict__ Ac32) {
+  constexpr int NST = DIM == 3 ? 27 : 9;
+  const long long I = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= C.N) return;
+  int cx, cy, cz;
+  vcoords(I, C, cx, cy, cz);
+  double acc[NST][4];
+#pragma unroll
+  for (int o = 0; o < NST; ++o)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) acc[o][e] = 0.0;
+  const long long sy = F.nx, sz = (long long)F.nx * F.ny;
+#pragma unroll
+  for (int dd = 0; dd < NST; ++dd) {
+    const int dx = dd % 3 - 1, dy = (dd / 3) % 3 - 1, dz = DIM == 3 ? dd / 9 - 1 : 0;
+    const int fx = 2 * cx + dx, fy = 2 * cy + dy, fz = (DIM == 3 ? 2 * cz : 0) + dz;
+    if (fx < 0 || fy < 0 || fz < 0 || fx >= F.nx || fy >= F.ny || fz >= F.nz) continue;
+    const long long i = fx + sy * fy + sz * fz;
+    const double wrow = (dx ? 0.5 : 1.0) * (dy ? 0.5 : 1.0) * (dz ? 0.5 : 1.0);
+    double wr0 = wrow, wr1 = wrow;
+    if (MASK) {
+      const uint8_t m = fmask[i];
+      if (m & 1) wr0 = 0.0;
+      if (m & 2) wr1 = 0.0;
+    }
+    const bool xm = fx > 0, xp = fx < F.nx - 1, ym = fy > 0, yp = fy < F.ny - 1;
+    const bool zm = DIM == 3 && fz > 0, zp = DIM == 3 && fz < F.nz - 1;
+#pragma unroll
+    for (int oo = 0; oo < NST; ++oo) {
+      const int ox = oo % 3 - 1, oy = (oo / 3) % 3 - 1, oz = DIM == 3 ? oo / 9 - 1 : 0;
+      const bool ok = (ox < 0 ? xm : (ox > 0 ? xp : true)) && (oy < 0 ? ym : (oy > 0 ? yp : true)) &&
+                      (oz < 0 ? zm : (oz > 0 ? zp : true));
+      if (!ok) continue;
+      const double2 b01 = reinterpret_cast<const double2 *>(Af + ((long long)oo * F.N + i) * 4)[0];
+      const double2 b23 = reinterpret_cast<const double2 *>(Af + ((long long)oo * F.N + i) * 4)[1];
+      double kc0 = 1.0, kc1 = 1.0;
+      if (MASK) {
+        const uint8_t m = fmask[i + ox + sy * oy + sz * oz];
+        if (m & 1) kc0 = 0.0;
+        if (m & 2) kc1 = 0.0;
+      }
+      const double e0 = wr0 * b01.x * kc0, e1 = wr0 * b01.y * kc1;
+      const double e2 = wr1 * b23.x * kc0, e3 = wr1 * b23.y * kc1;
+      const int sx_ = dx + ox, sy_ = dy + oy, sz_ = dz + oz;
+#pragma unroll
+      for (int tz = 0; tz < (DIM == 3 ? 2 : 1); ++tz)
+#pragma unroll
+        for (int ty = 0; ty < 2; ++ty)
+#pragma unroll
+          for (int tx = 0; tx < 2; ++tx) {
+            // per axis: even s -> single target (t = 0 only), odd s -> two targets
+            const bool vx = (sx_ & 1) || tx == 0;
+            const bool vy = (sy_ & 1) || ty == 0;
+            const bool vz = DIM != 3 || (sz_ & 1) || tz == 0;
+            if (!(vx && vy && vz)) continue;
+            const int Ox = (sx_ & 1) ? ((sx_ - 1) / 2 + tx) : sx_ / 2;
+            const int Oy = (sy_ & 1) ? ((sy_ - 1) / 2 + ty) : sy_ / 2;
+            const int Oz = DIM == 3 ? ((sz_ & 1) ? ((sz_ - 1) / 2 + tz) : sz_ / 2) : 0;
+            const double w = ((sx_ & 1) ? 0.5 : 1.0) * ((sy_ & 1) ? 0.5 : 1.0) *
+                             (DIM == 3 ? ((sz_ & 1) ? 0.5 : 1.0) : 1.0);
+            const int T = DIM == 3 ? (Ox + 1) + 3 * (Oy + 1) + 9 * (Oz + 1) : (Ox + 1) + 3 * (Oy + 1);
+            acc[T][0] += w * e0;
+            acc[T][1] += w * e1;
+            acc[T][2] += w * e2;
+            acc[T][3] += w * e3;
+          }
+    }
+  }
+#pragma unroll
+  for (int o = 0; o < NST; ++o) {
+    double *dst = Ac + ((long long)o * C.N + I) * 4;
+    reinterpret_cast<double2 *>(dst)[0] = make_double2(acc[o][0], acc[o][1]);
+    reinterpret_cast<double2 *>(dst)[1] = make_double2(acc[o][2], acc[o][3]);
+    if (Ac32)
+      *reinterpret_cast<float4 *>(Ac32 + ((long long)o * C.N + I) * 4) =
+          make_float4((float)acc[o][0], (float)acc[o][1], (float)acc[o][2], (float)acc[o][3]);
+  }
+}
+
+// Dense coarsest matrix (column-major n x n, n = 2 N) from the stencil rows.
+template <int DIM>
+__global__ void k_densify(const Geo G, const double *__restrict__ A, double *__restrict__ D, int n) {
+  constexpr int NST = DIM == 3 ? 27 : 9;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)NST * G.N) return;
+  const int o = (int)(t / G.N);
+  const long long v = t % G.N;
+  const int dx = o % 3 - 1, dy = (o / 3) % 3 - 1, dz = DIM == 3 ? o / 9 - 1 : 0;
+  int ix, iy, iz;
+  vcoords(v, G, ix, iy, iz);
+  const int x = ix + dx, y = iy + dy, z = iz + dz;
+  if (x < 0 || y < 0 || z < 0 || x >= G.nx || y >= G.ny || z >= G.nz) return;
+  const long long j = x + (long long)G.nx * (y + (long long)G.ny * z);
+  const double *b = A + ((long long)o * G.N + v) * 4;
+  D[(2 * j) * (long long)n + 2 * v] = b[0];
+  D[(2 * j + 1) * (long long)n + 2 * v] = b[1];
+  D[(2 * j) * (long long)n + 2 * v + 1] = b[2];
+  D[(2 * j + 1) * (long long)n + 2 * v + 1] = b[3];
+}
+
+__global__ void k_zero(double *p, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
+// Right-looking LU with partial pivoting of a column-major n x n matrix in one
+// workgroup (the coarsest level has at most a few thousand unknowns).
+__global__ void __launch_bounds__(1024) k_lu(double *__restrict__ a, int n, int *__restrict__ piv) {
+  __shared__ double smax[1024];
+  __shared__ int sidx[1024];
+  const int tid = threadIdx.x;
+  for (int k = 0; k < n; ++k) {
+    // pivot search in column k, rows k..n-1 (ties -> lowest row)
+    double best = -1.0;
+    int bi = k;
+    for (int i = k + tid; i < n; i += blockDim.x) {
+      const double vabs = fabs(a[(long long)k * n + i]);
+      if (vabs > best) { best = vabs; bi = i; }
+    }
+    smax[tid] = best;
+    sidx[tid] = bi;
+    __syncthreads();
+    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+      if (tid < st) {
+        const double o = smax[tid + st];
+        const int oi = sidx[tid + st];
+        if (o > smax[tid] || (o == smax[tid] && oi < sidx[tid])) { smax[tid] = o; sidx[tid] = oi; }
+      }
+      __syncthreads();
+    }
+    const int p = sidx[0];
+    if (tid == 0) piv[k] = p;
+    if (p != k) {
+      for (int j = tid; j < n; j += blockDim.x) {
+        const double t = a[(long long)j * n + k];
+        a[(long long)j * n + k] = a[(long long)j * n + p];
+        a[(long long)j * n + p] = t;
+      }
+    }
+    __syncthreads();
+    const double inv = 1.0 / a[(long long)k * n + k];
+    for (int i = k + 1 + tid; i < n; i += blockDim.x) a[(long long)k * n + i] *= inv;
+    __syncthreads();
+    const int m = n - k - 1;
+    for (long long e = tid; e < (long long)m * m; e += blockDim.x) {
+      const int j = k + 1 + (int)(e / m);
+      const int i = k + 1 + (int)(e % m);
+      a[(long long)j * n + i] -= a[(long long)k * n + i] * a[(long long)j * n + k];
+    }
+    __syncthreads();
+  }
+}
+
+// Column j of A^{-1} from the LU factors (one 64-lane block per column).
+__global__ void __launch_bounds__(64) k_lu_inverse(const double *__restrict__ lu, const int *__restrict__ piv,
+                                                   int n, double *__restrict__ inv) {
+  extern __shared__ double y[];
+  const int j = blockIdx.x;
+  const int lane = threadIdx.x;
+  for (int i = lane; i < n; i += 64) y[i] = (i == j) ? 1.0 : 0.0;
+  __syncthreads();
+  if (lane == 0)
+    for (int k = 0; k < n; ++k) {
+      const int p = piv[k];
+      if (p != k) { const double t = y[k]; y[k] = y[p]; y[p] = t; }
+    }
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {  // L y = P e_j (unit lower)
+    const double yk = y[k];
+    for (int i = k + 1 + lane; i < n; i += 64) y[i] -= lu[(long long)k * n + i] * yk;
+    __syncthreads();
+  }
+  for (int k = n - 1; k >= 0; --k) {  // U x = y
+    if (lane == 0) y[k] = y[k] / lu[(long long)k * n + k];
+    __syncthreads();
+    const double xk = y[k];
+    for (int i = lane; i < k; i += 64) y[i] -= lu[(long long)k * n + i] * xk;
+    __syncthreads();
+  }
+  for (int i = lane; i < n; i += 64) inv[(long long)j * n + i] = y[i];
+}
+
+// x = A^{-1} b on the coarsest level (column-major inverse, one thread per row).
+template <typename T>
+__global__ void __launch_bounds__(64) k_coarse_solve(const double *__restrict__ inv, int n,
+                                                     const T *__restrict__ b, T *__restrict__ x) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  double s = 0.0;
+  for (int c = 0; c < n; ++c) s += inv[(long long)c * n + r] * (double)b[c];
+  x[r] = (T)s;
+}
+
+template <typename TI, typename TO>
+__global__ void k_cast(const TI *__restrict__ a, TO *__restrict__ b, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    b[i] = (TO)a[i];
+}
+
+inline Geo geo(const Level &L) { return Geo{L.n[0], L.n[1], L.n[2], L.N}; }
+
+// ---- V-cycle driver ----------------------------------------------------------
+template <int DIM, typename T>
+tpf_status vcycle_t(tpf_grid *g, const double *bin, double *xout, hipStream_t s) {
+  const int L = g->L;
+  const T om = (T)g->omega;
+  const T *b0;
+  if (sizeof(T) == sizeof(double)) {
+    b0 = reinterpret_cast<const T *>(bin);
+  } else {
+    k_cast<double, T><<<1024, BS, 0, s>>>(bin, reinterpret_cast<T *>(g->lv[0].b), 2 * g->lv[0].N);
+    TPF_LAUNCH_CHECK();
+    b0 = reinterpret_cast<const T *>(g->lv[0].b);
+  }
+  auto A_of = [&](int l) -> const T * {
+    if (sizeof(T) == sizeof(double)) return reinterpret_cast<const T *>(g->lv[l].A64);
+    return reinterpret_cast<const T *>(g->lv[l].A32);
+  };
+  const T *bl[MAXL];
+  T *cur[MAXL];
+  bl[0] = b0;
+  for (int l = 0; l < L - 1; ++l) {
+    Level &lv = g->lv[l];
+    const Geo G = geo(lv);
+    const unsigned nb = blocks_for(lv.N);
+    T *X = reinterpret_cast<T *>(lv.x), *Y = reinterpret_cast<T *>(lv.y);
+    k_jacobi<DIM, T, T, true><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], nullptr, X, om);
+    TPF_LAUNCH_CHECK();
+    for (int k = 1; k < g->nu_pre; ++k) {
+      k_jacobi<DIM, T, T, false><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, Y, om);
+      TPF_LAUNCH_CHECK();
+      T *t = X; X = Y; Y = t;
+    }
+    cur[l] = X;
+    T *R = reinterpret_cast<T *>(lv.r);
+    k_resid<DIM, T><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, R);
+    TPF_LAUNCH_CHECK();
+    Level &lc = g->lv[l + 1];
+    T *bc = reinterpret_cast<T *>(lc.b);
+    k_restrict<DIM, T><<<blocks_for(lc.N), BS, 0, s>>>(G, geo(lc), R, l == 0 ? g->dmask : nullptr, bc);
+    TPF_LAUNCH_CHECK();
+    bl[l + 1] = bc;
+  }
+  // coarsest level
+  {
+    Level &lc = g->lv[L - 1];
+    T *X = (L == 1 && sizeof(T) == sizeof(double)) ? reinterpret_cast<T *>(xout) : reinterpret_cast<T *>(lc.x);
+    k_coarse_solve<T><<<(g->nc + 63) / 64, 64, 0, s>>>(g->ainv, g->nc, bl[L - 1], X);
+    TPF_LAUNCH_CHECK();
+    cur[L - 1] = X;
+    if (L == 1) {
+      if (sizeof(T) != sizeof(double)) {
+        k_cast<T, double><<<1024, BS, 0, s>>>(X, xout, 2 * lc.N);
+        TPF_LAUNCH_CHECK();
+      }
+      return TPF_OK;
+    }
+  }
+  for (int l = L - 2; l >= 0; --l) {
+    Level &lv = g->lv[l];
+    const Geo G = geo(lv);
+    const unsigned nb = blocks_for(lv.N);
+    T *X = cur[l];
+    T *Y = (X == reinterpret_cast<T *>(lv.x)) ? reinterpret_cast<T *>(lv.y) : reinterpret_cast<T *>(lv.x);
+    k_prolong<DIM, T><<<nb, BS, 0, s>>>(G, geo(g->lv[l + 1]), cur[l + 1], l == 0 ? g->dmask : nullptr, X);
+    TPF_LAUNCH_CHECK();
+    const int nu = g->nu_post;
+    for (int k = 0; k < nu; ++k) {
+      if (l == 0 && k == nu - 1) {
+        k_jacobi<DIM, T, double, false><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, xout, om);
+        TPF_LAUNCH_CHECK();
+        X = nullptr;
+        break;
+      }
+      k_jacobi<DIM, T, T, false><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, Y, om);
+      TPF_LAUNCH_CHECK();
+      T *t = X; X = Y; Y = t;
+    }
+    if (l == 0 && X != nullptr) {  // nu_post == 0
+      k_cast<T, double><<<1024, BS, 0, s>>>(X, xout, 2 * lv.N);
+      TPF_LAUNCH_CHECK();
+    }
+    cur[l] = X;
+  }
+  return TPF_OK;
+}
+
+template <int DIM>
+tpf_status hierarchy_t(tpf_grid *g, hipStream_t s) {
+  for (int l = 0; l + 1 < g->L; ++l) {
+    Level &f = g->lv[l], &c = g->lv[l + 1];
+    float *c32 = g->prec == TPF_MIXED ? c.A32 : nullptr;
+    if (l == 0)
+      k_rap<DIM, true><<<blocks_for(c.N, 128), 128, 0, s>>>(geo(f), geo(c), f.A64, g->dmask, c.A64, c32);
+    else
+      k_rap<DIM, false><<<blocks_for(c.N, 128), 128, 0, s>>>(geo(f), geo(c), f.A64, nullptr, c.A64, c32);
+    TPF_LAUNCH_CHECK();
+  }
+  Level &lc = g->lv[g->L - 1];
+  const int n = g->nc;
+  k_zero<<<256, BS, 0, s>>>(g->lu, (long long)n * n);
+  TPF_LAUNCH_CHECK();
+  constexpr int NST = DIM == 3 ? 27 : 9;
+  k_densify<DIM><<<blocks_for((long long)NST * lc.N), BS, 0, s>>>(geo(lc), lc.A64, g->lu, n);
+  TPF_LAUNCH_CHECK();
+  k_lu<<<1, 1024, 0, s>>>(g->lu, n, g->piv);
+  TPF_LAUNCH_CHECK();
+  k_lu_inverse<<<n, 64, (size_t)n * sizeof(double), s>>>(g->lu, g->piv, n, g->ainv);
+  TPF_LAUNCH_CHECK();
+  return TPF_OK;
+}
+
+template <int DIM>
+tpf_status spmv_t(tpf_grid *g, int level, const double *x, double *y, hipStream_t s) {
+  const Level &lv = g->lv[level];
+  k_spmv64<DIM, 0><<<blocks_for(lv.N), BS, 0, s>>>(geo(lv), lv.A64, x, y, nullptr, nullptr);
+  TPF_LAUNCH_CHECK();
+  return TPF_OK;
+}
+
+}  // namespace
+
+tpf_status build_hierarchy(tpf_grid *g, hipStream_t s) {
+  return g->dim == 3 ? hierarchy_t<3>(g, s) : hierarchy_t<2>(g, s);
+}
+
+tpf_status vcycle(tpf_grid *g, const double *b, double *x, hipStream_t s) {
+  if (g->prec == TPF_MIXED)
+    return g->dim == 3 ? vcycle_t<3, float>(g, b, x, s) : vcycle_t<2, float>(g, b, x, s);
+  return g->dim == 3 ? vcycle_t<3, double>(g, b, x, s) : vcycle_t<2, double>(g, b, x, s);
+}
+
+tpf_status spmv64(tpf_grid *g, int level, const double *x, double *y, hipStream_t s) {
+  return g->dim == 3 ? spmv_t<3>(g, level, x, y, s) : spmv_t<2>(g, level, x, y, s);
+}
+
+// Fused SpMV variants used by BiCGSTAB (declared in krylov.hip).
+tpf_status spmv64_mode(tpf_grid *g, int mode, const double *x, double *y, const double *d0, double *part,
+                       unsigned *nblk_out, hipStream_t s) {
+  const Level &lv = g->lv[0];
+  const unsigned nb = blocks_for(lv.N);
+  *nblk_out = nb;
+  const Geo G = geo(lv);
+  if (g->dim == 3) {
+    switch (mode) {
+      case 1: k_spmv64<3, 1><<<nb, BS, 0, s>>>(G, lv.A64, x, y, d0, part); break;
+      case 2: k_spmv64<3, 2><<<nb, BS, 0, s>>>(G, lv.A64, x, y, d0, part); break;
+      case 3: k_spmv64<3, 3><<<nb, BS, 0, s>>>(G, lv.A64, x, y, d0, part); break;
+      default: k_spmv64<3, 0><<<nb, BS, 0, s>>>(G, lv.A64, x, y, d0, part); break;
+    }
+  } else {
+    switch (mode) {
+      case 1: k_spmv64<2, 1><<<nb, BS, 0, s>>>(G, lv.A64, x, y, d0, part); break;
+      case 2: k_spmv64<2, 2><<<nb, BS, 0, s>>>(G, lv.A64, x, y, d0, part); break;
+      case 3: k_spmv64<2, 3><<<nb, BS, 0, s>>>(G, lv.A64, x, y, d0, part); break;
+      default: k_spmv64<2, 0><<<nb, BS, 0, s>>>(G, lv.A64, x, y, d0, part); break;
+    }
+  }
+  TPF_LAUNCH_CHECK();
+  return TPF_OK;
+}
+
+}  // namespace tpf

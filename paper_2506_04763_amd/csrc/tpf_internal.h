@@ -1,0 +1,138 @@
+// Internal declarations of the gfx950 stage-solver library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "tpf.h"
+
+namespace tpf {
+
+constexpr int MAXL = 12;          // multigrid levels
+constexpr int MAXK = 6;           // LIMEX stages
+constexpr double SE_MIN = 1.0e-6; // lower clamp of the effective saturation
+constexpr int BS = 256;           // threads per block of the vertex kernels
+constexpr int RED_BLOCKS = 1024;  // fixed grid of the grid-stride reduction kernels
+constexpr int NSCAL = 32;         // device scalars of the Krylov solver
+
+// Scalars of the Krylov recurrence kept on the device (indices into g->scal).
+enum Scal {
+  S_RHO = 0, S_RHO_OLD, S_ALPHA, S_OMEGA, S_BETA, S_RV, S_TS, S_TT, S_RR, S_FF, S_WW,
+  S_NORM_A, S_NORM_B, S_NORM_C, S_NORM_D, S_COUNT
+};
+
+// Physical and geometric constants passed by value to every kernel.
+struct Phys {
+  int nx, ny, nz;
+  long long N;        // vertices
+  int ncx, ncy, ncz;  // cells per axis (ncz = 1 in 2D)
+  double h[3];        // spacing (h[2] = 1 in 2D: unit depth)
+  double g[3];        // gravity
+  double rho_w, rho_n, mu_w, mu_n;
+  double swr, snr, D; // D = (1 - S_wr) - S_nr
+  double vol, scv;    // cell volume, sub-control-volume volume
+  double area[3];     // SCVF area of an edge along each axis
+};
+
+struct PatchDev {
+  int axis, side, phase, pad;
+  double lo[2], hi[2], rate;
+};
+struct Patches {
+  int n;
+  PatchDev p[TPF_MAX_PATCHES];
+};
+
+struct Level {
+  int n[3];
+  long long N;
+  double *A64;  // [nst][N][4]
+  float *A32;   // [nst][N][4] (mixed precision only)
+  void *x, *y, *b, *r;  // level vectors, 2N entries of the level type
+};
+
+}  // namespace tpf
+
+struct tpf_grid {
+  tpf::Phys P;
+  int dim, nst, L, prec, nu_pre, nu_post, kmax;
+  double omega;
+  long long ncells;
+  // scenario
+  double *K, *phi, *pd, *lam;
+  double *pdmin, *lamref, *pv;
+  uint8_t *dmask;
+  double *dval, *Q;
+  tpf::Level lv[tpf::MAXL];
+  // coarsest level, dense
+  int nc;
+  double *lu, *ainv;
+  int *piv;
+  // Krylov vectors (double[2N])
+  double *r, *rh, *p, *v, *s, *t, *ph, *sh, *w, *xb;
+  double *part;
+  long long npart;
+  double *scal;
+  // LIMEX
+  double *u0, *f0, *fv, *T[tpf::MAXK], *Tp;
+  // host side
+  double *hscal;  // pinned, NSCAL doubles
+  bool assembled;
+  bool has_f0;
+  size_t bytes;
+  int device;
+};
+
+namespace tpf {
+
+void set_error(const char *fmt, ...);
+
+#define TPF_HIP(call)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (call);                                                        \
+    if (e_ != hipSuccess) {                                                        \
+      ::tpf::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_),      \
+                       __FILE__, __LINE__);                                        \
+      return TPF_EDEVICE;                                                          \
+    }                                                                              \
+  } while (0)
+
+#define TPF_LAUNCH_CHECK() TPF_HIP(hipGetLastError())
+
+inline unsigned blocks_for(long long n, int bs = BS) { return (unsigned)((n + bs - 1) / bs); }
+
+// Logical block index of an XCD-aware launch: the hardware dispatches block k to
+// XCD k mod 8; this mapping gives every XCD one contiguous eighth of the grid so
+// that neighbouring rows (which share x entries) meet in the same L2.
+__device__ __forceinline__ unsigned xcd_block(unsigned bid, unsigned nblk) {
+  const unsigned per = nblk >> 3;
+  const unsigned full = per << 3;
+  if (bid >= full) return bid;
+  return (bid & 7u) * per + (bid >> 3);
+}
+
+// ---- launchers (assemble.hip) ----
+tpf_status setup_vertices(tpf_grid *g, const Patches &pt, hipStream_t s);
+tpf_status launch_residual(tpf_grid *g, const double *u, double *f, hipStream_t s);
+tpf_status launch_assemble(tpf_grid *g, const double *u0, double h, double *f0, hipStream_t s);
+tpf_status launch_apply_dirichlet(tpf_grid *g, double *u, hipStream_t s);
+
+// ---- launchers (mg.hip) ----
+tpf_status build_hierarchy(tpf_grid *g, hipStream_t s);
+tpf_status vcycle(tpf_grid *g, const double *b, double *x, hipStream_t s);
+// y = A x (FP64, level l); if dot_with != null also block partials of (dot_with, y)
+// and, if second != null, (second, y) and (y, y) as selected by mode.
+tpf_status spmv64(tpf_grid *g, int level, const double *x, double *y, hipStream_t s);
+
+// ---- krylov.hip ----
+tpf_status bicgstab(tpf_grid *g, const double *f, double *x, double rtol, int maxit,
+                    tpf_solve_stats *st, hipStream_t s);
+
+// ---- shared small kernels (krylov.hip) ----
+tpf_status fill_zero(double *p, long long n, hipStream_t s);
+tpf_status copy_vec(double *dst, const double *src, long long n, hipStream_t s);
+
+}  // namespace tpf
