@@ -1,0 +1,210 @@
+#!/usr/bin/env python3
+"""Stage-solve benchmark of the gfx950 two-phase solver.
+
+One step = one LIMEX stage solve on the 129^3-vertex log-normal cube (sigma_lnK = 2,
+correlation 8 cells, 4,293,378 DoF): assemble A = M(u0)/h - J(u0) and F(u0) in one
+kernel, build the 6-level Galerkin hierarchy (FP32 copies + coarsest inverse), then
+BiCGSTAB in FP64 preconditioned by the FP32 V(2,2) cycle to ||r|| <= 1e-8 ||F||.
+The state is resident in HBM before the clock starts.
+
+Prints one JSON line (see the field list in the design doc).  Options:
+  --gpus N      only N = 1 is supported (the path runs on one GPU)
+  --steps K     timed steps (default 10)      --warmup W  untimed steps (default 2)
+  --no-cpu      skip the oracle CPU baseline  --no-fp64   skip the FP64 comparison
+  --serve       also run the continuous-batching serving workload (p50/p99)
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+NST = 27
+
+
+def algorithmic_bytes(cls: str, N: int, Nc_levels) -> float:
+    """Bytes one launch of a kernel class must move (3D, per the data layout).
+
+    smooth0 / resid0 (FP32): 27 blocks x 16 B of matrix + x, b, out (3 x 8 B) per vertex
+    spmv64 (FP64): 27 x 32 B of matrix + x, y and the fused dot operand (3 x 16 B)
+    assemble (mixed): FP64 + FP32 matrix writes (864 + 432 B), F write, state and
+      per-vertex data reads (u, pv 32 B, p_dmin 8 B, Q 16 B, mask 1 B), cell data 32 B
+    rap: per coarse level, the FP64 fine matrix read and FP64 + FP32 coarse writes.
+    """
+    if cls in ("smooth0", "resid0"):
+        return N * (NST * 16 + 24)
+    if cls == "smooth0_first":
+        return N * (16 + 16)
+    if cls == "spmv64":
+        return N * (NST * 32 + 48)
+    if cls == "assemble":
+        return N * (NST * 48 + 16 + 32 + 8 + 16 + 1 + 32)
+    if cls == "rap":
+        return sum(nf * NST * 32 + nc * NST * 48 for nf, nc in Nc_levels) / max(len(Nc_levels), 1)
+    return float("nan")
+
+
+def cpu_baseline(n_sample=33):
+    """The FP64 oracle, as it stands, on a bounded sample: one full stage (assembly by
+    complex-step Jacobian, Galerkin hierarchy, BiCGSTAB to 1e-8) of the same recipe on
+    a 33^3 grid, single-threaded; scaled linearly in DoF to 129^3 stage solves/s."""
+    from threadpoolctl import threadpool_limits
+
+    import workloads as W
+    from oracle import stage as ST
+    scn = W.cube_3d(n_sample, 2.0, 3, levels=4)
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        st = ST.Stage(scn)
+        u = scn.u0.ravel()
+        f = st.residual(u)
+        st.assemble(u, 32.0)
+        x, info = st.solve(f, rtol=1e-8)
+        dt = time.perf_counter() - t0
+    scale = (n_sample ** 3) / (129 ** 3)
+    return {"value": scale / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"one oracle stage solve (assemble + GMG setup + BiCGSTAB to 1e-8) on the {n_sample}^3 "
+                      f"grid of the same recipe took {dt:.2f} s ({info['iters']} iterations); value scaled "
+                      f"linearly in DoF to 129^3"}
+
+
+def run(args):
+    import torch
+
+    import paper_2506_04763_amd as tpf
+    import workloads as W
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a ROCm GPU")
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    scn = W.cube_c3()
+    N = scn.nverts
+    h = 32.0
+    rtol = 1e-8
+    results = {}
+    for prec in (["mixed"] if args.no_fp64 else ["mixed", "fp64"]):
+        g = tpf.Grid(scn, precision=prec, levels=6)
+        u0 = g.initial_state()
+        f = g.empty()
+        x = g.empty()
+        stats = None
+        for _ in range(args.warmup):
+            g.assemble_stage(u0, h, f0_out=f)
+            x, stats = g.solve_stage(f, rtol=rtol, maxit=500, out=x)
+        torch.cuda.synchronize()
+        prof = prec == "mixed"
+        if prof:
+            g.profile_begin(200000)
+        t0 = time.perf_counter()
+        iters = []
+        for _ in range(args.steps):
+            g.assemble_stage(u0, h, f0_out=f)
+            x, stats = g.solve_stage(f, rtol=rtol, maxit=500, out=x)
+            iters.append(stats["iters"])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        kt = g.profile_end() if prof else None
+        results[prec] = dict(ms=(t1 - t0) * 1e3 / args.steps, iters=iters, stats=stats, kt=kt,
+                             levels=[g.level_dims(l) for l in range(g.levels)], bytes=g.nbytes)
+        g.close()
+        del g
+        torch.cuda.empty_cache()
+
+    mixed = results["mixed"]
+    lv = mixed["levels"]
+    nlev = [(lv[i][0] * lv[i][1] * lv[i][2], lv[i + 1][0] * lv[i + 1][1] * lv[i + 1][2]) for i in range(len(lv) - 1)]
+    kernels = {}
+    for cls, (cnt, tot) in mixed["kt"].items():
+        if cnt == 0:
+            continue
+        avg = tot / cnt
+        b = algorithmic_bytes(cls, N, nlev)
+        kernels[cls] = {"launches": cnt, "avg_ms": round(avg, 5), "total_ms_per_step": round(tot / args.steps, 3),
+                        "gbs": (round(b / (avg * 1e-3) / 1e9, 1) if b == b else None)}
+    hot = [k for k in ("smooth0", "resid0", "spmv64", "assemble") if k in kernels]
+    dom = max(hot, key=lambda k: kernels[k]["total_ms_per_step"])
+    avg_ms = kernels[dom]["avg_ms"]
+    ach = algorithmic_bytes(dom, N, nlev) / (avg_ms * 1e-3) / 1e9
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tfile):
+        try:
+            tj = json.load(open(tfile))
+            if tj.get("kernel") == dom and tj.get("source_hash") == _source_hash():
+                traffic = tj.get("bytes_per_launch")
+        except Exception:
+            traffic = None
+    line = {
+        "metric": "LIMEX stage solves/sec at 129^3 (assemble + GMG setup + BiCGSTAB to 1e-8)",
+        "value": round(1e3 / mixed["ms"], 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(mixed["ms"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": "cube129_lognormal_sigma2_seed3_mixed", "vertices": [129, 129, 129], "dof": 2 * N,
+                   "levels": len(lv), "precision": "FP32 multigrid in FP64 BiCGSTAB", "rtol": rtol, "h_s": h,
+                   "smoother": "V(2,2) block-Jacobi omega=2/3"},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic},
+        "iterations": mixed["iters"][-1],
+        "rel_res_true": mixed["stats"]["rel_res_true"],
+        "kernels": kernels,
+        "arena_gb": round(mixed["bytes"] / 1e9, 3),
+    }
+    if "fp64" in results:
+        r = results["fp64"]
+        line["fp64"] = {"solves_per_s": round(1e3 / r["ms"], 4), "ms_per_step": round(r["ms"], 3),
+                        "iterations": r["iters"][-1], "rel_res_true": r["stats"]["rel_res_true"]}
+        line["mixed_over_fp64"] = round(r["ms"] / mixed["ms"], 3)
+    sm = [kernels[k]["gbs"] for k in ("smooth0", "resid0") if k in kernels]
+    line["spmv_smoother_gbs"] = {"spmv64": kernels.get("spmv64", {}).get("gbs"),
+                                 "smoother_fp32": kernels.get("smooth0", {}).get("gbs"),
+                                 "resid_fp32": kernels.get("resid0", {}).get("gbs")}
+    if args.serve:
+        from paper_2506_04763_amd import serve as SV
+        line["serving"] = SV.run_benchmark(count=args.serve_requests, quiet=True)
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline()
+    return line
+
+
+def _source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(os.path.join(ROOT, "paper_2506_04763_amd", "csrc"))):
+        h.update(open(os.path.join(ROOT, "paper_2506_04763_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=256)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU: the stage solver has no multi-GPU "
+                                   "path (see DESIGN.md for how it would shard)", "n_gpus": args.gpus}))
+        sys.exit(2)
+    print(json.dumps(run(args)), flush=True)
+
+
+if __name__ == "__main__":
+    main()

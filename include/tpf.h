@@ -174,8 +174,10 @@ tpf_status tpf_residual(tpf_grid *g, const double *u, double *f, tpf_stream stre
  * linearly implicit Euler step divided by tau = h); then the multigrid hierarchy:
  * Galerkin coarse matrices, their FP32 copies in TPF_MIXED, and the inverse of the
  * coarsest matrix from an LU factorisation with partial pivoting.  u0: device
- * double[2N]; h > 0 seconds.  Also stores F(u0) for the first LIMEX substep. */
-tpf_status tpf_assemble_stage(tpf_grid *g, const double *u0, double h, tpf_stream stream);
+ * double[2N]; h > 0 seconds.  F(u0) is produced by the same kernel: if f0_out is
+ * not NULL it receives F(u0) (device double[2N], the right-hand side of the first
+ * substep of a stage). */
+tpf_status tpf_assemble_stage(tpf_grid *g, const double *u0, double h, double *f0_out, tpf_stream stream);
 
 /* Solves A x = f (A from the last assemble_stage) with right-preconditioned
  * BiCGSTAB, x0 = 0, one V(nu_pre, nu_post) cycle as preconditioner, until
@@ -221,6 +223,35 @@ tpf_status tpf_copy_coarse_inverse(tpf_grid *g, double *dst, tpf_stream stream);
 
 /* Device buffer with p_dmin per vertex (read-only view into the arena). */
 const double *tpf_pdmin_ptr(const tpf_grid *g);
+
+/* ---- kernel timing (HIP events recorded around selected launches) ----------- */
+enum {
+  TPF_K_ASSEMBLE = 0,   /* fine-level residual + stage-matrix assembly            */
+  TPF_K_RAP,            /* Galerkin coarse operator, all levels                   */
+  TPF_K_COARSE_LU,      /* dense LU + inverse of the coarsest level               */
+  TPF_K_SPMV64,         /* FP64 stencil SpMV on the finest level (all variants)   */
+  TPF_K_SMOOTH0,        /* block-Jacobi sweep on the finest level (full sweeps)   */
+  TPF_K_SMOOTH0_FIRST,  /* first sweep from a zero guess (diagonal only)          */
+  TPF_K_RESID0,         /* level residual on the finest level                     */
+  TPF_K_COARSE_LEVELS,  /* every smoother/residual/transfer launch below level 0  */
+  TPF_K_TRANSFER0,      /* restriction from and prolongation to the finest level  */
+  TPF_K_COUNT
+};
+
+typedef struct tpf_kernel_time {
+  int32_t count;        /* timed launches                                        */
+  int32_t reserved;
+  double total_ms;      /* summed event-to-event durations                       */
+} tpf_kernel_time;
+
+/* Starts recording a pair of HIP events around each launch of the classes above
+ * (up to max_launches launches; later launches are not timed).  Creates the
+ * events; no device memory is allocated. */
+tpf_status tpf_profile_begin(tpf_grid *g, int32_t max_launches);
+
+/* Synchronises the recorded events, writes per-class totals to out[TPF_K_COUNT]
+ * and destroys the events. */
+tpf_status tpf_profile_end(tpf_grid *g, tpf_kernel_time *out);
 
 #ifdef __cplusplus
 }

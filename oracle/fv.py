@@ -336,6 +336,12 @@ class FV:
         dofs = np.concatenate([2 * np.nonzero(m & 1)[0], 2 * np.nonzero(m & 2)[0] + 1])
         return np.sort(dofs)
 
+    def storage_part(self, u0, h):
+        """M(u0)/h with the Dirichlet rows cleared: the storage part of the stage matrix."""
+        keep = np.ones(2 * self.N)
+        keep[self.dirichlet_dofs()] = 0.0
+        return sp.csr_matrix(sp.diags(keep) @ self.mass_matrix(u0) / h)
+
     def stage_matrix(self, u0, h, cells=None):
         """A = M(u0)/h - J(u0) (Section 4: the linearly implicit Euler matrix divided
         by the step), with unit rows at the Dirichlet components."""

@@ -6,7 +6,15 @@ here (listed in DESIGN.md):
   * levels by vertex halving n -> (n-1)/2 + 1 along every active axis;
   * prolongation P = per-component (bi/tri)linear interpolation from level l+1 to l;
     on the finest level the rows of P at Dirichlet components are zero;
-  * restriction R = P^T and Galerkin coarse operators A_{l+1} = P^T A_l P;
+  * restriction R = P^T; coarse operators are Galerkin products of the flux part
+    plus a lumped storage part:
+        A_{l+1} = P^T (A_l - S_l) P + S_{l+1},
+        S_{l+1} = row-sum lumping of P^T S_l P placed on the S_n column,
+    where S_0 = M(u0)/h (zero on Dirichlet rows) is the box method's diagonal storage.
+    The plain product P^T A P turns the diagonal storage into a 27-point
+    consistent-mass block whose Jacobi spectrum reaches 27/8 > 2/omega; keeping
+    the coarse storage lumped, as the box method has it on the fine grid, keeps the
+    block-Jacobi smoother stable on every level;
   * smoother: damped point-block Jacobi with the 2x2 diagonal blocks D,
     x <- x + omega D^{-1} (b - A x), zero initial guess on every level;
   * V(nu1, nu2) cycle; the coarsest level is solved with a dense LU factorisation
@@ -37,13 +45,27 @@ def interp_1d(nf: int) -> sp.csr_matrix:
     return sp.csr_matrix((vals, (rows, cols)), shape=(nf, nc))
 
 
-def prolongation(n, dim, dir_mask=None) -> sp.csr_matrix:
-    """P for interleaved DoFs (2*v + comp), vertices x-fastest."""
+def aggregate_1d(nf: int) -> sp.csr_matrix:
+    """Piecewise-constant interpolation on a line: fine vertex i takes the value of
+    coarse vertex (i + 1) // 2 (coarse I aggregates fine 2I - 1 and 2I)."""
+    if nf == 1:
+        return sp.csr_matrix(np.ones((1, 1)))
+    nc = coarse_size(nf)
+    rows = np.arange(nf)
+    return sp.csr_matrix((np.ones(nf), (rows, (rows + 1) // 2)), shape=(nf, nc))
+
+
+def prolongation(n, dim, dir_mask=None, kinds=("linear", "constant")) -> sp.csr_matrix:
+    """P for interleaved DoFs (2*v + comp), vertices x-fastest; kinds[c] is the
+    interpolation of component c ('linear' or 'constant')."""
     nx, ny, nz = n
-    Px, Py = interp_1d(nx), interp_1d(ny)
-    Pz = interp_1d(nz) if dim == 3 else sp.csr_matrix(np.ones((1, 1)))
-    Pv = sp.kron(Pz, sp.kron(Py, Px, format="csr"), format="csr")
-    P = sp.kron(Pv, sp.identity(2, format="csr"), format="csr")
+    blocks = []
+    for kind in kinds:
+        f1 = interp_1d if kind == "linear" else aggregate_1d
+        Pz = f1(nz) if dim == 3 else sp.csr_matrix(np.ones((1, 1)))
+        blocks.append(sp.kron(Pz, sp.kron(f1(ny), f1(nx), format="csr"), format="csr"))
+    e = [sp.csr_matrix(([1.0], ([c], [c])), shape=(2, 2)) for c in range(2)]
+    P = sp.csr_matrix(sp.kron(blocks[0], e[0]) + sp.kron(blocks[1], e[1]))
     if dir_mask is not None:
         keep = np.ones(P.shape[0])
         keep[2 * np.nonzero(dir_mask & 1)[0]] = 0.0
@@ -76,15 +98,35 @@ def block_diag_inverse(A: sp.csr_matrix) -> np.ndarray:
     return inv
 
 
+def lumped_storage(P, S):
+    """Row sums of P^T S P placed on the S_n column of each 2x2 diagonal block."""
+    d = np.asarray((P.T @ S @ P).sum(axis=1)).ravel()
+    n2 = d.size
+    rows = np.arange(n2)
+    cols = 2 * (rows // 2) + 1
+    return sp.csr_matrix((d, (rows, cols)), shape=(n2, n2))
+
+
 class Hierarchy:
-    def __init__(self, A0, n, dim, levels, dir_mask, omega=2.0 / 3.0, nu1=2, nu2=2):
+    def __init__(self, A0, n, dim, levels, dir_mask, omega=2.0 / 3.0, nu1=2, nu2=2, S0=None):
+        """S0: storage part of A0 (block diagonal, S_n column only); None means zero."""
         self.sizes = level_sizes(n, dim, levels)
         self.A = [sp.csr_matrix(A0)]
+        S = sp.csr_matrix(A0.shape) if S0 is None else sp.csr_matrix(S0)
+        self.S = [S]
         self.P = []
         for l in range(levels - 1):
             P = prolongation(self.sizes[l], dim, dir_mask if l == 0 else None)
             self.P.append(P)
-            self.A.append(sp.csr_matrix(P.T @ self.A[-1] @ P))
+            Sc = lumped_storage(P, self.S[-1])
+            Ac = P.T @ (self.A[-1] - self.S[-1]) @ P + Sc
+            # coarse DoFs whose prolongation column is empty (an aggregate made only
+            # of Dirichlet components) are decoupled: give them a unit diagonal
+            empty = np.asarray(abs(P).sum(axis=0)).ravel() == 0.0
+            if empty.any():
+                Ac = Ac + sp.diags(empty.astype(np.float64))
+            self.A.append(sp.csr_matrix(Ac))
+            self.S.append(Sc)
         self.Dinv = [block_diag_inverse(A) for A in self.A]
         self.lu = sla.lu_factor(self.A[-1].toarray())
         self.omega, self.nu1, self.nu2 = omega, nu1, nu2

@@ -162,9 +162,16 @@ class Grid:
         L.check(self.lib.tpf_residual(self.handle, _ptr(u), _ptr(f), self._sptr()), "tpf_residual")
         return f
 
-    def assemble_stage(self, u0, h):
+    def assemble_stage(self, u0, h, f0_out=None):
+        """A = M(u0)/h - J(u0) and the hierarchy; if f0_out (a float64 device tensor of
+        2N entries) is given it receives F(u0), computed by the same kernel."""
         u0 = self._vec(u0)
-        L.check(self.lib.tpf_assemble_stage(self.handle, _ptr(u0), float(h), self._sptr()), "tpf_assemble_stage")
+        fp = None if f0_out is None else _ptr(self._vec(f0_out))
+        if f0_out is not None and fp.value != f0_out.data_ptr():
+            raise ValueError("f0_out must be a contiguous float64 tensor on the grid's device")
+        L.check(self.lib.tpf_assemble_stage(self.handle, _ptr(u0), float(h), fp, self._sptr()),
+                "tpf_assemble_stage")
+        return f0_out
 
     def solve_stage(self, f, rtol=1e-10, maxit=500, out=None, raise_on_soft=False):
         f = self._vec(f)
@@ -226,6 +233,14 @@ class Grid:
         out = self.torch.empty(nc * nc, dtype=self.torch.float64, device=self.device)
         L.check(self.lib.tpf_copy_coarse_inverse(self.handle, _ptr(out), self._sptr()), "tpf_copy_coarse_inverse")
         return out.reshape(nc, nc).t()  # column-major storage
+
+    def profile_begin(self, max_launches=65536):
+        L.check(self.lib.tpf_profile_begin(self.handle, int(max_launches)), "tpf_profile_begin")
+
+    def profile_end(self):
+        arr = (L.KernelTime * len(L.KERNEL_CLASSES))()
+        L.check(self.lib.tpf_profile_end(self.handle, arr), "tpf_profile_end")
+        return {name: (arr[i].count, arr[i].total_ms) for i, name in enumerate(L.KERNEL_CLASSES)}
 
     def close(self):
         if getattr(self, "handle", None):

@@ -61,6 +61,13 @@ class LimexStats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class KernelTime(C.Structure):
+    _fields_ = [("count", C.c_int32), ("reserved", C.c_int32), ("total_ms", C.c_double)]
+
+
+KERNEL_CLASSES = ["assemble", "rap", "coarse_lu", "spmv64", "smooth0", "smooth0_first", "resid0",
+                  "coarse_levels", "transfer0"]
+
 VP = C.c_void_p
 DP = C.c_void_p  # device pointers are passed as integers
 
@@ -72,7 +79,7 @@ _SIGS = {
     "tpf_destroy_grid": (None, [VP]),
     "tpf_apply_dirichlet": (C.c_int32, [VP, DP, VP]),
     "tpf_residual": (C.c_int32, [VP, DP, DP, VP]),
-    "tpf_assemble_stage": (C.c_int32, [VP, DP, C.c_double, VP]),
+    "tpf_assemble_stage": (C.c_int32, [VP, DP, C.c_double, DP, VP]),
     "tpf_solve_stage": (C.c_int32, [VP, DP, DP, C.c_double, C.c_int32, C.POINTER(SolveStats), VP]),
     "tpf_limex_step": (C.c_int32, [VP, DP, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(LimexOpts),
                                    C.POINTER(LimexStats), VP]),
@@ -83,6 +90,8 @@ _SIGS = {
     "tpf_precondition": (C.c_int32, [VP, DP, DP, VP]),
     "tpf_copy_coarse_inverse": (C.c_int32, [VP, DP, VP]),
     "tpf_pdmin_ptr": (VP, [VP]),
+    "tpf_profile_begin": (C.c_int32, [VP, C.c_int32]),
+    "tpf_profile_end": (C.c_int32, [VP, C.POINTER(KernelTime)]),
 }
 
 _lib = None

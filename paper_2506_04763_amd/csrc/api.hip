@@ -133,6 +133,7 @@ void layout(const tpf_grid_desc *d, Layout &L) {
     L.off_lv[l] = o;
     o += align_up((size_t)L.nst * 4 * L.Nl[l] * sizeof(double));
     if (d->precision == TPF_MIXED) o += align_up((size_t)L.nst * 4 * L.Nl[l] * sizeof(float));
+    o += align_up(2 * L.Nl[l] * sizeof(double));
     o += 4 * align_up(2 * L.Nl[l] * vsz);
   }
   L.off_coarse = o;
@@ -241,6 +242,7 @@ tpf_status tpf_create_grid(const tpf_grid_desc *d, void *arena, size_t arena_byt
     if (d->precision == TPF_MIXED) {
       lv.A32 = reinterpret_cast<float *>(base + o); o += align_up((size_t)L.nst * 4 * lv.N * sizeof(float));
     }
+    lv.mst = reinterpret_cast<double *>(base + o); o += align_up(2 * lv.N * sizeof(double));
     lv.x = base + o; o += align_up(2 * lv.N * vsz);
     lv.y = base + o; o += align_up(2 * lv.N * vsz);
     lv.b = base + o; o += align_up(2 * lv.N * vsz);
@@ -316,8 +318,11 @@ tpf_status tpf_create_grid(const tpf_grid_desc *d, void *arena, size_t arena_byt
   return TPF_OK;
 }
 
+static void prof_release(tpf_grid *g);
+
 void tpf_destroy_grid(tpf_grid *g) {
   if (!g) return;
+  prof_release(g);
   if (g->hscal) (void)hipHostFree(g->hscal);
   delete g;
 }
@@ -335,12 +340,13 @@ tpf_status tpf_residual(tpf_grid *g, const double *u, double *f, tpf_stream stre
   return launch_residual(g, u, f, reinterpret_cast<hipStream_t>(stream));
 }
 
-tpf_status tpf_assemble_stage(tpf_grid *g, const double *u0, double h, tpf_stream stream) {
+tpf_status tpf_assemble_stage(tpf_grid *g, const double *u0, double h, double *f0_out, tpf_stream stream) {
   g_err[0] = 0;
   if (!g || !u0) { set_error("NULL argument"); return TPF_EINVAL; }
   if (!(h > 0.0) || !std::isfinite(h)) { set_error("h must be positive and finite"); return TPF_EINVAL; }
+  if (f0_out == u0) { set_error("u0 and f0_out may not alias"); return TPF_EINVAL; }
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  tpf_status st = launch_assemble(g, u0, h, g->f0, s);
+  tpf_status st = launch_assemble(g, u0, h, f0_out ? f0_out : g->f0, s);
   if (st != TPF_OK) return st;
   st = build_hierarchy(g, s);
   if (st != TPF_OK) return st;
@@ -425,5 +431,56 @@ tpf_status tpf_copy_coarse_inverse(tpf_grid *g, double *dst, tpf_stream stream) 
 }
 
 const double *tpf_pdmin_ptr(const tpf_grid *g) { return g ? g->pdmin : nullptr; }
+
+static void prof_release(tpf_grid *g) {
+  Prof &p = g->prof;
+  if (p.ev) {
+    for (int i = 0; i < 2 * p.cap; ++i) (void)hipEventDestroy(p.ev[i]);
+    delete[] p.ev;
+  }
+  delete[] p.cls;
+  p = Prof();
+}
+
+tpf_status tpf_profile_begin(tpf_grid *g, int32_t max_launches) {
+  g_err[0] = 0;
+  if (!g || max_launches < 1 || max_launches > (1 << 20)) { set_error("bad argument"); return TPF_EINVAL; }
+  prof_release(g);
+  Prof &p = g->prof;
+  p.ev = new (std::nothrow) hipEvent_t[2 * (size_t)max_launches];
+  p.cls = new (std::nothrow) int[max_launches];
+  if (!p.ev || !p.cls) { prof_release(g); set_error("host allocation failed"); return TPF_ENOMEM; }
+  for (int i = 0; i < 2 * max_launches; ++i) {
+    if (hipEventCreate(&p.ev[i]) != hipSuccess) {
+      p.cap = i / 2;
+      prof_release(g);
+      set_error("hipEventCreate failed");
+      return TPF_EDEVICE;
+    }
+    p.cap = (i + 1) / 2;
+  }
+  p.cap = max_launches;
+  p.used = 0;
+  p.active = 1;
+  return TPF_OK;
+}
+
+tpf_status tpf_profile_end(tpf_grid *g, tpf_kernel_time *out) {
+  g_err[0] = 0;
+  if (!g || !out) { set_error("bad argument"); return TPF_EINVAL; }
+  Prof &p = g->prof;
+  for (int c = 0; c < TPF_K_COUNT; ++c) out[c] = tpf_kernel_time{0, 0, 0.0};
+  tpf_status st = TPF_OK;
+  for (int i = 0; i < p.used; ++i) {
+    if (hipEventSynchronize(p.ev[2 * i + 1]) != hipSuccess) { st = TPF_EDEVICE; break; }
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.ev[2 * i], p.ev[2 * i + 1]) != hipSuccess) { st = TPF_EDEVICE; break; }
+    out[p.cls[i]].count += 1;
+    out[p.cls[i]].total_ms += ms;
+  }
+  if (st != TPF_OK) set_error("event timing failed");
+  prof_release(g);
+  return st;
+}
 
 }  // extern "C"

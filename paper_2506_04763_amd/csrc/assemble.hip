@@ -23,7 +23,7 @@
 namespace tpf {
 namespace {
 
-__device__ __forceinline__ void eff_sat(double sn, const Phys &P, double &se, double &dse) {
+__host__ __device__ __forceinline__ void eff_sat(double sn, const Phys &P, double &se, double &dse) {
   const double raw = ((1.0 - sn) - P.swr) / P.D;
   if (raw < SE_MIN) {
     se = SE_MIN; dse = 0.0;
@@ -35,7 +35,7 @@ __device__ __forceinline__ void eff_sat(double sn, const Phys &P, double &se, do
 }
 
 // Burdine wetting relative permeability and its derivative w.r.t. S_n.
-__device__ __forceinline__ void krw(double sn, double lam, const Phys &P, double &k, double &dk) {
+__host__ __device__ __forceinline__ void krw(double sn, double lam, const Phys &P, double &k, double &dk) {
   double se, dse;
   eff_sat(sn, P, se, dse);
   const double e = (2.0 + 3.0 * lam) / lam;
@@ -44,7 +44,7 @@ __device__ __forceinline__ void krw(double sn, double lam, const Phys &P, double
 }
 
 // Burdine non-wetting relative permeability and its derivative w.r.t. S_n.
-__device__ __forceinline__ void krn(double sn, double lam, const Phys &P, double &k, double &dk) {
+__host__ __device__ __forceinline__ void krn(double sn, double lam, const Phys &P, double &k, double &dk) {
   double se, dse;
   eff_sat(sn, P, se, dse);
   const double a = (2.0 + lam) / lam;
@@ -109,12 +109,10 @@ __global__ void __launch_bounds__(BS) k_setup(const Phys P, const double *__rest
 
 // Vertex capillary pressure in the reference medium, P_i = p_dmin,i J(S_i), and its
 // derivative w.r.t. S_n,i (an input to every hat evaluation around the vertex).
-__global__ void __launch_bounds__(BS) k_vertex_pc(const Phys P, const double *__restrict__ u,
+__host__ __device__ __forceinline__ void vertex_pc(const long long v, const Phys &P, const double *__restrict__ u,
                                                   const double *__restrict__ pdmin,
                                                   const double *__restrict__ lamref,
                                                   double *__restrict__ pv) {
-  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= P.N) return;
   double se, dse;
   eff_sat(u[2 * v + 1], P, se, dse);
   const double lr = lamref[v];
@@ -123,29 +121,36 @@ __global__ void __launch_bounds__(BS) k_vertex_pc(const Phys P, const double *__
   pv[2 * v + 1] = pc * (-1.0 / lr) / se * dse;
 }
 
+__global__ void __launch_bounds__(BS) k_vertex_pc(const Phys P, const double *__restrict__ u,
+                                                  const double *__restrict__ pdmin,
+                                                  const double *__restrict__ lamref,
+                                                  double *__restrict__ pv) {
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= P.N) return;
+  vertex_pc(v, P, u, pdmin, lamref, pv);
+}
+
 template <int DIM>
-__device__ __forceinline__ constexpr int stencil_index(int dx, int dy, int dz) {
+__host__ __device__ __forceinline__ constexpr int stencil_index(int dx, int dy, int dz) {
   return DIM == 3 ? (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1) : (dx + 1) + 3 * (dy + 1);
 }
 
-__device__ __forceinline__ constexpr int bit(int l, int a) { return (l >> a) & 1; }
+__host__ __device__ __forceinline__ constexpr int bit(int l, int a) { return (l >> a) & 1; }
 
 // ---------------------------------------------------------------------------------
 // Residual F(u) and (WANT_A) the stage matrix A = M(u)/h - dF/du.
 // ---------------------------------------------------------------------------------
 template <int DIM, bool WANT_A, bool W32>
-__global__ void __launch_bounds__(BS)
-k_assemble(const Phys P, const double *__restrict__ u, const double *__restrict__ Kc,
-           const double *__restrict__ phic, const double *__restrict__ pdc,
-           const double *__restrict__ lamc, const double *__restrict__ pdmin,
-           const double *__restrict__ pv, const uint8_t *__restrict__ dmask,
-           const double *__restrict__ Q, const double inv_h, double *__restrict__ A64,
-           float *__restrict__ A32, double *__restrict__ F) {
+__host__ __device__ __forceinline__ void
+assemble_vertex(const long long v, const Phys &P, const double *__restrict__ u, const double *__restrict__ Kc,
+                const double *__restrict__ phic, const double *__restrict__ pdc,
+                const double *__restrict__ lamc, const double *__restrict__ pdmin,
+                const double *__restrict__ pv, const uint8_t *__restrict__ dmask,
+                const double *__restrict__ Q, const double inv_h, double *__restrict__ A64,
+                float *__restrict__ A32, double *__restrict__ F, double *__restrict__ mst) {
   constexpr int NC = 1 << DIM;
   constexpr int NST = DIM == 3 ? 27 : 9;
   constexpr int CEN = DIM == 3 ? 13 : 4;
-  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= P.N) return;
   const int ix = (int)(v % P.nx);
   const long long tq = v / P.nx;
   const int iy = (int)(tq % P.ny);
@@ -285,6 +290,9 @@ k_assemble(const Phys P, const double *__restrict__ u, const double *__restrict_
   if (WANT_A) {
     acc[CEN][1] += mwS * inv_h;
     acc[CEN][3] += mnS * inv_h;
+    // storage part of the centre block (kept apart for the coarse-level lumping)
+    *reinterpret_cast<double2 *>(mst + 2 * v) =
+        make_double2((m & 1) ? 0.0 : mwS * inv_h, (m & 2) ? 0.0 : mnS * inv_h);
     if (m & 1) {
 #pragma unroll
       for (int o = 0; o < NST; ++o) { acc[o][0] = 0.0; acc[o][1] = 0.0; }
@@ -306,6 +314,19 @@ k_assemble(const Phys P, const double *__restrict__ u, const double *__restrict_
       }
     }
   }
+}
+
+template <int DIM, bool WANT_A, bool W32>
+__global__ void __launch_bounds__(BS)
+k_assemble(const Phys P, const double *__restrict__ u, const double *__restrict__ Kc,
+           const double *__restrict__ phic, const double *__restrict__ pdc,
+           const double *__restrict__ lamc, const double *__restrict__ pdmin,
+           const double *__restrict__ pv, const uint8_t *__restrict__ dmask,
+           const double *__restrict__ Q, const double inv_h, double *__restrict__ A64,
+           float *__restrict__ A32, double *__restrict__ F, double *__restrict__ mst) {
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= P.N) return;
+  assemble_vertex<DIM, WANT_A, W32>(v, P, u, Kc, phic, pdc, lamc, pdmin, pv, dmask, Q, inv_h, A64, A32, F, mst);
 }
 
 __global__ void k_apply_dirichlet(long long N, const uint8_t *__restrict__ m,
@@ -335,10 +356,10 @@ tpf_status launch_residual(tpf_grid *g, const double *u, double *f, hipStream_t 
   TPF_LAUNCH_CHECK();
   if (g->dim == 3)
     k_assemble<3, false, false><<<nb, BS, 0, s>>>(g->P, u, g->K, g->phi, g->pd, g->lam, g->pdmin, g->pv,
-                                                   g->dmask, g->Q, 0.0, nullptr, nullptr, f);
+                                                   g->dmask, g->Q, 0.0, nullptr, nullptr, f, nullptr);
   else
     k_assemble<2, false, false><<<nb, BS, 0, s>>>(g->P, u, g->K, g->phi, g->pd, g->lam, g->pdmin, g->pv,
-                                                   g->dmask, g->Q, 0.0, nullptr, nullptr, f);
+                                                   g->dmask, g->Q, 0.0, nullptr, nullptr, f, nullptr);
   TPF_LAUNCH_CHECK();
   return TPF_OK;
 }
@@ -351,22 +372,24 @@ tpf_status launch_assemble(tpf_grid *g, const double *u0, double h, double *f0, 
   float *A32 = g->lv[0].A32;
   const double ih = 1.0 / h;
   const bool w32 = g->prec == TPF_MIXED;
+  const int ps = prof_begin(g, TPF_K_ASSEMBLE, s);
   if (g->dim == 3) {
     if (w32)
       k_assemble<3, true, true><<<nb, BS, 0, s>>>(g->P, u0, g->K, g->phi, g->pd, g->lam, g->pdmin, g->pv,
-                                                   g->dmask, g->Q, ih, A64, A32, f0);
+                                                   g->dmask, g->Q, ih, A64, A32, f0, g->lv[0].mst);
     else
       k_assemble<3, true, false><<<nb, BS, 0, s>>>(g->P, u0, g->K, g->phi, g->pd, g->lam, g->pdmin, g->pv,
-                                                    g->dmask, g->Q, ih, A64, nullptr, f0);
+                                                    g->dmask, g->Q, ih, A64, nullptr, f0, g->lv[0].mst);
   } else {
     if (w32)
       k_assemble<2, true, true><<<nb, BS, 0, s>>>(g->P, u0, g->K, g->phi, g->pd, g->lam, g->pdmin, g->pv,
-                                                   g->dmask, g->Q, ih, A64, A32, f0);
+                                                   g->dmask, g->Q, ih, A64, A32, f0, g->lv[0].mst);
     else
       k_assemble<2, true, false><<<nb, BS, 0, s>>>(g->P, u0, g->K, g->phi, g->pd, g->lam, g->pdmin, g->pv,
-                                                    g->dmask, g->Q, ih, A64, nullptr, f0);
+                                                    g->dmask, g->Q, ih, A64, nullptr, f0, g->lv[0].mst);
   }
   TPF_LAUNCH_CHECK();
+  prof_end(g, ps, s);
   return TPF_OK;
 }
 

@@ -9,41 +9,10 @@
 // 1-2 KB segment.  Entries for neighbours outside the grid are stored as zeros and
 // never dereference x.  P is per-component (bi/tri)linear interpolation between
 // vertex-halved grids; on the finest level its rows at Dirichlet components are zero.
-#include "tpf_internal.h"
+#include "stencil.h"
 
 namespace tpf {
 namespace {
-
-template <typename T> struct Vec2;
-template <> struct Vec2<double> { using type = double2; };
-template <> struct Vec2<float> { using type = float2; };
-
-template <typename T> struct Blk;
-template <> struct Blk<double> {
-  __device__ static __forceinline__ void load(const double *p, double (&b)[4]) {
-    const double2 a = reinterpret_cast<const double2 *>(p)[0];
-    const double2 c = reinterpret_cast<const double2 *>(p)[1];
-    b[0] = a.x; b[1] = a.y; b[2] = c.x; b[3] = c.y;
-  }
-};
-template <> struct Blk<float> {
-  __device__ static __forceinline__ void load(const float *p, float (&b)[4]) {
-    const float4 a = *reinterpret_cast<const float4 *>(p);
-    b[0] = a.x; b[1] = a.y; b[2] = a.z; b[3] = a.w;
-  }
-};
-
-struct Geo {
-  int nx, ny, nz;
-  long long N;
-};
-
-__device__ __forceinline__ void vcoords(long long v, const Geo &G, int &ix, int &iy, int &iz) {
-  ix = (int)(v % G.nx);
-  const long long t = v / G.nx;
-  iy = (int)(t % G.ny);
-  iz = (int)(t / G.ny);
-}
 
 // y = A x (row-block product) accumulated in the matrix type T for one vertex.
 // Returns (A x)_v; the centre block is copied out for the smoother.
@@ -186,26 +155,25 @@ __global__ void __launch_bounds__(BS) k_resid(const Geo G, const T *__restrict__
   *reinterpret_cast<typename Vec2<T>::type *>(r + 2 * v) = o;
 }
 
-// Restriction bc = P^T rf: gather of the 3^d fine neighbours of vertex 2I with
-// weights (1/2)^{|d|_1}; fine Dirichlet components (finest level) excluded.
+// Restriction bc = P^T rf.  Pressure component: (bi/tri)linear weights
+// (1/2)^{|d|_1} over the 3^d fine neighbours of vertex 2I.  Saturation component:
+// piecewise-constant aggregation, the sum over fine vertices 2I + d, d in {-1, 0}^d.
+// Fine Dirichlet components (finest level) are excluded.
 template <int DIM, typename T>
-__global__ void __launch_bounds__(BS) k_restrict(const Geo F, const Geo C, const T *__restrict__ rf,
-                                                 const uint8_t *__restrict__ fmask, T *__restrict__ bc) {
-  const long long I = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (I >= C.N) return;
+__host__ __device__ __forceinline__ void restrict_vertex(long long I, const Geo &F, const Geo &C,
+                                                        const T *__restrict__ rf,
+                                                        const uint8_t *__restrict__ fmask, T *__restrict__ bc) {
   int cx, cy, cz;
   vcoords(I, C, cx, cy, cz);
   const int fx = 2 * cx, fy = 2 * cy, fz = DIM == 3 ? 2 * cz : 0;
   T s0 = 0, s1 = 0;
-#pragma unroll
   for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0); ++dz)
-#pragma unroll
     for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
       for (int dx = -1; dx <= 1; ++dx) {
         const int x = fx + dx, y = fy + dy, z = fz + dz;
         if (x < 0 || y < 0 || z < 0 || x >= F.nx || y >= F.ny || z >= F.nz) continue;
-        const T w = (T)((dx ? 0.5 : 1.0) * (dy ? 0.5 : 1.0) * (dz ? 0.5 : 1.0));
+        const T wl = (T)((dx ? 0.5 : 1.0) * (dy ? 0.5 : 1.0) * (dz ? 0.5 : 1.0));
+        const T wc = (dx <= 0 && dy <= 0 && dz <= 0) ? (T)1 : (T)0;
         const long long i = x + (long long)F.nx * (y + (long long)F.ny * z);
         const auto rv = *reinterpret_cast<const typename Vec2<T>::type *>(rf + 2 * i);
         T r0 = rv.x, r1 = rv.y;
@@ -214,8 +182,8 @@ __global__ void __launch_bounds__(BS) k_restrict(const Geo F, const Geo C, const
           if (m & 1) r0 = 0;
           if (m & 2) r1 = 0;
         }
-        s0 += w * r0;
-        s1 += w * r1;
+        s0 += wl * r0;
+        s1 += wc * r1;
       }
   typename Vec2<T>::type o;
   o.x = s0;
@@ -223,23 +191,28 @@ __global__ void __launch_bounds__(BS) k_restrict(const Geo F, const Geo C, const
   *reinterpret_cast<typename Vec2<T>::type *>(bc + 2 * I) = o;
 }
 
-// Prolongation and correction xf += P ec.
 template <int DIM, typename T>
-__global__ void __launch_bounds__(BS) k_prolong(const Geo F, const Geo C, const T *__restrict__ ec,
-                                                const uint8_t *__restrict__ fmask, T *__restrict__ xf) {
-  const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
-  const long long i = (long long)blk * BS + threadIdx.x;
-  if (i >= F.N) return;
+__global__ void __launch_bounds__(BS) k_restrict(const Geo F, const Geo C, const T *__restrict__ rf,
+                                                 const uint8_t *__restrict__ fmask, T *__restrict__ bc) {
+  const long long I = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= C.N) return;
+  restrict_vertex<DIM, T>(I, F, C, rf, fmask, bc);
+}
+
+// Prolongation and correction xf += P ec: linear interpolation of the pressure
+// correction, injection from the aggregating coarse vertex ((i + 1) / 2 per axis)
+// of the saturation correction.
+template <int DIM, typename T>
+__host__ __device__ __forceinline__ void prolong_vertex(long long i, const Geo &F, const Geo &C,
+                                                       const T *__restrict__ ec,
+                                                       const uint8_t *__restrict__ fmask, T *__restrict__ xf) {
   int x, y, z;
   vcoords(i, F, x, y, z);
   const int xl = x >> 1, xh = (x + 1) >> 1, yl = y >> 1, yh = (y + 1) >> 1;
   const int zl = DIM == 3 ? z >> 1 : 0, zh = DIM == 3 ? (z + 1) >> 1 : 0;
-  T s0 = 0, s1 = 0;
-#pragma unroll
+  T s0 = 0;
   for (int kz = 0; kz < (DIM == 3 ? 2 : 1); ++kz)
-#pragma unroll
     for (int ky = 0; ky < 2; ++ky)
-#pragma unroll
       for (int kx = 0; kx < 2; ++kx) {
         const int X = kx ? xh : xl, Y = ky ? yh : yl, Z = kz ? zh : zl;
         // each axis contributes weight 1 (even index: both picks coincide, count once) or 1/2
@@ -249,10 +222,10 @@ __global__ void __launch_bounds__(BS) k_prolong(const Geo F, const Geo C, const 
         const T w = wx * wy * wz;
         if (w == (T)0) continue;
         const long long J = X + (long long)C.nx * (Y + (long long)C.ny * Z);
-        const auto ev = *reinterpret_cast<const typename Vec2<T>::type *>(ec + 2 * J);
-        s0 += w * ev.x;
-        s1 += w * ev.y;
+        s0 += w * ec[2 * J];
       }
+  const long long Ja = xh + (long long)C.nx * (yh + (long long)C.ny * zh);
+  T s1 = ec[2 * Ja + 1];
   if (fmask) {
     const uint8_t m = fmask[i];
     if (m & 1) s0 = 0;
@@ -264,91 +237,13 @@ __global__ void __launch_bounds__(BS) k_prolong(const Geo F, const Geo C, const 
   *reinterpret_cast<typename Vec2<T>::type *>(xf + 2 * i) = xv;
 }
 
-// Galerkin coarse operator A_c = P^T A_f P, one thread per coarse vertex I.
-// Fine row i = 2I + d, fine column j = i + o; per axis s = d + o decides the coarse
-// columns J = I + O carrying P(j, J): s even -> O = s/2 (weight 1), s odd ->
-// O = (s-1)/2 and (s+1)/2 (weight 1/2 each).  All indices are compile-time after
-// unrolling, so the 27 (9) coarse blocks stay in registers.
-template <int DIM, bool MASK>
-__global__ void __launch_bounds__(128) k_rap(const Geo F, const Geo C, const double *__restrict__ Af,
-                                             const uint8_t *__restrict__ fmask, double *__restrict__ Ac,
-                                             float *__restrict__ Ac32) {
-  constexpr int NST = DIM == 3 ? 27 : 9;
-  const long long I = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (I >= C.N) return;
-  int cx, cy, cz;
-  vcoords(I, C, cx, cy, cz);
-  double acc[NST][4];
-#pragma unroll
-  for (int o = 0; o < NST; ++o)
-#pragma unroll
-    for (int e = 0; e < 4; ++e) acc[o][e] = 0.0;
-  const long long sy = F.nx, sz = (long long)F.nx * F.ny;
-#pragma unroll
-  for (int dd = 0; dd < NST; ++dd) {
-    const int dx = dd % 3 - 1, dy = (dd / 3) % 3 - 1, dz = DIM == 3 ? dd / 9 - 1 : 0;
-    const int fx = 2 * cx + dx, fy = 2 * cy + dy, fz = (DIM == 3 ? 2 * cz : 0) + dz;
-    if (fx < 0 || fy < 0 || fz < 0 || fx >= F.nx || fy >= F.ny || fz >= F.nz) continue;
-    const long long i = fx + sy * fy + sz * fz;
-    const double wrow = (dx ? 0.5 : 1.0) * (dy ? 0.5 : 1.0) * (dz ? 0.5 : 1.0);
-    double wr0 = wrow, wr1 = wrow;
-    if (MASK) {
-      const uint8_t m = fmask[i];
-      if (m & 1) wr0 = 0.0;
-      if (m & 2) wr1 = 0.0;
-    }
-    const bool xm = fx > 0, xp = fx < F.nx - 1, ym = fy > 0, yp = fy < F.ny - 1;
-    const bool zm = DIM == 3 && fz > 0, zp = DIM == 3 && fz < F.nz - 1;
-#pragma unroll
-    for (int oo = 0; oo < NST; ++oo) {
-      const int ox = oo % 3 - 1, oy = (oo / 3) % 3 - 1, oz = DIM == 3 ? oo / 9 - 1 : 0;
-      const bool ok = (ox < 0 ? xm : (ox > 0 ? xp : true)) && (oy < 0 ? ym : (oy > 0 ? yp : true)) &&
-                      (oz < 0 ? zm : (oz > 0 ? zp : true));
-      if (!ok) continue;
-      const double2 b01 = reinterpret_cast<const double2 *>(Af + ((long long)oo * F.N + i) * 4)[0];
-      const double2 b23 = reinterpret_cast<const double2 *>(Af + ((long long)oo * F.N + i) * 4)[1];
-      double kc0 = 1.0, kc1 = 1.0;
-      if (MASK) {
-        const uint8_t m = fmask[i + ox + sy * oy + sz * oz];
-        if (m & 1) kc0 = 0.0;
-        if (m & 2) kc1 = 0.0;
-      }
-      const double e0 = wr0 * b01.x * kc0, e1 = wr0 * b01.y * kc1;
-      const double e2 = wr1 * b23.x * kc0, e3 = wr1 * b23.y * kc1;
-      const int sx_ = dx + ox, sy_ = dy + oy, sz_ = dz + oz;
-#pragma unroll
-      for (int tz = 0; tz < (DIM == 3 ? 2 : 1); ++tz)
-#pragma unroll
-        for (int ty = 0; ty < 2; ++ty)
-#pragma unroll
-          for (int tx = 0; tx < 2; ++tx) {
-            // per axis: even s -> single target (t = 0 only), odd s -> two targets
-            const bool vx = (sx_ & 1) || tx == 0;
-            const bool vy = (sy_ & 1) || ty == 0;
-            const bool vz = DIM != 3 || (sz_ & 1) || tz == 0;
-            if (!(vx && vy && vz)) continue;
-            const int Ox = (sx_ & 1) ? ((sx_ - 1) / 2 + tx) : sx_ / 2;
-            const int Oy = (sy_ & 1) ? ((sy_ - 1) / 2 + ty) : sy_ / 2;
-            const int Oz = DIM == 3 ? ((sz_ & 1) ? ((sz_ - 1) / 2 + tz) : sz_ / 2) : 0;
-            const double w = ((sx_ & 1) ? 0.5 : 1.0) * ((sy_ & 1) ? 0.5 : 1.0) *
-                             (DIM == 3 ? ((sz_ & 1) ? 0.5 : 1.0) : 1.0);
-            const int T = DIM == 3 ? (Ox + 1) + 3 * (Oy + 1) + 9 * (Oz + 1) : (Ox + 1) + 3 * (Oy + 1);
-            acc[T][0] += w * e0;
-            acc[T][1] += w * e1;
-            acc[T][2] += w * e2;
-            acc[T][3] += w * e3;
-          }
-    }
-  }
-#pragma unroll
-  for (int o = 0; o < NST; ++o) {
-    double *dst = Ac + ((long long)o * C.N + I) * 4;
-    reinterpret_cast<double2 *>(dst)[0] = make_double2(acc[o][0], acc[o][1]);
-    reinterpret_cast<double2 *>(dst)[1] = make_double2(acc[o][2], acc[o][3]);
-    if (Ac32)
-      *reinterpret_cast<float4 *>(Ac32 + ((long long)o * C.N + I) * 4) =
-          make_float4((float)acc[o][0], (float)acc[o][1], (float)acc[o][2], (float)acc[o][3]);
-  }
+template <int DIM, typename T>
+__global__ void __launch_bounds__(BS) k_prolong(const Geo F, const Geo C, const T *__restrict__ ec,
+                                                const uint8_t *__restrict__ fmask, T *__restrict__ xf) {
+  const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
+  const long long i = (long long)blk * BS + threadIdx.x;
+  if (i >= F.N) return;
+  prolong_vertex<DIM, T>(i, F, C, ec, fmask, xf);
 }
 
 // Dense coarsest matrix (column-major n x n, n = 2 N) from the stencil rows.
@@ -498,29 +393,39 @@ tpf_status vcycle_t(tpf_grid *g, const double *bin, double *xout, hipStream_t s)
     const Geo G = geo(lv);
     const unsigned nb = blocks_for(lv.N);
     T *X = reinterpret_cast<T *>(lv.x), *Y = reinterpret_cast<T *>(lv.y);
+    int ps = prof_begin(g, l == 0 ? TPF_K_SMOOTH0_FIRST : TPF_K_COARSE_LEVELS, s);
     k_jacobi<DIM, T, T, true><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], nullptr, X, om);
     TPF_LAUNCH_CHECK();
+    prof_end(g, ps, s);
     for (int k = 1; k < g->nu_pre; ++k) {
+      ps = prof_begin(g, l == 0 ? TPF_K_SMOOTH0 : TPF_K_COARSE_LEVELS, s);
       k_jacobi<DIM, T, T, false><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, Y, om);
       TPF_LAUNCH_CHECK();
+      prof_end(g, ps, s);
       T *t = X; X = Y; Y = t;
     }
     cur[l] = X;
     T *R = reinterpret_cast<T *>(lv.r);
+    ps = prof_begin(g, l == 0 ? TPF_K_RESID0 : TPF_K_COARSE_LEVELS, s);
     k_resid<DIM, T><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, R);
     TPF_LAUNCH_CHECK();
+    prof_end(g, ps, s);
     Level &lc = g->lv[l + 1];
     T *bc = reinterpret_cast<T *>(lc.b);
+    ps = prof_begin(g, l == 0 ? TPF_K_TRANSFER0 : TPF_K_COARSE_LEVELS, s);
     k_restrict<DIM, T><<<blocks_for(lc.N), BS, 0, s>>>(G, geo(lc), R, l == 0 ? g->dmask : nullptr, bc);
     TPF_LAUNCH_CHECK();
+    prof_end(g, ps, s);
     bl[l + 1] = bc;
   }
   // coarsest level
   {
     Level &lc = g->lv[L - 1];
     T *X = (L == 1 && sizeof(T) == sizeof(double)) ? reinterpret_cast<T *>(xout) : reinterpret_cast<T *>(lc.x);
+    const int ps = prof_begin(g, TPF_K_COARSE_LEVELS, s);
     k_coarse_solve<T><<<(g->nc + 63) / 64, 64, 0, s>>>(g->ainv, g->nc, bl[L - 1], X);
     TPF_LAUNCH_CHECK();
+    prof_end(g, ps, s);
     cur[L - 1] = X;
     if (L == 1) {
       if (sizeof(T) != sizeof(double)) {
@@ -536,18 +441,23 @@ tpf_status vcycle_t(tpf_grid *g, const double *bin, double *xout, hipStream_t s)
     const unsigned nb = blocks_for(lv.N);
     T *X = cur[l];
     T *Y = (X == reinterpret_cast<T *>(lv.x)) ? reinterpret_cast<T *>(lv.y) : reinterpret_cast<T *>(lv.x);
+    int ps = prof_begin(g, l == 0 ? TPF_K_TRANSFER0 : TPF_K_COARSE_LEVELS, s);
     k_prolong<DIM, T><<<nb, BS, 0, s>>>(G, geo(g->lv[l + 1]), cur[l + 1], l == 0 ? g->dmask : nullptr, X);
     TPF_LAUNCH_CHECK();
+    prof_end(g, ps, s);
     const int nu = g->nu_post;
     for (int k = 0; k < nu; ++k) {
+      ps = prof_begin(g, l == 0 ? TPF_K_SMOOTH0 : TPF_K_COARSE_LEVELS, s);
       if (l == 0 && k == nu - 1) {
         k_jacobi<DIM, T, double, false><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, xout, om);
         TPF_LAUNCH_CHECK();
+        prof_end(g, ps, s);
         X = nullptr;
         break;
       }
       k_jacobi<DIM, T, T, false><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, Y, om);
       TPF_LAUNCH_CHECK();
+      prof_end(g, ps, s);
       T *t = X; X = Y; Y = t;
     }
     if (l == 0 && X != nullptr) {  // nu_post == 0
@@ -562,16 +472,18 @@ tpf_status vcycle_t(tpf_grid *g, const double *bin, double *xout, hipStream_t s)
 template <int DIM>
 tpf_status hierarchy_t(tpf_grid *g, hipStream_t s) {
   for (int l = 0; l + 1 < g->L; ++l) {
-    Level &f = g->lv[l], &c = g->lv[l + 1];
+    const Level &f = g->lv[l];
+    Level &c = g->lv[l + 1];
     float *c32 = g->prec == TPF_MIXED ? c.A32 : nullptr;
-    if (l == 0)
-      k_rap<DIM, true><<<blocks_for(c.N, 128), 128, 0, s>>>(geo(f), geo(c), f.A64, g->dmask, c.A64, c32);
-    else
-      k_rap<DIM, false><<<blocks_for(c.N, 128), 128, 0, s>>>(geo(f), geo(c), f.A64, nullptr, c.A64, c32);
-    TPF_LAUNCH_CHECK();
+    const int ps = prof_begin(g, TPF_K_RAP, s);
+    const tpf_status st = launch_rap(g->dim, l == 0, f.n, f.N, c.n, c.N, f.A64, l == 0 ? g->dmask : nullptr, f.mst,
+                                     c.A64, c32, c.mst, s);
+    if (st != TPF_OK) return st;
+    prof_end(g, ps, s);
   }
   Level &lc = g->lv[g->L - 1];
   const int n = g->nc;
+  const int pl = prof_begin(g, TPF_K_COARSE_LU, s);
   k_zero<<<256, BS, 0, s>>>(g->lu, (long long)n * n);
   TPF_LAUNCH_CHECK();
   constexpr int NST = DIM == 3 ? 27 : 9;
@@ -581,14 +493,17 @@ tpf_status hierarchy_t(tpf_grid *g, hipStream_t s) {
   TPF_LAUNCH_CHECK();
   k_lu_inverse<<<n, 64, (size_t)n * sizeof(double), s>>>(g->lu, g->piv, n, g->ainv);
   TPF_LAUNCH_CHECK();
+  prof_end(g, pl, s);
   return TPF_OK;
 }
 
 template <int DIM>
 tpf_status spmv_t(tpf_grid *g, int level, const double *x, double *y, hipStream_t s) {
   const Level &lv = g->lv[level];
+  const int ps = prof_begin(g, level == 0 ? TPF_K_SPMV64 : TPF_K_COARSE_LEVELS, s);
   k_spmv64<DIM, 0><<<blocks_for(lv.N), BS, 0, s>>>(geo(lv), lv.A64, x, y, nullptr, nullptr);
   TPF_LAUNCH_CHECK();
+  prof_end(g, ps, s);
   return TPF_OK;
 }
 
@@ -615,6 +530,7 @@ tpf_status spmv64_mode(tpf_grid *g, int mode, const double *x, double *y, const 
   const unsigned nb = blocks_for(lv.N);
   *nblk_out = nb;
   const Geo G = geo(lv);
+  const int ps = prof_begin(g, TPF_K_SPMV64, s);
   if (g->dim == 3) {
     switch (mode) {
       case 1: k_spmv64<3, 1><<<nb, BS, 0, s>>>(G, lv.A64, x, y, d0, part); break;
@@ -631,6 +547,7 @@ tpf_status spmv64_mode(tpf_grid *g, int mode, const double *x, double *y, const 
     }
   }
   TPF_LAUNCH_CHECK();
+  prof_end(g, ps, s);
   return TPF_OK;
 }
 

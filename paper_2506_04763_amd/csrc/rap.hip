@@ -1,0 +1,169 @@
+// Coarse-level operators of the geometric multigrid hierarchy (gfx950).
+//
+//   A_c = P^T (A_f - S_f) P + S_c,   S_c = lumped P^T S_f P on the S_n column,
+//
+// S_f the storage part of the fine centre blocks.  P interpolates each component
+// separately: (bi/tri)linearly for the pressure, by piecewise-constant aggregation
+// (coarse I <- fine 2I-1, 2I per axis) for the saturation; on the finest level the
+// rows of P at Dirichlet components are zero.  One thread per coarse vertex I walks
+// the coarse offsets O; for each it sums, per axis, the (d, o) pairs with fine row
+// i = 2I + d, fine column j = i + o that carry a non-zero weight (tables below), so
+// only 4 accumulators are live at a time.  A coarse unknown whose prolongation
+// column is empty (an aggregate made only of Dirichlet components) is decoupled
+// and gets a unit diagonal.
+#include "stencil.h"
+
+namespace tpf {
+namespace {
+
+// Per axis and coarse offset O in {-1, 0, 1}: every (fine-row offset d, fine-column
+// offset o) with j = 2I + d + o interpolating from J = I + O, and the linear
+// weight P(j, J).  The aggregation weights are non-zero on a subset of these pairs.
+struct AxisTerms {
+  int n;
+  int d[7], o[7];
+  double w[7];
+};
+__host__ __device__ __forceinline__ AxisTerms axis_terms(int O) {
+  if (O < 0) return AxisTerms{3, {-1, -1, 0}, {-1, 0, -1}, {1.0, 0.5, 0.5}};
+  if (O > 0) return AxisTerms{3, {0, 1, 1}, {1, 0, 1}, {0.5, 0.5, 1.0}};
+  return AxisTerms{7, {-1, 0, -1, 0, 1, 0, 1}, {0, -1, 1, 0, -1, 1, 0}, {0.5, 0.5, 1.0, 1.0, 1.0, 0.5, 0.5}};
+}
+__host__ __device__ __forceinline__ AxisTerms axis_flat() { return AxisTerms{1, {0}, {0}, {1.0}}; }
+
+// 1-D weights: linear row weight P(2I + d, I), aggregation row weight, aggregation
+// column weight P_agg(j, J) for s = j - 2I and O = J - I.
+__host__ __device__ __forceinline__ double lin_row(int d) { return d ? 0.5 : 1.0; }
+__host__ __device__ __forceinline__ double agg_row(int d) { return d <= 0 ? 1.0 : 0.0; }
+__host__ __device__ __forceinline__ double agg_col(int s, int O) { return (s == 2 * O - 1 || s == 2 * O) ? 1.0 : 0.0; }
+
+template <int DIM, bool MASK>
+__host__ __device__ __forceinline__ void rap_vertex(long long I, const Geo &F, const Geo &C,
+                                                   const double *__restrict__ Af,
+                                                   const uint8_t *__restrict__ fmask,
+                                                   const double *__restrict__ mf, double *__restrict__ Ac,
+                                                   float *__restrict__ Ac32, double *__restrict__ mc) {
+  constexpr int NST = DIM == 3 ? 27 : 9;
+  constexpr int CEN = DIM == 3 ? 13 : 4;
+  int cx, cy, cz;
+  vcoords(I, C, cx, cy, cz);
+  const long long sy = F.nx, sz = (long long)F.nx * F.ny;
+  // lumped coarse storage: sum_i P_r(i, I) keep_S(i) S_f(i, r); and whether the
+  // prolongation columns of (I, p) and (I, S) carry any weight
+  double ms0 = 0.0, ms1 = 0.0;
+  bool live0 = false, live1 = false;
+  for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0); ++dz)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int fx = 2 * cx + dx, fy = 2 * cy + dy, fz = (DIM == 3 ? 2 * cz : 0) + dz;
+        if (fx < 0 || fy < 0 || fz < 0 || fx >= F.nx || fy >= F.ny || fz >= F.nz) continue;
+        const long long i = fx + sy * fy + sz * fz;
+        const double wl = lin_row(dx) * lin_row(dy) * (DIM == 3 ? lin_row(dz) : 1.0);
+        const double wa = agg_row(dx) * agg_row(dy) * (DIM == 3 ? agg_row(dz) : 1.0);
+        double k0 = 1.0, k1 = 1.0;
+        if (MASK) {
+          const uint8_t m = fmask[i];
+          if (m & 2) { k0 = 0.0; k1 = 0.0; }  // keep_S(i) = 0: no lumped storage at i
+          if (m & 1) k0 = 0.0;                 // keep_p(i) = 0
+          if (!(m & 1)) live0 = true;
+          if (!(m & 2) && wa != 0.0) live1 = true;
+        } else {
+          live0 = true;
+          if (wa != 0.0) live1 = true;
+        }
+        ms0 += wl * k0 * mf[2 * i];
+        ms1 += wa * k1 * mf[2 * i + 1];
+      }
+  for (int T = 0; T < NST; ++T) {
+    const int Ox = T % 3 - 1, Oy = (T / 3) % 3 - 1, Oz = DIM == 3 ? T / 9 - 1 : 0;
+    const AxisTerms tx = axis_terms(Ox), ty = axis_terms(Oy);
+    const AxisTerms tz = DIM == 3 ? axis_terms(Oz) : axis_flat();
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    for (int kz = 0; kz < tz.n; ++kz) {
+      const int fz = (DIM == 3 ? 2 * cz : 0) + tz.d[kz], jz = fz + tz.o[kz];
+      if (fz < 0 || fz >= F.nz || jz < 0 || jz >= F.nz) continue;
+      const double rz_l = DIM == 3 ? lin_row(tz.d[kz]) : 1.0, rz_a = DIM == 3 ? agg_row(tz.d[kz]) : 1.0;
+      const double cz_a = DIM == 3 ? agg_col(tz.d[kz] + tz.o[kz], Oz) : 1.0;
+      for (int ky = 0; ky < ty.n; ++ky) {
+        const int fy = 2 * cy + ty.d[ky], jy = fy + ty.o[ky];
+        if (fy < 0 || fy >= F.ny || jy < 0 || jy >= F.ny) continue;
+        const double ry_l = lin_row(ty.d[ky]), ry_a = agg_row(ty.d[ky]);
+        const double cy_a = agg_col(ty.d[ky] + ty.o[ky], Oy);
+        for (int kx = 0; kx < tx.n; ++kx) {
+          const int fx = 2 * cx + tx.d[kx], jx = fx + tx.o[kx];
+          if (fx < 0 || fx >= F.nx || jx < 0 || jx >= F.nx) continue;
+          const double rl = lin_row(tx.d[kx]) * ry_l * rz_l;          // P_p(i, I)
+          const double ra = agg_row(tx.d[kx]) * ry_a * rz_a;          // P_S(i, I)
+          const double cl = tx.w[kx] * ty.w[ky] * tz.w[kz];          // P_p(j, J)
+          const double ca = agg_col(tx.d[kx] + tx.o[kx], Ox) * cy_a * cz_a;  // P_S(j, J)
+          const long long i = fx + sy * fy + sz * fz;
+          const long long j = jx + sy * jy + sz * jz;
+          const int oo = DIM == 3 ? (tx.o[kx] + 1) + 3 * (ty.o[ky] + 1) + 9 * (tz.o[kz] + 1)
+                                  : (tx.o[kx] + 1) + 3 * (ty.o[ky] + 1);
+          const double2 *bp = reinterpret_cast<const double2 *>(Af + ((long long)oo * F.N + i) * 4);
+          const double2 b01 = bp[0], b23 = bp[1];
+          double e1 = b01.y, e3 = b23.y;
+          if (oo == CEN) {  // flux part only: remove the fine storage
+            e1 -= mf[2 * i];
+            e3 -= mf[2 * i + 1];
+          }
+          double r0 = rl, r1 = ra, c0 = cl, c1 = ca;
+          if (MASK) {
+            const uint8_t mi = fmask[i], mj = fmask[j];
+            if (mi & 1) r0 = 0.0;
+            if (mi & 2) r1 = 0.0;
+            if (mj & 1) c0 = 0.0;
+            if (mj & 2) c1 = 0.0;
+          }
+          a0 += r0 * b01.x * c0;
+          a1 += r0 * e1 * c1;
+          a2 += r1 * b23.x * c0;
+          a3 += r1 * e3 * c1;
+        }
+      }
+    }
+    if (T == CEN) {
+      a1 += ms0;
+      a3 += ms1;
+      if (!live0) a0 += 1.0;
+      if (!live1) a3 += 1.0;
+    }
+    double *dst = Ac + ((long long)T * C.N + I) * 4;
+    reinterpret_cast<double2 *>(dst)[0] = make_double2(a0, a1);
+    reinterpret_cast<double2 *>(dst)[1] = make_double2(a2, a3);
+    if (Ac32)
+      *reinterpret_cast<float4 *>(Ac32 + ((long long)T * C.N + I) * 4) =
+          make_float4((float)a0, (float)a1, (float)a2, (float)a3);
+  }
+  *reinterpret_cast<double2 *>(mc + 2 * I) = make_double2(ms0, ms1);
+}
+
+template <int DIM, bool MASK>
+__global__ void __launch_bounds__(BS) k_rap(const Geo F, const Geo C, const double *__restrict__ Af,
+                                            const uint8_t *__restrict__ fmask, const double *__restrict__ mf,
+                                            double *__restrict__ Ac, float *__restrict__ Ac32,
+                                            double *__restrict__ mc) {
+  const long long I = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= C.N) return;
+  rap_vertex<DIM, MASK>(I, F, C, Af, fmask, mf, Ac, Ac32, mc);
+}
+
+}  // namespace
+
+tpf_status launch_rap(int dim, bool mask, const int nf[3], long long Nf, const int nc[3], long long Nc,
+                      const double *Af, const uint8_t *fmask, const double *mf, double *Ac, float *Ac32,
+                      double *mc, hipStream_t s) {
+  const Geo F = geo_of(nf, Nf), C = geo_of(nc, Nc);
+  const unsigned nb = blocks_for(Nc);
+  if (dim == 3) {
+    if (mask) k_rap<3, true><<<nb, BS, 0, s>>>(F, C, Af, fmask, mf, Ac, Ac32, mc);
+    else k_rap<3, false><<<nb, BS, 0, s>>>(F, C, Af, fmask, mf, Ac, Ac32, mc);
+  } else {
+    if (mask) k_rap<2, true><<<nb, BS, 0, s>>>(F, C, Af, fmask, mf, Ac, Ac32, mc);
+    else k_rap<2, false><<<nb, BS, 0, s>>>(F, C, Af, fmask, mf, Ac, Ac32, mc);
+  }
+  TPF_LAUNCH_CHECK();
+  return TPF_OK;
+}
+
+}  // namespace tpf

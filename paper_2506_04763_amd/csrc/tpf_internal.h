@@ -46,11 +46,19 @@ struct Patches {
   PatchDev p[TPF_MAX_PATCHES];
 };
 
+// Event timer of selected launch classes (host state only).
+struct Prof {
+  int active = 0, cap = 0, used = 0;
+  hipEvent_t *ev = nullptr;  // 2 * cap
+  int *cls = nullptr;        // cap
+};
+
 struct Level {
   int n[3];
   long long N;
   double *A64;  // [nst][N][4]
   float *A32;   // [nst][N][4] (mixed precision only)
+  double *mst;  // [N][2] storage part of the centre block, (w,S) and (n,S) entries
   void *x, *y, *b, *r;  // level vectors, 2N entries of the level type
 };
 
@@ -84,7 +92,23 @@ struct tpf_grid {
   bool has_f0;
   size_t bytes;
   int device;
+  tpf::Prof prof;
 };
+
+namespace tpf {
+// Records the start event of a timed launch of class `c`; returns the slot or -1.
+inline int prof_begin(tpf_grid *g, int c, hipStream_t s) {
+  Prof &p = g->prof;
+  if (!p.active || p.used >= p.cap) return -1;
+  const int i = p.used++;
+  p.cls[i] = c;
+  if (hipEventRecord(p.ev[2 * i], s) != hipSuccess) return -1;
+  return i;
+}
+inline void prof_end(tpf_grid *g, int slot, hipStream_t s) {
+  if (slot >= 0) (void)hipEventRecord(g->prof.ev[2 * slot + 1], s);
+}
+}  // namespace tpf
 
 namespace tpf {
 

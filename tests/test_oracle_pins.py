@@ -308,9 +308,14 @@ def test_prolongation_reproduces_linear_functions():
                              indexing="ij")
     zf, yf, xf = np.meshgrid(np.arange(n[2]) * 1.0, np.arange(n[1]) * 1.0, np.arange(n[0]) * 1.0,
                              indexing="ij")
-    lin_c = np.stack([3 * xc - yc + 2 * zc + 1, xc + 5], axis=-1).ravel()
-    lin_f = np.stack([3 * xf - yf + 2 * zf + 1, xf + 5], axis=-1).ravel()
+    # pressure: (tri)linear interpolation reproduces linear functions; saturation:
+    # aggregation reproduces constants and maps fine vertex i to coarse (i + 1) // 2
+    lin_c = np.stack([3 * xc - yc + 2 * zc + 1, np.full_like(xc, 7.0)], axis=-1).ravel()
+    lin_f = np.stack([3 * xf - yf + 2 * zf + 1, np.full_like(xf, 7.0)], axis=-1).ravel()
     np.testing.assert_allclose(P @ lin_c, lin_f, rtol=0, atol=1e-13)
+    PS = P[1::2, 1::2]
+    assert np.all(np.asarray(PS.sum(axis=1)).ravel() == 1.0)
+    assert PS.sum() == np.prod(n)
 
 
 def test_galerkin_and_two_grid_contraction():
@@ -320,8 +325,21 @@ def test_galerkin_and_two_grid_contraction():
     A = st.assemble(u.ravel(), 32.0)
     H = st.H
     P = H.P[0].toarray()
-    np.testing.assert_allclose(H.A[1].toarray(), P.T @ A.toarray() @ P,
+    S0 = H.S[0].toarray()
+    # flux part: exact Galerkin product of the fine flux part, plus a unit diagonal on
+    # coarse unknowns whose prolongation column is empty (all-Dirichlet aggregates)
+    empty = np.abs(P).sum(axis=0) == 0
+    assert empty.sum() > 0 and np.all(np.nonzero(empty)[0] % 2 == 1)
+    np.testing.assert_allclose((H.A[1] - H.S[1]).toarray(), P.T @ (A.toarray() - S0) @ P + np.diag(empty * 1.0),
                                rtol=0, atol=1e-12 * np.abs(A).max())
+    # lumped coarse storage: diagonal blocks, S_n column only, total storage conserved
+    Sc = H.S[1].toarray()
+    off = Sc.copy()
+    for i in range(0, Sc.shape[0], 2):
+        off[i:i + 2, i + 1] = 0.0
+    assert np.all(off == 0.0)
+    keep_cols = np.abs(P).sum(axis=1) > 0
+    assert Sc.sum() == pytest.approx(S0[keep_cols][:, keep_cols].sum(), rel=1e-12)
     # two-grid iteration with exact coarse solve contracts the error
     xs = np.random.default_rng(0).standard_normal(A.shape[0])
     b = A @ xs
@@ -439,3 +457,21 @@ def test_integration_point_exact_for_bilinear_pressure(dim):
     # inflow into b_0 = K/mu rho * (int_{x-face} dp/dx + int_{y-face} dp/dy); z-face: dp/dz = 0
     expect = 1000.0 * 2e-11 / 1e-3 * 1e3 * (dy ** 2 / 8 + dx ** 2 / 8) * depth
     assert F[0, 0] == pytest.approx(expect, rel=1e-12)
+
+
+def test_vcycle_is_a_contraction_on_a_heterogeneous_cube():
+    """sigma_lnK = 2 on 33^3: the V(2,2) block-Jacobi cycle with lumped coarse storage
+    is a convergent stationary iteration (the plain Galerkin product is not: its
+    coarse storage blocks push the Jacobi spectrum past 2/omega)."""
+    scn = W.cube_3d(33, 2.0, 3, levels=4)
+    st = ST.Stage(scn)
+    A = st.assemble(scn.u0.ravel(), 32.0)
+    xs = np.random.default_rng(0).standard_normal(A.shape[0])
+    b = A @ xs
+    x = np.zeros_like(b)
+    res = []
+    for _ in range(6):
+        x = x + st.H.vcycle(b - A @ x)
+        res.append(np.linalg.norm(b - A @ x) / np.linalg.norm(b))
+    assert all(res[i + 1] < res[i] for i in range(5))
+    assert res[-1] < 1e-7
