@@ -217,7 +217,7 @@ tpf_status tpf_spmv(tpf_grid *g, int32_t level, const double *x, double *y, tpf_
 /* x = one V-cycle applied to b (the preconditioner of solve_stage). */
 tpf_status tpf_precondition(tpf_grid *g, const double *b, double *x, tpf_stream stream);
 
-/* Copies the inverse of the coarsest matrix (column-major, double[nc*nc],
+/* Copies the inverse of the coarsest matrix (row-major, double[nc*nc],
  * nc = 2 N_coarsest) to dst (device). */
 tpf_status tpf_copy_coarse_inverse(tpf_grid *g, double *dst, tpf_stream stream);
 

@@ -232,7 +232,7 @@ class Grid:
         nc = 2 * n[0] * n[1] * n[2]
         out = self.torch.empty(nc * nc, dtype=self.torch.float64, device=self.device)
         L.check(self.lib.tpf_copy_coarse_inverse(self.handle, _ptr(out), self._sptr()), "tpf_copy_coarse_inverse")
-        return out.reshape(nc, nc).t()  # column-major storage
+        return out.reshape(nc, nc)  # row-major storage
 
     def profile_begin(self, max_launches=65536):
         L.check(self.lib.tpf_profile_begin(self.handle, int(max_launches)), "tpf_profile_begin")

@@ -14,7 +14,7 @@ LIB = os.path.join(HERE, "libtpf.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["rap.hip", "assemble.hip", "mg.hip", "krylov.hip", "limex.hip", "api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wall", "-Wno-unused-function",
+FLAGS = ["-O3", "-std=c++20", "-fPIC", "--offload-arch=gfx950", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-I", INCLUDE, "-I", CSRC]
 
 

@@ -1,13 +1,16 @@
 // Box-method residual and stage-matrix assembly on structured Q1 grids (gfx950).
 //
-// One thread per vertex gathers the contributions of the 2^d cells around it (no
-// atomics, deterministic).  For every cell it evaluates, at the cell's corners, the
+// Vertex-centric gather (no atomics, deterministic): the thread(s) of a vertex visit
+// the 2^d cells around it.  For every cell they evaluate, at the cell's corners, the
 // sub-control-volume saturation of the p_dmin interface condition (Eq. hSw) and the
 // element-local capillary pressure, then the fluxes through the d sub-control-volume
-// faces incident to its vertex (Section 3.1, Eqs. dsW/dpN; upwinding Section 3.2;
+// faces incident to the vertex (Section 3.1, Eqs. dsW/dpN; upwinding Section 3.2;
 // barrier on the non-wetting mobility only, Eqs. krn_ip/krw_ip) with their exact
-// derivatives.  The row is kept in registers and written once as 2x2 blocks in the
-// [offset][vertex][4] layout (coalesced 32-byte stores per lane).
+// derivatives.  The row is accumulated in registers and written once as 2x2 blocks in
+// the [offset][vertex][4] layout (coalesced 32-byte stores per lane).  In 3D the
+// matrix kernel splits each vertex over two threads by the z half of its cells (18
+// stencil slots each) and adds the shared dz = 0 plane through LDS in a fixed order,
+// which keeps the accumulators in registers.
 //
 // Discretisation choices (shared with the independent FP64 oracle, from the paper's
 // text): unknowns (p_w, S_n); the convective non-wetting flux is upwinded with the
@@ -18,6 +21,9 @@
 // sub-control volume uses its hat saturation; SCVF oriented from lower to higher
 // vertex index with ties upwinded to the lower one; integration point at the face
 // barycentre.
+#include <type_traits>
+#include <utility>
+
 #include "tpf_internal.h"
 
 namespace tpf {
@@ -137,196 +143,290 @@ __host__ __device__ __forceinline__ constexpr int stencil_index(int dx, int dy, 
 
 __host__ __device__ __forceinline__ constexpr int bit(int l, int a) { return (l >> a) & 1; }
 
+struct CellIn {
+  const double *u, *Kc, *phic, *pdc, *lamc, *pdmin, *pv;
+};
+
 // ---------------------------------------------------------------------------------
-// Residual F(u) and (WANT_A) the stage matrix A = M(u)/h - dF/du.
+// Cell contributions to the residual row of vertex v and (WANT_A) to its row of
+// -dF/du: cells with corner index cc, restricted to bit 2 of cc == HALF when
+// HALF >= 0; stencil slot o goes to acc[o - BASE].  Storage derivatives are returned
+// in mwS, mnS (dm_w/dS_n and dm_n/dS_n of the vertex).
 // ---------------------------------------------------------------------------------
-template <int DIM, bool WANT_A, bool W32>
-__host__ __device__ __forceinline__ void
-assemble_vertex(const long long v, const Phys &P, const double *__restrict__ u, const double *__restrict__ Kc,
-                const double *__restrict__ phic, const double *__restrict__ pdc,
-                const double *__restrict__ lamc, const double *__restrict__ pdmin,
-                const double *__restrict__ pv, const uint8_t *__restrict__ dmask,
-                const double *__restrict__ Q, const double inv_h, double *__restrict__ A64,
-                float *__restrict__ A32, double *__restrict__ F, double *__restrict__ mst) {
+template <int DIM, bool WANT_A, int HALF, int BASE, int NSLOT>
+__host__ __device__ __forceinline__ void accumulate_cells(const long long v, const Phys &P, const CellIn &in,
+                                                         double (&acc)[NSLOT][4], double &Fw, double &Fn,
+                                                         double &mwS, double &mnS) {
   constexpr int NC = 1 << DIM;
-  constexpr int NST = DIM == 3 ? 27 : 9;
-  constexpr int CEN = DIM == 3 ? 13 : 4;
   const int ix = (int)(v % P.nx);
   const long long tq = v / P.nx;
   const int iy = (int)(tq % P.ny);
   const int iz = (int)(tq / P.ny);
   const long long sy = P.nx, sz = (long long)P.nx * P.ny;
-
-  double acc[WANT_A ? NST : 1][4];
-  if (WANT_A) {
-#pragma unroll
-    for (int o = 0; o < NST; ++o)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) acc[o][e] = 0.0;
-  }
-  double Fw = 0.0, Fn = 0.0, mwS = 0.0, mnS = 0.0;
   const double rw = P.rho_w, rn = P.rho_n;
 
-#pragma unroll
-  for (int cc = 0; cc < NC; ++cc) {
-    // cell whose corner `cc` is this vertex: origin = vertex - bits(cc)
-    const int ox = ix - bit(cc, 0), oy = iy - bit(cc, 1), oz = (DIM == 3) ? iz - bit(cc, 2) : 0;
-    if (ox < 0 || oy < 0 || oz < 0 || ox >= P.ncx || oy >= P.ncy || oz >= P.ncz) continue;
-    const long long c = ox + (long long)P.ncx * (oy + (long long)P.ncy * oz);
-    const double Ke = Kc[c], phie = phic[c], pde = pdc[c], lame = lamc[c];
-    double p[NC], sn[NC], sh[NC], dsh[NC], pc[NC], dpc[NC];
-#pragma unroll
-    for (int l = 0; l < NC; ++l) {
-      const int dx = bit(l, 0) - bit(cc, 0), dy = bit(l, 1) - bit(cc, 1);
-      const int dz = (DIM == 3) ? bit(l, 2) - bit(cc, 2) : 0;
-      const long long vl = v + dx + sy * dy + sz * dz;
-      const double2 ul = *reinterpret_cast<const double2 *>(u + 2 * vl);
-      p[l] = ul.x;
-      sn[l] = ul.y;
-      const double pdm = pdmin[vl];
-      const double2 pvl = *reinterpret_cast<const double2 *>(pv + 2 * vl);
-      // interface condition (Eq. hSw): equal entry pressure / barrier / continuity
-      if (pde == pdm) {
-        sh[l] = sn[l]; dsh[l] = 1.0;
-      } else if (pde >= pvl.x) {
-        sh[l] = P.snr; dsh[l] = 0.0;
-      } else {
-        const double ses = pow(pvl.x / pde, -lame);
-        sh[l] = 1.0 - (P.swr + ses * P.D);
-        dsh[l] = -P.D * (-lame * ses / pvl.x * pvl.y);
-      }
-      double se, dse;
-      eff_sat(sh[l], P, se, dse);
-      pc[l] = pde * pow(se, -1.0 / lame);
-      dpc[l] = pc[l] * (-1.0 / lame) / se * dse * dsh[l];
-    }
-    // storage of the sub-control volume (vertex, cell): only dM/dS_n is non-zero
-    mwS -= phie * rw * P.scv * dsh[cc];
-    mnS += phie * rn * P.scv * dsh[cc];
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-      const int cj = cc ^ (1 << a);
-      const int l0 = bit(cc, a) ? cj : cc;
-      const int l1 = bit(cc, a) ? cc : cj;
-      const double sgn = bit(cc, a) ? 1.0 : -1.0;  // F_l0 -= flux, F_l1 += flux
-      // shape functions and x_a-derivatives at the SCVF barycentre
-      double Nl[NC], Gl[NC];
+  // The body runs once per adjacent cell with the corner index `cc` a template
+  // constant, so every stencil slot of the row accumulator is a compile-time index.
+  auto cell = [&]<int cc>(std::integral_constant<int, cc>) {
+    if constexpr (HALF >= 0 && bit(cc, 2) != HALF) {
+      return;
+    } else {
+      // cell whose corner `cc` is this vertex: origin = vertex - bits(cc)
+      const int ox = ix - bit(cc, 0), oy = iy - bit(cc, 1), oz = (DIM == 3) ? iz - bit(cc, 2) : 0;
+      if (ox < 0 || oy < 0 || oz < 0 || ox >= P.ncx || oy >= P.ncy || oz >= P.ncz) return;
+      const long long c = ox + (long long)P.ncx * (oy + (long long)P.ncy * oz);
+      const double Ke = in.Kc[c], phie = in.phic[c], pde = in.pdc[c], lame = in.lamc[c];
+      double p[NC], sn[NC], sh[NC], dsh[NC], pc[NC], dpc[NC];
 #pragma unroll
       for (int l = 0; l < NC; ++l) {
-        double n = 1.0, gg = (bit(l, a) ? 1.0 : -1.0) / P.h[a];
-#pragma unroll
-        for (int b = 0; b < DIM; ++b) {
-          const double xi = (b == a) ? 0.5 : (bit(cc, b) ? 0.75 : 0.25);
-          const double f = bit(l, b) ? xi : 1.0 - xi;
-          n *= f;
-          if (b != a) gg *= f;
+        const int dx = bit(l, 0) - bit(cc, 0), dy = bit(l, 1) - bit(cc, 1);
+        const int dz = (DIM == 3) ? bit(l, 2) - bit(cc, 2) : 0;
+        const long long vl = v + dx + sy * dy + sz * dz;
+        const double2 ul = *reinterpret_cast<const double2 *>(in.u + 2 * vl);
+        p[l] = ul.x;
+        sn[l] = ul.y;
+        const double pdm = in.pdmin[vl];
+        const double2 pvl = *reinterpret_cast<const double2 *>(in.pv + 2 * vl);
+        // interface condition (Eq. hSw): equal entry pressure / barrier / continuity
+        if (pde == pdm) {
+          sh[l] = sn[l]; dsh[l] = 1.0;
+        } else if (pde >= pvl.x) {
+          sh[l] = P.snr; dsh[l] = 0.0;
+        } else {
+          const double ses = pow(pvl.x / pde, -lame);
+          sh[l] = 1.0 - (P.swr + ses * P.D);
+          dsh[l] = -P.D * (-lame * ses / pvl.x * pvl.y);
         }
-        Nl[l] = n;
-        Gl[l] = gg;
+        double se, dse;
+        eff_sat(sh[l], P, se, dse);
+        pc[l] = pde * pow(se, -1.0 / lame);
+        dpc[l] = pc[l] * (-1.0 / lame) / se * dse * dsh[l];
       }
-      double dp = 0.0, sip = 0.0, gpc = 0.0;
+      // storage of the sub-control volume (vertex, cell): only dM/dS_n is non-zero
+      mwS -= phie * rw * P.scv * dsh[cc];
+      mnS += phie * rn * P.scv * dsh[cc];
 #pragma unroll
-      for (int l = 0; l < NC; ++l) {
-        dp += p[l] * Gl[l];
-        sip += Nl[l] * sh[l];
-        gpc += pc[l] * Gl[l];
-      }
-      const double area = P.area[a];
-      const double ga = P.g[a];
-      // wetting phase, upwinded plain saturation
-      const double cw = -(Ke / P.mu_w) * area;
-      const double phw = cw * (dp - rw * ga);
-      const bool upw0 = phw >= 0.0;
-      double kw, dkw;
-      krw(upw0 ? sn[l0] : sn[l1], lame, P, kw, dkw);
-      const double fw = rw * kw * phw;
-      // non-wetting phase, upwinded hat saturation
-      const double cn = -(Ke / P.mu_n) * area;
-      const double phn = cn * (dp - rn * ga);
-      const bool upn0 = phn >= 0.0;
-      double kn, dkn;
-      krn(upn0 ? sh[l0] : sh[l1], lame, P, kn, dkn);
-      const double fn = rn * kn * phn;
-      // capillary diffusion, central
-      double kip, dkip;
-      krn(sip, lame, P, kip, dkip);
-      const double cc_ = -rn * (Ke / P.mu_n) * area;
-      const double fc = cc_ * kip * gpc;
-      Fw += sgn * fw;
-      Fn += sgn * (fn + fc);
-      if (WANT_A) {
-        // A_{i,l} -= sgn * d(flux)/du_l
+      for (int a = 0; a < DIM; ++a) {
+        const int cj = cc ^ (1 << a);
+        const int l0 = bit(cc, a) ? cj : cc;
+        const int l1 = bit(cc, a) ? cc : cj;
+        const double sgn = bit(cc, a) ? 1.0 : -1.0;  // F_l0 -= flux, F_l1 += flux
+        // shape functions and x_a-derivatives at the SCVF barycentre
+        double Nl[NC], Gl[NC];
 #pragma unroll
         for (int l = 0; l < NC; ++l) {
-          const int dx = bit(l, 0) - bit(cc, 0), dy = bit(l, 1) - bit(cc, 1);
-          const int dz = (DIM == 3) ? bit(l, 2) - bit(cc, 2) : 0;
-          const int o = stencil_index<DIM>(dx, dy, dz);
-          acc[o][0] -= sgn * (rw * kw * cw * Gl[l]);
-          acc[o][2] -= sgn * (rn * kn * cn * Gl[l]);
-          acc[o][3] -= sgn * (cc_ * (dkip * Nl[l] * dsh[l] * gpc + kip * Gl[l] * dpc[l]));
+          double n = 1.0, gg = (bit(l, a) ? 1.0 : -1.0) / P.h[a];
+#pragma unroll
+          for (int b = 0; b < DIM; ++b) {
+            const double xi = (b == a) ? 0.5 : (bit(cc, b) ? 0.75 : 0.25);
+            const double f = bit(l, b) ? xi : 1.0 - xi;
+            n *= f;
+            if (b != a) gg *= f;
+          }
+          Nl[l] = n;
+          Gl[l] = gg;
         }
-        const double dfw = rw * phw * dkw;
-        const double dfn = rn * phn * dkn;
-        {
+        double dp = 0.0, sip = 0.0, gpc = 0.0;
+#pragma unroll
+        for (int l = 0; l < NC; ++l) {
+          dp += p[l] * Gl[l];
+          sip += Nl[l] * sh[l];
+          gpc += pc[l] * Gl[l];
+        }
+        const double area = P.area[a];
+        const double ga = P.g[a];
+        // wetting phase, upwinded plain saturation
+        const double cw = -(Ke / P.mu_w) * area;
+        const double phw = cw * (dp - rw * ga);
+        const bool upw0 = phw >= 0.0;
+        double kw, dkw;
+        krw(upw0 ? sn[l0] : sn[l1], lame, P, kw, dkw);
+        const double fw = rw * kw * phw;
+        // non-wetting phase, upwinded hat saturation
+        const double cn = -(Ke / P.mu_n) * area;
+        const double phn = cn * (dp - rn * ga);
+        const bool upn0 = phn >= 0.0;
+        double kn, dkn;
+        krn(upn0 ? sh[l0] : sh[l1], lame, P, kn, dkn);
+        const double fn = rn * kn * phn;
+        // capillary diffusion, central
+        double kip, dkip;
+        krn(sip, lame, P, kip, dkip);
+        const double cc_ = -rn * (Ke / P.mu_n) * area;
+        const double fc = cc_ * kip * gpc;
+        Fw += sgn * fw;
+        Fn += sgn * (fn + fc);
+        if (WANT_A) {
+          // A_{i,l} -= sgn * d(flux)/du_l
+#pragma unroll
+          for (int l = 0; l < NC; ++l) {
+            const int dx = bit(l, 0) - bit(cc, 0), dy = bit(l, 1) - bit(cc, 1);
+            const int dz = (DIM == 3) ? bit(l, 2) - bit(cc, 2) : 0;
+            const int o = stencil_index<DIM>(dx, dy, dz) - BASE;
+            acc[o][0] -= sgn * (rw * kw * cw * Gl[l]);
+            acc[o][2] -= sgn * (rn * kn * cn * Gl[l]);
+            acc[o][3] -= sgn * (cc_ * (dkip * Nl[l] * dsh[l] * gpc + kip * Gl[l] * dpc[l]));
+          }
+          const double dfw = rw * phw * dkw;
+          const double dfn = rn * phn * dkn;
           const int dx0 = bit(l0, 0) - bit(cc, 0), dy0 = bit(l0, 1) - bit(cc, 1);
           const int dz0 = (DIM == 3) ? bit(l0, 2) - bit(cc, 2) : 0;
           const int dx1 = bit(l1, 0) - bit(cc, 0), dy1 = bit(l1, 1) - bit(cc, 1);
           const int dz1 = (DIM == 3) ? bit(l1, 2) - bit(cc, 2) : 0;
-          const int o0 = stencil_index<DIM>(dx0, dy0, dz0);
-          const int o1 = stencil_index<DIM>(dx1, dy1, dz1);
+          const int o0 = stencil_index<DIM>(dx0, dy0, dz0) - BASE;
+          const int o1 = stencil_index<DIM>(dx1, dy1, dz1) - BASE;
           if (upw0) acc[o0][1] -= sgn * dfw; else acc[o1][1] -= sgn * dfw;
           if (upn0) acc[o0][3] -= sgn * dfn * dsh[l0]; else acc[o1][3] -= sgn * dfn * dsh[l1];
         }
       }
     }
-  }
-  const double2 q = *reinterpret_cast<const double2 *>(Q + 2 * v);
-  Fw += q.x;
-  Fn += q.y;
+  };
+  [&]<int... CCs>(std::integer_sequence<int, CCs...>) {
+    (cell(std::integral_constant<int, CCs>{}), ...);
+  }(std::make_integer_sequence<int, NC>{});
+}
+
+// Completes and stores the row of vertex v for the stencil slots BASE..BASE+NSLOT-1
+// (acc[k] = slot BASE + k): Dirichlet rows become unit rows (the unit entry on the
+// centre slot), and the thread holding the centre (OWNER) adds the storage M/h,
+// the Neumann source, and writes F and the storage part.
+template <int DIM, bool WANT_A, bool W32, bool OWNER, int BASE, int NSLOT>
+__host__ __device__ __forceinline__ void finish_vertex(const long long v, const Phys &P,
+                                                      const uint8_t *__restrict__ dmask,
+                                                      const double *__restrict__ Q, const double inv_h,
+                                                      double (&acc)[NSLOT][4], double Fw, double Fn, double mwS,
+                                                      double mnS, double *__restrict__ A64, float *__restrict__ A32,
+                                                      double *__restrict__ F, double *__restrict__ mst) {
+  constexpr int CEN = DIM == 3 ? 13 : 4;
+  constexpr bool HAS_CEN = CEN >= BASE && CEN < BASE + NSLOT;
   const uint8_t m = dmask[v];
-  if (m & 1) Fw = 0.0;
-  if (m & 2) Fn = 0.0;
-  if (F != nullptr) *reinterpret_cast<double2 *>(F + 2 * v) = make_double2(Fw, Fn);
-  if (WANT_A) {
-    acc[CEN][1] += mwS * inv_h;
-    acc[CEN][3] += mnS * inv_h;
+  if (OWNER) {
+    const double2 q = *reinterpret_cast<const double2 *>(Q + 2 * v);
+    Fw += q.x;
+    Fn += q.y;
+    if (m & 1) Fw = 0.0;
+    if (m & 2) Fn = 0.0;
+    if (F != nullptr) *reinterpret_cast<double2 *>(F + 2 * v) = make_double2(Fw, Fn);
+  }
+  if (!WANT_A) return;
+  if constexpr (OWNER && HAS_CEN) {
+    acc[CEN - BASE][1] += mwS * inv_h;
+    acc[CEN - BASE][3] += mnS * inv_h;
     // storage part of the centre block (kept apart for the coarse-level lumping)
     *reinterpret_cast<double2 *>(mst + 2 * v) =
         make_double2((m & 1) ? 0.0 : mwS * inv_h, (m & 2) ? 0.0 : mnS * inv_h);
-    if (m & 1) {
+  }
+  if (m & 1) {
 #pragma unroll
-      for (int o = 0; o < NST; ++o) { acc[o][0] = 0.0; acc[o][1] = 0.0; }
-      acc[CEN][0] = 1.0;
-    }
-    if (m & 2) {
+    for (int o = 0; o < NSLOT; ++o) { acc[o][0] = 0.0; acc[o][1] = 0.0; }
+    if constexpr (HAS_CEN) acc[CEN - BASE][0] = 1.0;
+  }
+  if (m & 2) {
 #pragma unroll
-      for (int o = 0; o < NST; ++o) { acc[o][2] = 0.0; acc[o][3] = 0.0; }
-      acc[CEN][3] = 1.0;
-    }
+    for (int o = 0; o < NSLOT; ++o) { acc[o][2] = 0.0; acc[o][3] = 0.0; }
+    if constexpr (HAS_CEN) acc[CEN - BASE][3] = 1.0;
+  }
 #pragma unroll
-    for (int o = 0; o < NST; ++o) {
-      double *dst = A64 + ((long long)o * P.N + v) * 4;
-      reinterpret_cast<double2 *>(dst)[0] = make_double2(acc[o][0], acc[o][1]);
-      reinterpret_cast<double2 *>(dst)[1] = make_double2(acc[o][2], acc[o][3]);
-      if (W32) {
-        float4 f4 = make_float4((float)acc[o][0], (float)acc[o][1], (float)acc[o][2], (float)acc[o][3]);
-        *reinterpret_cast<float4 *>(A32 + ((long long)o * P.N + v) * 4) = f4;
-      }
+  for (int k = 0; k < NSLOT; ++k) {
+    const int o = BASE + k;
+    double *dst = A64 + ((long long)o * P.N + v) * 4;
+    reinterpret_cast<double2 *>(dst)[0] = make_double2(acc[k][0], acc[k][1]);
+    reinterpret_cast<double2 *>(dst)[1] = make_double2(acc[k][2], acc[k][3]);
+    if (W32) {
+      float4 f4 = make_float4((float)acc[k][0], (float)acc[k][1], (float)acc[k][2], (float)acc[k][3]);
+      *reinterpret_cast<float4 *>(A32 + ((long long)o * P.N + v) * 4) = f4;
     }
   }
 }
 
+// Residual F(u) and (WANT_A) the stage matrix A = M(u)/h - dF/du for one vertex,
+// all cells in one thread.
+template <int DIM, bool WANT_A, bool W32>
+__host__ __device__ __forceinline__ void assemble_vertex(const long long v, const Phys &P, const CellIn &in,
+                                                        const uint8_t *__restrict__ dmask,
+                                                        const double *__restrict__ Q, const double inv_h,
+                                                        double *__restrict__ A64, float *__restrict__ A32,
+                                                        double *__restrict__ F, double *__restrict__ mst) {
+  constexpr int NST = DIM == 3 ? 27 : 9;
+  constexpr int NS = WANT_A ? NST : 1;
+  double acc[NS][4];
+#pragma unroll
+  for (int o = 0; o < NS; ++o)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) acc[o][e] = 0.0;
+  double Fw = 0.0, Fn = 0.0, mwS = 0.0, mnS = 0.0;
+  accumulate_cells<DIM, WANT_A, -1, 0, NS>(v, P, in, acc, Fw, Fn, mwS, mnS);
+  finish_vertex<DIM, WANT_A, W32, true, 0, NS>(v, P, dmask, Q, inv_h, acc, Fw, Fn, mwS, mnS, A64, A32, F, mst);
+}
+
 template <int DIM, bool WANT_A, bool W32>
 __global__ void __launch_bounds__(BS)
-k_assemble(const Phys P, const double *__restrict__ u, const double *__restrict__ Kc,
-           const double *__restrict__ phic, const double *__restrict__ pdc,
-           const double *__restrict__ lamc, const double *__restrict__ pdmin,
-           const double *__restrict__ pv, const uint8_t *__restrict__ dmask,
-           const double *__restrict__ Q, const double inv_h, double *__restrict__ A64,
-           float *__restrict__ A32, double *__restrict__ F, double *__restrict__ mst) {
+k_assemble(const Phys P, const CellIn in, const uint8_t *__restrict__ dmask, const double *__restrict__ Q,
+           const double inv_h, double *__restrict__ A64, float *__restrict__ A32, double *__restrict__ F,
+           double *__restrict__ mst) {
   const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= P.N) return;
-  assemble_vertex<DIM, WANT_A, W32>(v, P, u, Kc, phic, pdc, lamc, pdmin, pv, dmask, Q, inv_h, A64, A32, F, mst);
+  assemble_vertex<DIM, WANT_A, W32>(v, P, in, dmask, Q, inv_h, A64, A32, F, mst);
+}
+
+// 3D matrix assembly with two threads per vertex.  Thread half 1 takes the four
+// cells below the vertex (stencil planes dz = -1, 0: slots 0..17), half 0 the four
+// above (dz = 0, +1: slots 9..26).  Half 1 hands its dz = 0 plane and its partial
+// sums to half 0 through LDS; half 0 owns the centre, the residual and the storage.
+constexpr int SPLIT_V = BS / 2;  // vertices per block
+template <bool W32>
+__global__ void __launch_bounds__(BS)
+k_assemble3_split(const Phys P, const CellIn in, const uint8_t *__restrict__ dmask, const double *__restrict__ Q,
+                  const double inv_h, double *__restrict__ A64, float *__restrict__ A32, double *__restrict__ F,
+                  double *__restrict__ mst) {
+  __shared__ double xch[SPLIT_V][9 * 4 + 4];
+  const int half = threadIdx.x / SPLIT_V;  // waves 0-1: half 0, waves 2-3: half 1
+  const int lv = threadIdx.x % SPLIT_V;
+  const long long v = (long long)blockIdx.x * SPLIT_V + lv;
+  const bool valid = v < P.N;
+  double acc[18][4];
+#pragma unroll
+  for (int o = 0; o < 18; ++o)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) acc[o][e] = 0.0;
+  double Fw = 0.0, Fn = 0.0, mwS = 0.0, mnS = 0.0;
+  if (valid) {
+    if (half == 1)
+      accumulate_cells<3, true, 1, 0, 18>(v, P, in, acc, Fw, Fn, mwS, mnS);
+    else
+      accumulate_cells<3, true, 0, 9, 18>(v, P, in, acc, Fw, Fn, mwS, mnS);
+  }
+  if (half == 1) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) xch[lv][4 * k + e] = acc[9 + k][e];
+    xch[lv][36] = Fw;
+    xch[lv][37] = Fn;
+    xch[lv][38] = mwS;
+    xch[lv][39] = mnS;
+  }
+  __syncthreads();
+  if (!valid) return;
+  if (half == 0) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[k][e] += xch[lv][4 * k + e];
+    Fw += xch[lv][36];
+    Fn += xch[lv][37];
+    mwS += xch[lv][38];
+    mnS += xch[lv][39];
+    finish_vertex<3, true, W32, true, 9, 18>(v, P, dmask, Q, inv_h, acc, Fw, Fn, mwS, mnS, A64, A32, F, mst);
+  } else {
+    double low[9][4];
+#pragma unroll
+    for (int k = 0; k < 9; ++k)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) low[k][e] = acc[k][e];
+    finish_vertex<3, true, W32, false, 0, 9>(v, P, dmask, Q, inv_h, low, 0.0, 0.0, 0.0, 0.0, A64, A32, nullptr,
+                                             nullptr);
+  }
 }
 
 __global__ void k_apply_dirichlet(long long N, const uint8_t *__restrict__ m,
@@ -336,6 +436,10 @@ __global__ void k_apply_dirichlet(long long N, const uint8_t *__restrict__ m,
   const uint8_t b = m[v];
   if (b & 1) u[2 * v] = val[2 * v];
   if (b & 2) u[2 * v + 1] = val[2 * v + 1];
+}
+
+inline CellIn cell_in(const tpf_grid *g, const double *u) {
+  return CellIn{u, g->K, g->phi, g->pd, g->lam, g->pdmin, g->pv};
 }
 
 }  // namespace
@@ -354,12 +458,11 @@ tpf_status launch_residual(tpf_grid *g, const double *u, double *f, hipStream_t 
   const unsigned nb = blocks_for(g->P.N);
   k_vertex_pc<<<nb, BS, 0, s>>>(g->P, u, g->pdmin, g->lamref, g->pv);
   TPF_LAUNCH_CHECK();
+  const CellIn in = cell_in(g, u);
   if (g->dim == 3)
-    k_assemble<3, false, false><<<nb, BS, 0, s>>>(g->P, u, g->K, g->phi, g->pd, g->lam, g->pdmin, g->pv,
-                                                   g->dmask, g->Q, 0.0, nullptr, nullptr, f, nullptr);
+    k_assemble<3, false, false><<<nb, BS, 0, s>>>(g->P, in, g->dmask, g->Q, 0.0, nullptr, nullptr, f, nullptr);
   else
-    k_assemble<2, false, false><<<nb, BS, 0, s>>>(g->P, u, g->K, g->phi, g->pd, g->lam, g->pdmin, g->pv,
-                                                   g->dmask, g->Q, 0.0, nullptr, nullptr, f, nullptr);
+    k_assemble<2, false, false><<<nb, BS, 0, s>>>(g->P, in, g->dmask, g->Q, 0.0, nullptr, nullptr, f, nullptr);
   TPF_LAUNCH_CHECK();
   return TPF_OK;
 }
@@ -369,24 +472,22 @@ tpf_status launch_assemble(tpf_grid *g, const double *u0, double h, double *f0, 
   k_vertex_pc<<<nb, BS, 0, s>>>(g->P, u0, g->pdmin, g->lamref, g->pv);
   TPF_LAUNCH_CHECK();
   double *A64 = g->lv[0].A64;
-  float *A32 = g->lv[0].A32;
+  float *A32 = g->prec == TPF_MIXED ? g->lv[0].A32 : nullptr;
+  double *mst = g->lv[0].mst;
   const double ih = 1.0 / h;
-  const bool w32 = g->prec == TPF_MIXED;
+  const CellIn in = cell_in(g, u0);
   const int ps = prof_begin(g, TPF_K_ASSEMBLE, s);
   if (g->dim == 3) {
-    if (w32)
-      k_assemble<3, true, true><<<nb, BS, 0, s>>>(g->P, u0, g->K, g->phi, g->pd, g->lam, g->pdmin, g->pv,
-                                                   g->dmask, g->Q, ih, A64, A32, f0, g->lv[0].mst);
+    const unsigned nb2 = blocks_for(g->P.N, SPLIT_V);
+    if (A32)
+      k_assemble3_split<true><<<nb2, BS, 0, s>>>(g->P, in, g->dmask, g->Q, ih, A64, A32, f0, mst);
     else
-      k_assemble<3, true, false><<<nb, BS, 0, s>>>(g->P, u0, g->K, g->phi, g->pd, g->lam, g->pdmin, g->pv,
-                                                    g->dmask, g->Q, ih, A64, nullptr, f0, g->lv[0].mst);
+      k_assemble3_split<false><<<nb2, BS, 0, s>>>(g->P, in, g->dmask, g->Q, ih, A64, nullptr, f0, mst);
   } else {
-    if (w32)
-      k_assemble<2, true, true><<<nb, BS, 0, s>>>(g->P, u0, g->K, g->phi, g->pd, g->lam, g->pdmin, g->pv,
-                                                   g->dmask, g->Q, ih, A64, A32, f0, g->lv[0].mst);
+    if (A32)
+      k_assemble<2, true, true><<<nb, BS, 0, s>>>(g->P, in, g->dmask, g->Q, ih, A64, A32, f0, mst);
     else
-      k_assemble<2, true, false><<<nb, BS, 0, s>>>(g->P, u0, g->K, g->phi, g->pd, g->lam, g->pdmin, g->pv,
-                                                    g->dmask, g->Q, ih, A64, nullptr, f0, g->lv[0].mst);
+      k_assemble<2, true, false><<<nb, BS, 0, s>>>(g->P, in, g->dmask, g->Q, ih, A64, nullptr, f0, mst);
   }
   TPF_LAUNCH_CHECK();
   prof_end(g, ps, s);

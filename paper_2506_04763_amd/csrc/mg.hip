@@ -274,47 +274,54 @@ __global__ void k_zero(double *p, long long n) {
 
 // Right-looking LU with partial pivoting of a column-major n x n matrix in one
 // workgroup (the coarsest level has at most a few thousand unknowns).
+// One wavefront finds the pivot (shuffle arg-max, ties to the lowest row), the
+// multipliers of column k are staged in LDS, and the trailing update runs with 64
+// consecutive rows per wavefront and 16 wavefronts over the columns.  n <= 4096.
 __global__ void __launch_bounds__(1024) k_lu(double *__restrict__ a, int n, int *__restrict__ piv) {
-  __shared__ double smax[1024];
-  __shared__ int sidx[1024];
-  const int tid = threadIdx.x;
+  __shared__ double lcol[4096];
+  __shared__ int sp;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   for (int k = 0; k < n; ++k) {
-    // pivot search in column k, rows k..n-1 (ties -> lowest row)
-    double best = -1.0;
-    int bi = k;
-    for (int i = k + tid; i < n; i += blockDim.x) {
-      const double vabs = fabs(a[(long long)k * n + i]);
-      if (vabs > best) { best = vabs; bi = i; }
-    }
-    smax[tid] = best;
-    sidx[tid] = bi;
-    __syncthreads();
-    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
-      if (tid < st) {
-        const double o = smax[tid + st];
-        const int oi = sidx[tid + st];
-        if (o > smax[tid] || (o == smax[tid] && oi < sidx[tid])) { smax[tid] = o; sidx[tid] = oi; }
+    double *colk = a + (long long)k * n;
+    if (wv == 0) {
+      double best = -1.0;
+      int bi = k;
+      for (int i = k + lane; i < n; i += 64) {
+        const double vabs = fabs(colk[i]);
+        if (vabs > best) { best = vabs; bi = i; }
       }
-      __syncthreads();
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ob = __shfl_down(best, off, 64);
+        const int oi = __shfl_down(bi, off, 64);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      if (lane == 0) {
+        sp = bi;
+        piv[k] = bi;
+      }
     }
-    const int p = sidx[0];
-    if (tid == 0) piv[k] = p;
+    __syncthreads();
+    const int p = sp;
     if (p != k) {
-      for (int j = tid; j < n; j += blockDim.x) {
+      for (int j = tid; j < n; j += 1024) {
         const double t = a[(long long)j * n + k];
         a[(long long)j * n + k] = a[(long long)j * n + p];
         a[(long long)j * n + p] = t;
       }
     }
     __syncthreads();
-    const double inv = 1.0 / a[(long long)k * n + k];
-    for (int i = k + 1 + tid; i < n; i += blockDim.x) a[(long long)k * n + i] *= inv;
+    const double inv = 1.0 / colk[k];
+    for (int i = k + 1 + tid; i < n; i += 1024) {
+      const double l = colk[i] * inv;
+      colk[i] = l;
+      lcol[i] = l;
+    }
     __syncthreads();
-    const int m = n - k - 1;
-    for (long long e = tid; e < (long long)m * m; e += blockDim.x) {
-      const int j = k + 1 + (int)(e / m);
-      const int i = k + 1 + (int)(e % m);
-      a[(long long)j * n + i] -= a[(long long)k * n + i] * a[(long long)j * n + k];
+    for (int j = k + 1 + wv; j < n; j += 16) {
+      double *colj = a + (long long)j * n;
+      const double u = colj[k];
+      for (int i = k + 1 + lane; i < n; i += 64) colj[i] -= lcol[i] * u;
     }
     __syncthreads();
   }
@@ -346,18 +353,23 @@ __global__ void __launch_bounds__(64) k_lu_inverse(const double *__restrict__ lu
     for (int i = lane; i < k; i += 64) y[i] -= lu[(long long)k * n + i] * xk;
     __syncthreads();
   }
-  for (int i = lane; i < n; i += 64) inv[(long long)j * n + i] = y[i];
+  for (int i = lane; i < n; i += 64) inv[(long long)i * n + j] = y[i];  // row-major
 }
 
-// x = A^{-1} b on the coarsest level (column-major inverse, one thread per row).
+// x = A^{-1} b on the coarsest level: row-major inverse, one 64-lane wavefront per
+// row (coalesced row reads, fixed-order shuffle reduction).
 template <typename T>
-__global__ void __launch_bounds__(64) k_coarse_solve(const double *__restrict__ inv, int n,
-                                                     const T *__restrict__ b, T *__restrict__ x) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n) return;
+__global__ void __launch_bounds__(256) k_coarse_solve(const double *__restrict__ inv, int n,
+                                                      const T *__restrict__ b, T *__restrict__ x) {
+  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (r >= n) return;  // whole wavefront exits together
+  const double *row = inv + (long long)r * n;
   double s = 0.0;
-  for (int c = 0; c < n; ++c) s += inv[(long long)c * n + r] * (double)b[c];
-  x[r] = (T)s;
+  for (int c = lane; c < n; c += 64) s += row[c] * (double)b[c];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if (lane == 0) x[r] = (T)s;
 }
 
 template <typename TI, typename TO>
@@ -423,7 +435,7 @@ tpf_status vcycle_t(tpf_grid *g, const double *bin, double *xout, hipStream_t s)
     Level &lc = g->lv[L - 1];
     T *X = (L == 1 && sizeof(T) == sizeof(double)) ? reinterpret_cast<T *>(xout) : reinterpret_cast<T *>(lc.x);
     const int ps = prof_begin(g, TPF_K_COARSE_LEVELS, s);
-    k_coarse_solve<T><<<(g->nc + 63) / 64, 64, 0, s>>>(g->ainv, g->nc, bl[L - 1], X);
+    k_coarse_solve<T><<<(g->nc + 3) / 4, 256, 0, s>>>(g->ainv, g->nc, bl[L - 1], X);
     TPF_LAUNCH_CHECK();
     prof_end(g, ps, s);
     cur[L - 1] = X;

@@ -17,19 +17,27 @@ namespace tpf {
 namespace {
 
 // Per axis and coarse offset O in {-1, 0, 1}: every (fine-row offset d, fine-column
-// offset o) with j = 2I + d + o interpolating from J = I + O, and the linear
-// weight P(j, J).  The aggregation weights are non-zero on a subset of these pairs.
+// offset o) with j = 2I + d + o interpolating linearly from J = I + O.  The pairs are
+// packed 4 bits each ((d+1) | (o+1) << 2) into one integer per O, so that no table
+// is indexed at run time (which would put it in scratch memory); the linear weight
+// P(j, J) is 1 for s = d + o = 2 O and 1/2 otherwise.  The aggregation weights are
+// non-zero on a subset of these pairs.
 struct AxisTerms {
-  int n;
-  int d[7], o[7];
-  double w[7];
+  int n;      // number of pairs
+  unsigned packed;
+  bool flat;  // the absent z axis of 2D grids: the single pair (0, 0)
+  __host__ __device__ __forceinline__ int d(int k) const { return flat ? 0 : (int)((packed >> (4 * k)) & 3u) - 1; }
+  __host__ __device__ __forceinline__ int o(int k) const { return flat ? 0 : (int)((packed >> (4 * k + 2)) & 3u) - 1; }
 };
 __host__ __device__ __forceinline__ AxisTerms axis_terms(int O) {
-  if (O < 0) return AxisTerms{3, {-1, -1, 0}, {-1, 0, -1}, {1.0, 0.5, 0.5}};
-  if (O > 0) return AxisTerms{3, {0, 1, 1}, {1, 0, 1}, {0.5, 0.5, 1.0}};
-  return AxisTerms{7, {-1, 0, -1, 0, 1, 0, 1}, {0, -1, 1, 0, -1, 1, 0}, {0.5, 0.5, 1.0, 1.0, 1.0, 0.5, 0.5}};
+  // O = -1: (-1,-1) (-1,0) (0,-1);  O = +1: (0,1) (1,0) (1,1);
+  // O = 0: (-1,0) (0,-1) (-1,1) (0,0) (1,-1) (0,1) (1,0)
+  if (O < 0) return AxisTerms{3, 0x140u, false};
+  if (O > 0) return AxisTerms{3, 0xA69u, false};
+  return AxisTerms{7, 0x6925814u, false};
 }
-__host__ __device__ __forceinline__ AxisTerms axis_flat() { return AxisTerms{1, {0}, {0}, {1.0}}; }
+__host__ __device__ __forceinline__ AxisTerms axis_flat() { return AxisTerms{1, 0u, true}; }
+__host__ __device__ __forceinline__ double lin_col(int s, int O) { return s == 2 * O ? 1.0 : 0.5; }
 
 // 1-D weights: linear row weight P(2I + d, I), aggregation row weight, aggregation
 // column weight P_agg(j, J) for s = j - 2I and O = J - I.
@@ -80,26 +88,28 @@ __host__ __device__ __forceinline__ void rap_vertex(long long I, const Geo &F, c
     const AxisTerms tz = DIM == 3 ? axis_terms(Oz) : axis_flat();
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     for (int kz = 0; kz < tz.n; ++kz) {
-      const int fz = (DIM == 3 ? 2 * cz : 0) + tz.d[kz], jz = fz + tz.o[kz];
+      const int dz = tz.d(kz), oz = tz.o(kz);
+      const int fz = (DIM == 3 ? 2 * cz : 0) + dz, jz = fz + oz;
       if (fz < 0 || fz >= F.nz || jz < 0 || jz >= F.nz) continue;
-      const double rz_l = DIM == 3 ? lin_row(tz.d[kz]) : 1.0, rz_a = DIM == 3 ? agg_row(tz.d[kz]) : 1.0;
-      const double cz_a = DIM == 3 ? agg_col(tz.d[kz] + tz.o[kz], Oz) : 1.0;
+      const double rz_l = DIM == 3 ? lin_row(dz) : 1.0, rz_a = DIM == 3 ? agg_row(dz) : 1.0;
+      const double cz_l = DIM == 3 ? lin_col(dz + oz, Oz) : 1.0, cz_a = DIM == 3 ? agg_col(dz + oz, Oz) : 1.0;
       for (int ky = 0; ky < ty.n; ++ky) {
-        const int fy = 2 * cy + ty.d[ky], jy = fy + ty.o[ky];
+        const int dy = ty.d(ky), oy = ty.o(ky);
+        const int fy = 2 * cy + dy, jy = fy + oy;
         if (fy < 0 || fy >= F.ny || jy < 0 || jy >= F.ny) continue;
-        const double ry_l = lin_row(ty.d[ky]), ry_a = agg_row(ty.d[ky]);
-        const double cy_a = agg_col(ty.d[ky] + ty.o[ky], Oy);
+        const double ry_l = lin_row(dy), ry_a = agg_row(dy);
+        const double cy_l = lin_col(dy + oy, Oy), cy_a = agg_col(dy + oy, Oy);
         for (int kx = 0; kx < tx.n; ++kx) {
-          const int fx = 2 * cx + tx.d[kx], jx = fx + tx.o[kx];
+          const int dx = tx.d(kx), ox = tx.o(kx);
+          const int fx = 2 * cx + dx, jx = fx + ox;
           if (fx < 0 || fx >= F.nx || jx < 0 || jx >= F.nx) continue;
-          const double rl = lin_row(tx.d[kx]) * ry_l * rz_l;          // P_p(i, I)
-          const double ra = agg_row(tx.d[kx]) * ry_a * rz_a;          // P_S(i, I)
-          const double cl = tx.w[kx] * ty.w[ky] * tz.w[kz];          // P_p(j, J)
-          const double ca = agg_col(tx.d[kx] + tx.o[kx], Ox) * cy_a * cz_a;  // P_S(j, J)
+          const double rl = lin_row(dx) * ry_l * rz_l;          // P_p(i, I)
+          const double ra = agg_row(dx) * ry_a * rz_a;          // P_S(i, I)
+          const double cl = lin_col(dx + ox, Ox) * cy_l * cz_l;  // P_p(j, J)
+          const double ca = agg_col(dx + ox, Ox) * cy_a * cz_a;  // P_S(j, J)
           const long long i = fx + sy * fy + sz * fz;
           const long long j = jx + sy * jy + sz * jz;
-          const int oo = DIM == 3 ? (tx.o[kx] + 1) + 3 * (ty.o[ky] + 1) + 9 * (tz.o[kz] + 1)
-                                  : (tx.o[kx] + 1) + 3 * (ty.o[ky] + 1);
+          const int oo = DIM == 3 ? (ox + 1) + 3 * (oy + 1) + 9 * (oz + 1) : (ox + 1) + 3 * (oy + 1);
           const double2 *bp = reinterpret_cast<const double2 *>(Af + ((long long)oo * F.N + i) * 4);
           const double2 b01 = bp[0], b23 = bp[1];
           double e1 = b01.y, e3 = b23.y;
