@@ -244,7 +244,8 @@ class Grid:
 
     def close(self):
         if getattr(self, "handle", None):
-            self.torch.cuda.synchronize(self.device)
+            # all of the grid's device work is on its stream: wait for it, then free
+            self.stream.synchronize()
             self.lib.tpf_destroy_grid(self.handle)
             self.handle = None
             self.arena = None

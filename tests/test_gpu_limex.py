@@ -1,0 +1,92 @@
+"""LIMEX steps on the GPU (through the C ABI) against the FP64 oracle.
+
+Each step compares the accept/reject decision, the error estimate eps, the proposed
+next step and the state; solves run to rtol 1e-10 on both sides, so the states agree
+to the accumulated solve tolerance (bound 1e-8 relative per field after 10 steps).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import stage as ST
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+tpf = pytest.importorskip("paper_2506_04763_amd")
+
+
+def per_field(a, b):
+    return max(float(np.linalg.norm(a[c::2] - b[c::2]) / np.linalg.norm(b[c::2])) for c in (0, 1))
+
+
+def run_sequence(scn, steps, stages, dt0, tol=5e-3, safety=0.75, dt_max=8.64e6, precision="fp64"):
+    g = tpf.Grid(scn, precision=precision, limex_stages=stages)
+    u = torch.as_tensor(scn.u0.ravel().copy(), device="cuda")
+    ref = ST.Stage(scn)
+    uo = scn.u0.ravel().copy()
+    t = to = 0.0
+    dt = dto = dt0
+    log = []
+    for k in range(steps):
+        print(f"[limex] {scn.name} step {k} dt={dt:.4g}", flush=True)
+        acc, t, dt_next, st = g.limex_step(u, t, dt, stages=stages, tol=tol, safety=safety, dt_max=dt_max,
+                                           rtol=1e-10, maxit=400)
+        out, info = ref.limex_step(uo, dto, stages=stages, tol=tol, safety=safety, dt_max=dt_max, rtol=1e-10)
+        assert acc == info["accepted"], (k, st, info)
+        assert st["eps"] == pytest.approx(info["eps"], rel=1e-6, abs=1e-12)
+        assert dt_next == pytest.approx(info["dt_next"], rel=1e-6)
+        if info["accepted"]:
+            uo = out
+            to += dto
+        dto = info["dt_next"]
+        dt = dt_next
+        err = per_field(u.cpu().numpy(), uo)
+        log.append((acc, st["eps"], dt_next, err, st["solves"], st["iters_total"]))
+        assert t == pytest.approx(to, rel=1e-12)
+    g.close()
+    return log, u.cpu().numpy(), uo
+
+
+def test_limex_lens_2d_ten_steps():
+    scn = W.lens_2d()
+    log, ug, uo = run_sequence(scn, steps=10, stages=2, dt0=32.0)
+    print(log)
+    assert per_field(ug, uo) < 1e-8
+    assert sum(1 for l in log if l[0]) >= 8
+
+
+def test_limex_cube_three_stages():
+    scn = W.small_cube(9, sigma=1.5, seed=31, levels=3)
+    log, ug, uo = run_sequence(scn, steps=3, stages=3, dt0=32.0)
+    print(log)
+    assert per_field(ug, uo) < 1e-8
+
+
+def test_limex_rejection_leaves_state_unchanged():
+    scn = W.lens_2d(17, 9)
+    scn.levels = 3
+    g = tpf.Grid(scn, precision="fp64", limex_stages=2)
+    u = torch.as_tensor(scn.u0.ravel().copy(), device="cuda")
+    u_before = u.clone()
+    # an unreachable tolerance forces a rejection
+    acc, t, dt, st = g.limex_step(u, 0.0, 1000.0, stages=2, tol=1e-30, rtol=1e-10)
+    assert not acc and t == 0.0 and dt < 1000.0
+    assert torch.equal(u, u_before)
+    g.close()
+
+
+def test_limex_mixed_precision_close_to_fp64():
+    scn = W.lens_2d()
+    g64 = tpf.Grid(scn, precision="fp64", limex_stages=2)
+    g32 = tpf.Grid(scn, precision="mixed", limex_stages=2)
+    u64 = torch.as_tensor(scn.u0.ravel().copy(), device="cuda")
+    u32 = u64.clone()
+    t64 = t32 = 0.0
+    d64 = d32 = 32.0
+    for _ in range(5):
+        a64, t64, d64, _ = g64.limex_step(u64, t64, d64, stages=2, rtol=1e-10)
+        a32, t32, d32, _ = g32.limex_step(u32, t32, d32, stages=2, rtol=1e-10)
+        assert a64 == a32
+    assert per_field(u32.cpu().numpy(), u64.cpu().numpy()) < 1e-8
+    g64.close()
+    g32.close()
