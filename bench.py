@@ -137,7 +137,7 @@ def run(args):
     if os.path.exists(tfile):
         try:
             tj = json.load(open(tfile))
-            if tj.get("kernel") == dom and tj.get("source_hash") == _source_hash():
+            if tj.get("kernel") == dom and tj.get("source_hash") == _source_hash(dom):
                 traffic = tj.get("bytes_per_launch")
         except Exception:
             traffic = None
@@ -181,10 +181,45 @@ def run(args):
     return line
 
 
-def _source_hash():
+def counters_driver(cycles=4, copy_bytes=1 << 30):
+    """Short workload for hardware-counter runs: one 129^3 mixed-precision stage
+    assembly, `cycles` V-cycles (4 fine-level smoother sweeps each), and a plain
+    device-to-device copy of `copy_bytes` bytes whose FETCH_SIZE / WRITE_SIZE readings
+    calibrate the counters against a known byte count."""
+    import torch
+
+    import paper_2506_04763_amd as tpf
+    import workloads as W
+    scn = W.cube_c3()
+    g = tpf.Grid(scn, precision="mixed", levels=6)
+    u0 = g.initial_state()
+    f = g.empty()
+    g.assemble_stage(u0, 32.0, f0_out=f)
+    for _ in range(cycles):
+        g.precondition(f)
+    a = torch.empty(copy_bytes // 4, dtype=torch.float32, device="cuda")
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"counters_driver": "done", "vertices": scn.nverts, "copy_bytes": copy_bytes,
+                      "source_hash": {k: _source_hash(k) for k in KERNEL_SOURCES}}), flush=True)
+
+
+KERNEL_SOURCES = {  # files whose text defines each timed kernel class
+    "smooth0": ["mg.hip", "stencil.h", "tpf_internal.h"],
+    "resid0": ["mg.hip", "stencil.h", "tpf_internal.h"],
+    "spmv64": ["mg.hip", "stencil.h", "tpf_internal.h"],
+    "assemble": ["assemble.hip", "tpf_internal.h"],
+}
+
+
+def _source_hash(kernel="smooth0"):
+    """Hash of the sources of a kernel class: hardware-counter figures recorded for
+    one version of a kernel are not reported for another."""
     import hashlib
     h = hashlib.sha256()
-    for f in sorted(os.listdir(os.path.join(ROOT, "paper_2506_04763_amd", "csrc"))):
+    for f in KERNEL_SOURCES.get(kernel, sorted(os.listdir(os.path.join(ROOT, "paper_2506_04763_amd", "csrc")))):
         h.update(open(os.path.join(ROOT, "paper_2506_04763_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -198,7 +233,12 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=256)
+    ap.add_argument("--counters", action="store_true",
+                    help="run the short hardware-counter workload instead of the benchmark")
     args = ap.parse_args()
+    if args.counters:
+        counters_driver()
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU: the stage solver has no multi-GPU "
                                    "path (see DESIGN.md for how it would shard)", "n_gpus": args.gpus}))
