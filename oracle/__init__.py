@@ -15,7 +15,8 @@ interface rules; the branch taken at the evaluated state is frozen).
 Modules
   fv      geometry of the box method on Q1 cells, Brooks-Corey-Burdine laws, the
           p_dmin interface condition, storage m(u), residual F(u), J, M, stage matrix
-  gmg     trilinear prolongation, Galerkin hierarchy, damped 2x2 block Jacobi,
+  gmg     per-component prolongation (linear p_w, aggregated S_n), Galerkin hierarchy
+          with lumped coarse storage, damped 2x2 block Jacobi,
           V(nu1, nu2) cycle with a dense LU solve on the coarsest level
   krylov  right-preconditioned BiCGSTAB
   limex   linearly implicit Euler substeps, extrapolation tableau, scaled error norm

@@ -7,8 +7,9 @@
 // [offset][vertex][4]: for a fixed offset, consecutive lanes read consecutive 16-byte
 // (FP32) or 32-byte (FP64) blocks, so every matrix load of a wave is one contiguous
 // 1-2 KB segment.  Entries for neighbours outside the grid are stored as zeros and
-// never dereference x.  P is per-component (bi/tri)linear interpolation between
-// vertex-halved grids; on the finest level its rows at Dirichlet components are zero.
+// never dereference x.  P acts per component between vertex-halved grids: (bi/tri)
+// linear interpolation of the pressure, piecewise-constant aggregation of the
+// saturation; on the finest level its rows at Dirichlet components are zero.
 #include "stencil.h"
 
 namespace tpf {
