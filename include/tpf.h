@@ -244,10 +244,12 @@ typedef struct tpf_kernel_time {
   double total_ms;      /* summed event-to-event durations                       */
 } tpf_kernel_time;
 
-/* Starts recording a pair of HIP events around each launch of the classes above
- * (up to max_launches launches; later launches are not timed).  Creates the
- * events; no device memory is allocated. */
-tpf_status tpf_profile_begin(tpf_grid *g, int32_t max_launches);
+/* Starts recording a pair of HIP events around each launch of the classes whose
+ * bit (1u << class) is set in class_mask (0: every class), up to max_launches
+ * launches; later launches are not timed.  Each recorded event is a marker in the
+ * stream, so timing only the classes of interest keeps the others unperturbed.
+ * Creates the events; no device memory is allocated. */
+tpf_status tpf_profile_begin(tpf_grid *g, int32_t max_launches, uint32_t class_mask);
 
 /* Synchronises the recorded events, writes per-class totals to out[TPF_K_COUNT]
  * and destroys the events. */

@@ -234,8 +234,12 @@ class Grid:
         L.check(self.lib.tpf_copy_coarse_inverse(self.handle, _ptr(out), self._sptr()), "tpf_copy_coarse_inverse")
         return out.reshape(nc, nc)  # row-major storage
 
-    def profile_begin(self, max_launches=65536):
-        L.check(self.lib.tpf_profile_begin(self.handle, int(max_launches)), "tpf_profile_begin")
+    def profile_begin(self, max_launches=65536, classes=None):
+        """Times every launch of the named kernel classes (all when None) with HIP events."""
+        mask = 0
+        for c in (classes or []):
+            mask |= 1 << L.KERNEL_CLASSES.index(c)
+        L.check(self.lib.tpf_profile_begin(self.handle, int(max_launches), mask), "tpf_profile_begin")
 
     def profile_end(self):
         arr = (L.KernelTime * len(L.KERNEL_CLASSES))()

@@ -90,7 +90,7 @@ _SIGS = {
     "tpf_precondition": (C.c_int32, [VP, DP, DP, VP]),
     "tpf_copy_coarse_inverse": (C.c_int32, [VP, DP, VP]),
     "tpf_pdmin_ptr": (VP, [VP]),
-    "tpf_profile_begin": (C.c_int32, [VP, C.c_int32]),
+    "tpf_profile_begin": (C.c_int32, [VP, C.c_int32, C.c_uint32]),
     "tpf_profile_end": (C.c_int32, [VP, C.POINTER(KernelTime)]),
 }
 

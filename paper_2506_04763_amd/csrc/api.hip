@@ -442,7 +442,7 @@ static void prof_release(tpf_grid *g) {
   p = Prof();
 }
 
-tpf_status tpf_profile_begin(tpf_grid *g, int32_t max_launches) {
+tpf_status tpf_profile_begin(tpf_grid *g, int32_t max_launches, uint32_t class_mask) {
   g_err[0] = 0;
   if (!g || max_launches < 1 || max_launches > (1 << 20)) { set_error("bad argument"); return TPF_EINVAL; }
   prof_release(g);
@@ -461,6 +461,7 @@ tpf_status tpf_profile_begin(tpf_grid *g, int32_t max_launches) {
   }
   p.cap = max_launches;
   p.used = 0;
+  p.mask = class_mask ? class_mask : ~0u;
   p.active = 1;
   return TPF_OK;
 }

@@ -15,35 +15,80 @@
 namespace tpf {
 namespace {
 
+// Offsets per group of the branch-free row product: every matrix block and x value
+// of a group is loaded before any of them is used, so a wave keeps a group's loads in
+// flight together instead of waiting on each offset in turn.
+#ifndef TPF_ROW_GROUP32
+#define TPF_ROW_GROUP32 9
+#endif
+#ifndef TPF_ROW_GROUP64
+#define TPF_ROW_GROUP64 9
+#endif
+
+typedef float tpf_f4 __attribute__((ext_vector_type(4)));
+typedef double tpf_d2 __attribute__((ext_vector_type(2)));
+
+// One 2x2 block; NT: non-temporal load for a matrix streamed once per sweep from HBM
+// (the finest level), which leaves the caches to the x gathers.
+template <typename T, bool NT>
+__device__ __forceinline__ void load_block(const T *p, T (&b)[4]) {
+  if constexpr (NT && sizeof(T) == 4) {
+    const tpf_f4 a = __builtin_nontemporal_load(reinterpret_cast<const tpf_f4 *>(p));
+    b[0] = a.x; b[1] = a.y; b[2] = a.z; b[3] = a.w;
+  } else if constexpr (NT) {
+    const tpf_d2 a = __builtin_nontemporal_load(reinterpret_cast<const tpf_d2 *>(p));
+    const tpf_d2 c = __builtin_nontemporal_load(reinterpret_cast<const tpf_d2 *>(p) + 1);
+    b[0] = a.x; b[1] = a.y; b[2] = c.x; b[3] = c.y;
+  } else {
+    Blk<T>::load(p, b);
+  }
+}
+
 // y = A x (row-block product) accumulated in the matrix type T for one vertex.
-// Returns (A x)_v; the centre block is copied out for the smoother.
-template <int DIM, typename T, typename TX>
+// Returns (A x)_v; the centre block is copied out for the smoother.  Neighbours
+// outside the grid have zero blocks; their x value is read at the clamped (valid)
+// position and masked to zero, so no load depends on a branch.
+template <int DIM, typename T, typename TX, bool NT = false>
 __device__ __forceinline__ void row_apply(const Geo &G, long long v, const T *__restrict__ A,
                                           const TX *__restrict__ x, T &y0, T &y1, T (&dblk)[4]) {
   constexpr int NST = DIM == 3 ? 27 : 9;
   constexpr int CEN = DIM == 3 ? 13 : 4;
+  constexpr int GRP0 = sizeof(T) == 4 ? TPF_ROW_GROUP32 : TPF_ROW_GROUP64;
+  constexpr int GRP = GRP0 > NST ? NST : GRP0;
+  static_assert(NST % GRP == 0, "group size must divide the stencil size");
   int ix, iy, iz;
   vcoords(v, G, ix, iy, iz);
-  const bool xm = ix > 0, xp = ix < G.nx - 1, ym = iy > 0, yp = iy < G.ny - 1;
-  const bool zm = DIM == 3 && iz > 0, zp = DIM == 3 && iz < G.nz - 1;
   const long long sy = G.nx, sz = (long long)G.nx * G.ny;
+  const bool okx[3] = {ix > 0, true, ix < G.nx - 1};
+  const bool oky[3] = {iy > 0, true, iy < G.ny - 1};
+  const bool okz[3] = {DIM == 3 && iz > 0, true, DIM == 3 && iz < G.nz - 1};
+  const long long offx[3] = {okx[0] ? -1 : 0, 0, okx[2] ? 1 : 0};
+  const long long offy[3] = {oky[0] ? -sy : 0, 0, oky[2] ? sy : 0};
+  const long long offz[3] = {okz[0] ? -sz : 0, 0, okz[2] ? sz : 0};
+  using X2 = typename Vec2<TX>::type;
   T a0 = 0, a1 = 0;
 #pragma unroll
-  for (int o = 0; o < NST; ++o) {
-    const int dx = o % 3 - 1, dy = (o / 3) % 3 - 1, dz = DIM == 3 ? o / 9 - 1 : 0;
-    T b[4];
-    Blk<T>::load(A + ((long long)o * G.N + v) * 4, b);
-    if (o == CEN) {
-      dblk[0] = b[0]; dblk[1] = b[1]; dblk[2] = b[2]; dblk[3] = b[3];
+  for (int g0 = 0; g0 < NST; g0 += GRP) {
+    T b[GRP][4];
+    X2 xv[GRP];
+#pragma unroll
+    for (int k = 0; k < GRP; ++k) {
+      const int o = g0 + k;
+      const int ax = o % 3, ay = (o / 3) % 3, az = DIM == 3 ? o / 9 : 1;
+      load_block<T, NT>(A + ((long long)o * G.N + v) * 4, b[k]);
+      xv[k] = *reinterpret_cast<const X2 *>(x + 2 * (v + offx[ax] + offy[ay] + offz[az]));
     }
-    const bool ok = (dx < 0 ? xm : (dx > 0 ? xp : true)) && (dy < 0 ? ym : (dy > 0 ? yp : true)) &&
-                    (dz < 0 ? zm : (dz > 0 ? zp : true));
-    if (ok) {
-      const long long vn = v + dx + sy * dy + sz * dz;
-      const auto xv = *reinterpret_cast<const typename Vec2<TX>::type *>(x + 2 * vn);
-      const T x0 = (T)xv.x, x1 = (T)xv.y;
-      a0 += b[0] * x0 + b[1] * x1;
-      a1 += b[2] * x0 + b[3] * x1;
+#pragma unroll
+    for (int k = 0; k < GRP; ++k) {
+      const int o = g0 + k;
+      const int ax = o % 3, ay = (o / 3) % 3, az = DIM == 3 ? o / 9 : 1;
+      if (o == CEN) {
+        dblk[0] = b[k][0]; dblk[1] = b[k][1]; dblk[2] = b[k][2]; dblk[3] = b[k][3];
+      }
+      const bool ok = okx[ax] && oky[ay] && okz[az];
+      const T x0 = ok ? (T)xv[k].x : (T)0, x1 = ok ? (T)xv[k].y : (T)0;
+      a0 += b[k][0] * x0 + b[k][1] * x1;
+      a1 += b[k][2] * x0 + b[k][3] * x1;
     }
   }
   y0 = a0;
@@ -108,15 +153,13 @@ __global__ void __launch_bounds__(BS) k_spmv64(const Geo G, const double *__rest
   if (MODE != 0) block_reduce_store<MODE == 2 ? 2 : 1>(acc, part, blk, gridDim.x);
 }
 
-// Damped block Jacobi sweep: xo = xi + omega D^{-1} (b - A xi); FIRST: xi = 0.
-template <int DIM, typename T, typename TO, bool FIRST>
-__global__ void __launch_bounds__(BS) k_jacobi(const Geo G, const T *__restrict__ A,
-                                               const T *__restrict__ b, const T *__restrict__ xi,
-                                               TO *__restrict__ xo, const T omega) {
+// Damped block Jacobi update of one vertex: xo = xi + omega D^{-1} (b - A xi);
+// FIRST: xi = 0, so only the diagonal block is read.
+template <int DIM, typename T, typename TO, bool FIRST, bool NT = false>
+__device__ __forceinline__ void jacobi_vertex(const Geo &G, const T *__restrict__ A, const T *__restrict__ b,
+                                              const T *__restrict__ xi, TO *__restrict__ xo, const T omega,
+                                              long long v) {
   constexpr int CEN = DIM == 3 ? 13 : 4;
-  const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
-  const long long v = (long long)blk * BS + threadIdx.x;
-  if (v >= G.N) return;
   const auto bb = *reinterpret_cast<const typename Vec2<T>::type *>(b + 2 * v);
   T r0, r1, d[4], x0 = 0, x1 = 0;
   if (FIRST) {
@@ -125,7 +168,7 @@ __global__ void __launch_bounds__(BS) k_jacobi(const Geo G, const T *__restrict_
     r1 = bb.y;
   } else {
     T a0, a1;
-    row_apply<DIM, T, T>(G, v, A, xi, a0, a1, d);
+    row_apply<DIM, T, T, NT>(G, v, A, xi, a0, a1, d);
     const auto xx = *reinterpret_cast<const typename Vec2<T>::type *>(xi + 2 * v);
     x0 = xx.x;
     x1 = xx.y;
@@ -140,20 +183,36 @@ __global__ void __launch_bounds__(BS) k_jacobi(const Geo G, const T *__restrict_
   *reinterpret_cast<typename Vec2<TO>::type *>(xo + 2 * v) = out;
 }
 
-// r = b - A x on a level.
-template <int DIM, typename T>
-__global__ void __launch_bounds__(BS) k_resid(const Geo G, const T *__restrict__ A, const T *__restrict__ b,
-                                              const T *__restrict__ x, T *__restrict__ r) {
+template <int DIM, typename T, typename TO, bool FIRST, bool NT = false>
+__global__ void __launch_bounds__(BS) k_jacobi(const Geo G, const T *__restrict__ A,
+                                               const T *__restrict__ b, const T *__restrict__ xi,
+                                               TO *__restrict__ xo, const T omega) {
   const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
   const long long v = (long long)blk * BS + threadIdx.x;
   if (v >= G.N) return;
+  jacobi_vertex<DIM, T, TO, FIRST, NT>(G, A, b, xi, xo, omega, v);
+}
+
+// r = b - A x at one vertex of a level.
+template <int DIM, typename T, bool NT = false>
+__device__ __forceinline__ void resid_vertex(const Geo &G, const T *__restrict__ A, const T *__restrict__ b,
+                                             const T *__restrict__ x, T *__restrict__ r, long long v) {
   T a0, a1, d[4];
-  row_apply<DIM, T, T>(G, v, A, x, a0, a1, d);
+  row_apply<DIM, T, T, NT>(G, v, A, x, a0, a1, d);
   const auto bb = *reinterpret_cast<const typename Vec2<T>::type *>(b + 2 * v);
   typename Vec2<T>::type o;
   o.x = bb.x - a0;
   o.y = bb.y - a1;
   *reinterpret_cast<typename Vec2<T>::type *>(r + 2 * v) = o;
+}
+
+template <int DIM, typename T, bool NT = false>
+__global__ void __launch_bounds__(BS) k_resid(const Geo G, const T *__restrict__ A, const T *__restrict__ b,
+                                              const T *__restrict__ x, T *__restrict__ r) {
+  const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
+  const long long v = (long long)blk * BS + threadIdx.x;
+  if (v >= G.N) return;
+  resid_vertex<DIM, T, NT>(G, A, b, x, r, v);
 }
 
 // Restriction bc = P^T rf.  Pressure component: (bi/tri)linear weights
@@ -357,20 +416,25 @@ __global__ void __launch_bounds__(64) k_lu_inverse(const double *__restrict__ lu
   for (int i = lane; i < n; i += 64) inv[(long long)i * n + j] = y[i];  // row-major
 }
 
-// x = A^{-1} b on the coarsest level: row-major inverse, one 64-lane wavefront per
-// row (coalesced row reads, fixed-order shuffle reduction).
+// Row r of x = A^{-1} b on the coarsest level (row-major inverse), computed by one
+// 64-lane wavefront: coalesced row reads and a fixed-order shuffle reduction.
 template <typename T>
-__global__ void __launch_bounds__(256) k_coarse_solve(const double *__restrict__ inv, int n,
-                                                      const T *__restrict__ b, T *__restrict__ x) {
-  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (r >= n) return;  // whole wavefront exits together
+__device__ __forceinline__ void coarse_row(const double *__restrict__ inv, int n, const T *__restrict__ b,
+                                           T *__restrict__ x, int r, int lane) {
   const double *row = inv + (long long)r * n;
   double s = 0.0;
   for (int c = lane; c < n; c += 64) s += row[c] * (double)b[c];
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
   if (lane == 0) x[r] = (T)s;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_coarse_solve(const double *__restrict__ inv, int n,
+                                                      const T *__restrict__ b, T *__restrict__ x) {
+  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= n) return;  // whole wavefront exits together
+  coarse_row<T>(inv, n, b, x, r, threadIdx.x & 63);
 }
 
 template <typename TI, typename TO>
@@ -398,6 +462,20 @@ tpf_status vcycle_t(tpf_grid *g, const double *bin, double *xout, hipStream_t s)
     if (sizeof(T) == sizeof(double)) return reinterpret_cast<const T *>(g->lv[l].A64);
     return reinterpret_cast<const T *>(g->lv[l].A32);
   };
+  constexpr bool NT0 = sizeof(T) == sizeof(float);  // finest FP32 matrix: streamed, non-temporal
+  if (L == 1) {  // single level: the dense solve is the whole cycle
+    Level &lc = g->lv[0];
+    T *X = sizeof(T) == sizeof(double) ? reinterpret_cast<T *>(xout) : reinterpret_cast<T *>(lc.x);
+    const int ps = prof_begin(g, TPF_K_COARSE_LEVELS, s);
+    k_coarse_solve<T><<<(g->nc + 3) / 4, 256, 0, s>>>(g->ainv, g->nc, b0, X);
+    TPF_LAUNCH_CHECK();
+    prof_end(g, ps, s);
+    if (sizeof(T) != sizeof(double)) {
+      k_cast<T, double><<<1024, BS, 0, s>>>(X, xout, 2 * lc.N);
+      TPF_LAUNCH_CHECK();
+    }
+    return TPF_OK;
+  }
   const T *bl[MAXL];
   T *cur[MAXL];
   bl[0] = b0;
@@ -412,7 +490,10 @@ tpf_status vcycle_t(tpf_grid *g, const double *bin, double *xout, hipStream_t s)
     prof_end(g, ps, s);
     for (int k = 1; k < g->nu_pre; ++k) {
       ps = prof_begin(g, l == 0 ? TPF_K_SMOOTH0 : TPF_K_COARSE_LEVELS, s);
-      k_jacobi<DIM, T, T, false><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, Y, om);
+      if (l == 0)
+        k_jacobi<DIM, T, T, false, NT0><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, Y, om);
+      else
+        k_jacobi<DIM, T, T, false><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, Y, om);
       TPF_LAUNCH_CHECK();
       prof_end(g, ps, s);
       T *t = X; X = Y; Y = t;
@@ -420,7 +501,10 @@ tpf_status vcycle_t(tpf_grid *g, const double *bin, double *xout, hipStream_t s)
     cur[l] = X;
     T *R = reinterpret_cast<T *>(lv.r);
     ps = prof_begin(g, l == 0 ? TPF_K_RESID0 : TPF_K_COARSE_LEVELS, s);
-    k_resid<DIM, T><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, R);
+    if (l == 0)
+      k_resid<DIM, T, NT0><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, R);
+    else
+      k_resid<DIM, T><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, R);
     TPF_LAUNCH_CHECK();
     prof_end(g, ps, s);
     Level &lc = g->lv[l + 1];
@@ -431,22 +515,15 @@ tpf_status vcycle_t(tpf_grid *g, const double *bin, double *xout, hipStream_t s)
     prof_end(g, ps, s);
     bl[l + 1] = bc;
   }
-  // coarsest level
+  // coarsest level: x = A^{-1} b, one wavefront per row of the inverse
   {
     Level &lc = g->lv[L - 1];
-    T *X = (L == 1 && sizeof(T) == sizeof(double)) ? reinterpret_cast<T *>(xout) : reinterpret_cast<T *>(lc.x);
+    T *X = reinterpret_cast<T *>(lc.x);
     const int ps = prof_begin(g, TPF_K_COARSE_LEVELS, s);
     k_coarse_solve<T><<<(g->nc + 3) / 4, 256, 0, s>>>(g->ainv, g->nc, bl[L - 1], X);
     TPF_LAUNCH_CHECK();
     prof_end(g, ps, s);
     cur[L - 1] = X;
-    if (L == 1) {
-      if (sizeof(T) != sizeof(double)) {
-        k_cast<T, double><<<1024, BS, 0, s>>>(X, xout, 2 * lc.N);
-        TPF_LAUNCH_CHECK();
-      }
-      return TPF_OK;
-    }
   }
   for (int l = L - 2; l >= 0; --l) {
     Level &lv = g->lv[l];
@@ -462,13 +539,16 @@ tpf_status vcycle_t(tpf_grid *g, const double *bin, double *xout, hipStream_t s)
     for (int k = 0; k < nu; ++k) {
       ps = prof_begin(g, l == 0 ? TPF_K_SMOOTH0 : TPF_K_COARSE_LEVELS, s);
       if (l == 0 && k == nu - 1) {
-        k_jacobi<DIM, T, double, false><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, xout, om);
+        k_jacobi<DIM, T, double, false, NT0><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, xout, om);
         TPF_LAUNCH_CHECK();
         prof_end(g, ps, s);
         X = nullptr;
         break;
       }
-      k_jacobi<DIM, T, T, false><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, Y, om);
+      if (l == 0)
+        k_jacobi<DIM, T, T, false, NT0><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, Y, om);
+      else
+        k_jacobi<DIM, T, T, false><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, Y, om);
       TPF_LAUNCH_CHECK();
       prof_end(g, ps, s);
       T *t = X; X = Y; Y = t;

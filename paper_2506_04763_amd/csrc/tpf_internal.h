@@ -49,6 +49,7 @@ struct Patches {
 // Event timer of selected launch classes (host state only).
 struct Prof {
   int active = 0, cap = 0, used = 0;
+  unsigned mask = ~0u;       // classes timed
   hipEvent_t *ev = nullptr;  // 2 * cap
   int *cls = nullptr;        // cap
 };
@@ -99,7 +100,7 @@ namespace tpf {
 // Records the start event of a timed launch of class `c`; returns the slot or -1.
 inline int prof_begin(tpf_grid *g, int c, hipStream_t s) {
   Prof &p = g->prof;
-  if (!p.active || p.used >= p.cap) return -1;
+  if (!p.active || p.used >= p.cap || !((p.mask >> c) & 1u)) return -1;
   const int i = p.used++;
   p.cls[i] = c;
   if (hipEventRecord(p.ev[2 * i], s) != hipSuccess) return -1;
