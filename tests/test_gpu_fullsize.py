@@ -1,0 +1,233 @@
+"""Full-size parity of the HIP path, in the configuration the benchmark times.
+
+Workloads: the 129^3 log-normal cube (sigma_lnK 2, mixed precision, 6 levels, rtol
+1e-8: the benchmark's stage), the 65^3 cube (sigma_lnK 1, FP64, 5 levels, rtol 1e-10)
+and the 257^3 layered cube (mixed, 6 levels, LIMEX k = 3).  These grids are too large
+for the whole-grid oracle inside a test, so
+
+  * residual and stage-matrix rows are compared at sampled vertices (corners, edges,
+    faces, injection-patch edges, next to Dirichlet faces, seeded interior vertices)
+    with the oracle run on a window reaching two cells past each sample, which
+    reproduces the full grid's rows exactly (tests/test_window.py);
+  * rows of the first Galerkin coarse operator likewise, from windows of +-4 fine
+    vertices around 2I;
+  * the solution is checked by the property that defines it, ||f - A x|| <= rtol ||f||
+    with A x evaluated by plain PyTorch on the assembled matrix, and against the
+    oracle's own solution at sampled vertices where a committed script stored it
+    (tests/golden/make_fullsize_reference.py).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import stage as ST
+from tests._window import local_index, row_window, sample_vertices, vertex_index, window
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+tpf = pytest.importorskip("paper_2506_04763_amd")
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+H = 32.0
+CONFIGS = {
+    "cube129_mixed": dict(make=W.cube_c3, precision="mixed", levels=6, rtol=1e-8, n_random=40, n_coarse=10,
+                          golden="cube129_stage_solution.json", sol_tol=2e-5),
+    "cube65_fp64": dict(make=W.cube_c2, precision="fp64", levels=5, rtol=1e-10, n_random=40, n_coarse=10,
+                        golden="cube65_stage_solution.json", sol_tol=1e-8),
+}
+
+
+def stencil_apply(A, x, n):
+    """y = A x for stencil blocks A (27, N, 4) and x (N, 2), plain PyTorch, FP64."""
+    nx, ny, nz = n
+    X = x.reshape(nz, ny, nx, 2)
+    Xp = torch.nn.functional.pad(X.permute(3, 0, 1, 2), (1, 1, 1, 1, 1, 1)).permute(1, 2, 3, 0)
+    y = torch.zeros_like(x)
+    for o in range(27):
+        dx, dy, dz = o % 3 - 1, (o // 3) % 3 - 1, o // 9 - 1
+        xs = Xp[1 + dz:1 + dz + nz, 1 + dy:1 + dy + ny, 1 + dx:1 + dx + nx].reshape(-1, 2)
+        a = A[o]
+        y[:, 0] += a[:, 0] * xs[:, 0] + a[:, 1] * xs[:, 1]
+        y[:, 1] += a[:, 2] * xs[:, 0] + a[:, 3] * xs[:, 1]
+    return y
+
+
+@pytest.fixture(scope="module", params=sorted(CONFIGS), ids=sorted(CONFIGS))
+def stage(request):
+    name = request.param
+    cfg = CONFIGS[name]
+    scn = cfg["make"]()
+    print(f"[fullsize] {name} n={scn.n} precision={cfg['precision']}", flush=True)
+    g = tpf.Grid(scn, precision=cfg["precision"], levels=cfg["levels"])
+    u0 = g.initial_state()
+    f = g.empty()
+    g.assemble_stage(u0, H, f0_out=f)
+    x, st = g.solve_stage(f, rtol=cfg["rtol"], maxit=500)
+    torch.cuda.synchronize()
+    yield dict(name=name, cfg=cfg, scn=scn, g=g, f=f, x=x, st=st)
+    g.close()
+    torch.cuda.empty_cache()
+
+
+def check_fine_rows(scn, g, u, f, samples, mixed, label):
+    """Sampled rows of F (f: device F(u) from assemble_stage) and of the assembled
+    stage matrix against the windowed oracle at state u (host (N, 2))."""
+    gidx = torch.as_tensor([vertex_index(scn, v) for v in samples], device="cuda")
+    A = g.matrix(0)
+    blocks = A[:, gidx, :].cpu().numpy()                      # (27, S, 4)
+    del A
+    blocks32 = g.matrix(0, "mixed")[:, gidx, :].cpu().numpy() if mixed else None
+    F = f.reshape(-1, 2)[gidx].cpu().numpy()
+    Fref = np.zeros_like(F)
+    worst = 0.0
+    for s, v in enumerate(samples):
+        lo, hi = row_window(scn, v, 2)
+        w = window(scn, lo, hi, u=u)
+        st = ST.Stage(w, levels=1)
+        Aw = st.assemble(w.u0.ravel(), H).tocsr()
+        Fw = st.residual(w.u0.ravel())
+        lv = local_index(lo, hi, v)
+        Fref[s] = Fw[2 * lv:2 * lv + 2]
+        for r in (0, 1):
+            scale = abs(Aw[2 * lv + r].data).max()
+            for o in range(27):
+                d = (o % 3 - 1, (o // 3) % 3 - 1, o // 9 - 1)
+                nb = [v[a] + d[a] for a in range(3)]
+                inside = all(0 <= nb[a] < scn.n[a] for a in range(3))
+                for c in (0, 1):
+                    got = blocks[o, s, 2 * r + c]
+                    if not inside:
+                        assert got == 0.0
+                        continue
+                    ref = Aw[2 * lv + r, 2 * local_index(lo, hi, nb) + c]
+                    err = abs(got - ref) / scale
+                    worst = max(worst, err)
+                    assert err <= 1e-11, (v, o, r, c, got, ref)
+        if blocks32 is not None:
+            np.testing.assert_array_equal(blocks32[:, s, :], blocks[:, s, :].astype(np.float32))
+    for c in (0, 1):  # residual per field, relative to the largest sampled value (a field
+        # that is zero at equilibrium, the wetting balance of a hydrostatic state, is held
+        # to the scale of the other)
+        scale = max(abs(Fref[:, c]).max(), abs(Fref).max(), 1e-300)
+        assert abs(F[:, c] - Fref[:, c]).max() <= 1e-11 * scale, (c, abs(F[:, c] - Fref[:, c]).max(), scale)
+    print(f"[fullsize] {label}: {len(samples)} sampled rows, max rel err {worst:.2e}", flush=True)
+
+
+def test_sampled_fine_rows(stage):
+    scn = stage["scn"]
+    samples = sample_vertices(scn, stage["cfg"]["n_random"], seed=5)
+    check_fine_rows(scn, stage["g"], scn.u0.reshape(-1, 2), stage["f"], samples,
+                    stage["cfg"]["precision"] == "mixed", stage["name"])
+
+
+def test_sampled_coarse_rows(stage):
+    scn, g = stage["scn"], stage["g"]
+    nc = g.level_dims(1)
+    rng = np.random.default_rng(8)
+    picks = {(0, 0, 0), (nc[0] - 1, nc[1] - 1, nc[2] - 1), (nc[0] - 1, 0, nc[2] // 2), (0, nc[1] // 2, nc[2] - 1)}
+    while len(picks) < stage["cfg"]["n_coarse"]:
+        picks.add(tuple(int(rng.integers(0, nc[a])) for a in range(3)))
+    picks = sorted(picks)
+    gi = torch.as_tensor([I[0] + nc[0] * (I[1] + nc[1] * I[2]) for I in picks], device="cuda")
+    blocks = g.matrix(1)[:, gi, :].cpu().numpy()
+    u = scn.u0.reshape(-1, 2)
+    for s, I in enumerate(picks):
+        v = tuple(2 * I[a] for a in range(3))
+        lo, hi = row_window(scn, v, 4)
+        w = window(scn, lo, hi, u=u, levels=2)
+        st = ST.Stage(w, levels=2)
+        st.assemble(w.u0.ravel(), H)
+        A1 = st.H.A[1].tocsr()
+        ncw = [(w.n[a] - 1) // 2 + 1 for a in range(3)]
+        clo = [lo[a] // 2 for a in range(3)]
+        li = (I[0] - clo[0]) + ncw[0] * ((I[1] - clo[1]) + ncw[1] * (I[2] - clo[2]))
+        for r in (0, 1):
+            scale = abs(A1[2 * li + r].data).max()
+            for o in range(27):
+                d = (o % 3 - 1, (o // 3) % 3 - 1, o // 9 - 1)
+                J = [I[a] + d[a] for a in range(3)]
+                if not all(0 <= J[a] < nc[a] for a in range(3)):
+                    assert blocks[o, s, 2 * r] == 0.0 and blocks[o, s, 2 * r + 1] == 0.0
+                    continue
+                lj = (J[0] - clo[0]) + ncw[0] * ((J[1] - clo[1]) + ncw[1] * (J[2] - clo[2]))
+                for c in (0, 1):
+                    ref = A1[2 * li + r, 2 * lj + c]
+                    assert abs(blocks[o, s, 2 * r + c] - ref) <= 1e-11 * scale, (I, o, r, c)
+
+
+def test_solution_satisfies_system(stage):
+    scn, g = stage["scn"], stage["g"]
+    rtol = stage["cfg"]["rtol"]
+    st = stage["st"]
+    assert st["status"] == "TPF_OK"
+    A = g.matrix(0)
+    x = stage["x"].reshape(-1, 2)
+    f = stage["f"].reshape(-1, 2)
+    r = f - stencil_apply(A, x, scn.n)
+    rel = float(torch.linalg.norm(r) / torch.linalg.norm(f))
+    del A
+    print(f"[fullsize] {stage['name']}: {st['iters']} iterations, ||f - A x||/||f|| = {rel:.3e} "
+          f"(library: {st['rel_res_true']:.3e})", flush=True)
+    assert rel <= rtol * 1.0001
+    # the two evaluations of f - A x differ in summation order: ~ eps ||A|| ||x|| / ||f||
+    assert abs(rel - st["rel_res_true"]) <= 1e-6 * rel + 1e-14
+
+
+def test_solution_matches_oracle_samples(stage):
+    path = os.path.join(GOLDEN, stage["cfg"]["golden"])
+    if not os.path.exists(path):
+        pytest.skip(f"{os.path.basename(path)} not generated (tests/golden/make_fullsize_reference.py)")
+    ref = json.load(open(path))
+    idx = torch.as_tensor([s[0] for s in ref["samples"]], device="cuda")
+    xs = stage["x"].reshape(-1, 2)[idx].cpu().numpy()
+    want = np.array([[s[1], s[2]] for s in ref["samples"]])
+    err = [float(abs(xs[:, c] - want[:, c]).max() / ref["norm_inf"][c]) for c in (0, 1)]
+    print(f"[fullsize] {stage['name']}: sampled per-field error vs oracle (inf-norm relative) "
+          f"p_w {err[0]:.2e}, S_n {err[1]:.2e}", flush=True)
+    assert max(err) <= stage["cfg"]["sol_tol"]
+
+
+def test_sampled_rows_perturbed_state(stage):
+    """Same grid and launch, state with S_n in [0.02, 0.6] and perturbed pressure, so
+    every interface case and both upwind directions occur (runs last: re-assembles)."""
+    scn, g = stage["scn"], stage["g"]
+    u = W.perturbed_state(scn, 9, sn_lo=0.02, sn_hi=0.6)
+    f = g.empty()
+    g.assemble_stage(torch.as_tensor(u.ravel(), device="cuda"), H, f0_out=f)
+    samples = sample_vertices(scn, 20, seed=6)
+    check_fine_rows(scn, g, u.reshape(-1, 2), f, samples, stage["cfg"]["precision"] == "mixed",
+                    stage["name"] + " perturbed")
+
+
+def test_cube257_limex_first_step():
+    """The 257^3 layered cube: sampled stage-matrix rows at the initial state and one
+    LIMEX step with k = 3 (three assemblies, six solves) from tau0 = 32 s."""
+    scn = W.cube_c4()
+    print(f"[fullsize] cube257 n={scn.n}", flush=True)
+    g = tpf.Grid(scn, precision="mixed", levels=6, limex_stages=3)
+    u0 = g.initial_state()
+    f = g.empty()
+    g.assemble_stage(u0, H, f0_out=f)
+    samples = sample_vertices(scn, 12, seed=7)
+    check_fine_rows(scn, g, scn.u0.reshape(-1, 2), f, samples, True, "cube257")
+    u = u0.clone()
+    tol, safety, dt_max = 5e-3, 0.75, 8.64e6
+    acc, t, dt_next, st = g.limex_step(u, 0.0, H, stages=3, tol=tol, safety=safety, dt_max=dt_max, rtol=1e-8)
+    print(f"[fullsize] cube257 LIMEX step: accepted={acc} eps={st['eps']:.3e} dt_next={dt_next:.4g} "
+          f"solves={st['solves']} iterations={st['iters_total']}", flush=True)
+    assert st["solves"] == 6 and st["unconverged"] == 0
+    assert np.isfinite(st["eps"]) and st["eps"] >= 0.0
+    want = dt_max if st["eps"] == 0.0 else min(dt_max, H * (safety * tol / st["eps"]) ** (1.0 / 3.0))
+    assert dt_next == pytest.approx(want, rel=1e-12)
+    assert acc == (st["eps"] <= tol)
+    if acc:
+        assert t == H
+        assert bool(torch.isfinite(u).all())
+        assert float((u - u0).abs().max()) > 0.0
+    else:
+        assert t == 0.0 and bool(torch.equal(u, u0))
+    g.close()
+    torch.cuda.empty_cache()
