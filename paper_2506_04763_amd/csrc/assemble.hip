@@ -40,24 +40,95 @@ __host__ __device__ __forceinline__ void eff_sat(double sn, const Phys &P, doubl
   }
 }
 
+// Natural logarithm of a positive, finite, normal x: x = m 2^e with m in
+// [sqrt(1/2), sqrt(2)), log m = 2 atanh(s) = 2 (s + s^3/3 + s^5/5 + ...) with
+// s = (m - 1)/(m + 1), |s| <= 0.172, so terms up to s^25 reach double precision
+// (a few ulp overall); log 2 is split into a high part exact in 32 bits and the rest.
+__host__ __device__ __forceinline__ double log_pos(double x) {
+  int e;
+  double m = frexp(x, &e);  // m in [0.5, 1)
+  if (m < 0.70710678118654752) {
+    m *= 2.0;
+    e -= 1;
+  }
+  const double s = (m - 1.0) / (m + 1.0);
+  const double z = s * s;
+  double q = 1.0 / 25.0;
+  q = fma(q, z, 1.0 / 23.0);
+  q = fma(q, z, 1.0 / 21.0);
+  q = fma(q, z, 1.0 / 19.0);
+  q = fma(q, z, 1.0 / 17.0);
+  q = fma(q, z, 1.0 / 15.0);
+  q = fma(q, z, 1.0 / 13.0);
+  q = fma(q, z, 1.0 / 11.0);
+  q = fma(q, z, 1.0 / 9.0);
+  q = fma(q, z, 1.0 / 7.0);
+  q = fma(q, z, 1.0 / 5.0);
+  q = fma(q, z, 1.0 / 3.0);
+  const double lm = 2.0 * s + 2.0 * s * z * q;
+  constexpr double LN2_HI = 0.693147180369123816490;    // 32 significant bits
+  constexpr double LN2_LO = 1.90821492927058770002e-10;  // log 2 - LN2_HI
+  return fma((double)e, LN2_HI, fma((double)e, LN2_LO, lm));
+}
+
+// exp(x) for finite x: x = k log 2 + r with k = round(x / log 2), |r| <= log(2)/2
+// (reduction with the split log 2), exp(r) by its Taylor series to r^14/14!, scaled
+// by 2^k (overflow gives inf, underflow 0 or a subnormal).
+__host__ __device__ __forceinline__ double exp_fin(double x) {
+  constexpr double LN2_HI = 0.693147180369123816490;
+  constexpr double LN2_LO = 1.90821492927058770002e-10;
+  const double k = rint(x * 1.44269504088896340736);
+  const double r = fma(-k, LN2_LO, fma(-k, LN2_HI, x));
+  double q = 1.0 / 87178291200.0;           // 1/14!
+  q = fma(q, r, 1.0 / 6227020800.0);        // 1/13!
+  q = fma(q, r, 1.0 / 479001600.0);
+  q = fma(q, r, 1.0 / 39916800.0);
+  q = fma(q, r, 1.0 / 3628800.0);
+  q = fma(q, r, 1.0 / 362880.0);
+  q = fma(q, r, 1.0 / 40320.0);
+  q = fma(q, r, 1.0 / 5040.0);
+  q = fma(q, r, 1.0 / 720.0);
+  q = fma(q, r, 1.0 / 120.0);
+  q = fma(q, r, 1.0 / 24.0);
+  q = fma(q, r, 1.0 / 6.0);
+  q = fma(q, r, 0.5);
+  q = fma(q, r, 1.0);
+  q = fma(q, r, 1.0);
+  return ldexp(q, (int)k);
+}
+
+// Every Brooks-Corey / Burdine power of one effective saturation follows from
+// t = S_e^(1/lam), one log and one exp: p_c = p_d / t, S_e^((2+lam)/lam) = S_e t^2,
+// S_e^((2+3 lam)/lam) = S_e^3 t^2 (S_e >= 1e-6, so the log is finite).
+__host__ __device__ __forceinline__ double root_lam(double se, double inv_lam) {
+  return exp_fin(log_pos(se) * inv_lam);
+}
+
 // Burdine wetting relative permeability and its derivative w.r.t. S_n.
-__host__ __device__ __forceinline__ void krw(double sn, double lam, const Phys &P, double &k, double &dk) {
+__host__ __device__ __forceinline__ void krw(double sn, double inv_lam, const Phys &P, double &k, double &dk) {
   double se, dse;
   eff_sat(sn, P, se, dse);
-  const double e = (2.0 + 3.0 * lam) / lam;
-  k = pow(se, e);
-  dk = e * (k / se) * dse;
+  const double t = root_lam(se, inv_lam);
+  k = se * se * se * t * t;
+  dk = (3.0 + 2.0 * inv_lam) * (k / se) * dse;
+}
+
+// Burdine non-wetting relative permeability from S_e and t = S_e^(1/lam), and its
+// derivative w.r.t. S_e.
+__host__ __device__ __forceinline__ void krn_se(double se, double t, double inv_lam, double &k, double &dk_dse) {
+  const double sa = se * t * t;
+  const double om = 1.0 - se;
+  k = om * om * (1.0 - sa);
+  dk_dse = -2.0 * om * (1.0 - sa) - om * om * (1.0 + 2.0 * inv_lam) * t * t;
 }
 
 // Burdine non-wetting relative permeability and its derivative w.r.t. S_n.
-__host__ __device__ __forceinline__ void krn(double sn, double lam, const Phys &P, double &k, double &dk) {
+__host__ __device__ __forceinline__ void krn(double sn, double inv_lam, const Phys &P, double &k, double &dk) {
   double se, dse;
   eff_sat(sn, P, se, dse);
-  const double a = (2.0 + lam) / lam;
-  const double sa = pow(se, a);
-  const double om = 1.0 - se;
-  k = om * om * (1.0 - sa);
-  dk = (-2.0 * om * (1.0 - sa) - om * om * a * (sa / se)) * dse;
+  double dk_dse;
+  krn_se(se, root_lam(se, inv_lam), inv_lam, k, dk_dse);
+  dk = dk_dse * dse;
 }
 
 // ---------------------------------------------------------------------------------
@@ -122,7 +193,7 @@ __host__ __device__ __forceinline__ void vertex_pc(const long long v, const Phys
   double se, dse;
   eff_sat(u[2 * v + 1], P, se, dse);
   const double lr = lamref[v];
-  const double pc = pdmin[v] * pow(se, -1.0 / lr);
+  const double pc = pdmin[v] / root_lam(se, 1.0 / lr);
   pv[2 * v] = pc;
   pv[2 * v + 1] = pc * (-1.0 / lr) / se * dse;
 }
@@ -176,7 +247,8 @@ __host__ __device__ __forceinline__ void accumulate_cells(const long long v, con
       if (ox < 0 || oy < 0 || oz < 0 || ox >= P.ncx || oy >= P.ncy || oz >= P.ncz) return;
       const long long c = ox + (long long)P.ncx * (oy + (long long)P.ncy * oz);
       const double Ke = in.Kc[c], phie = in.phic[c], pde = in.pdc[c], lame = in.lamc[c];
-      double p[NC], sn[NC], sh[NC], dsh[NC], pc[NC], dpc[NC];
+      const double il = 1.0 / lame;
+      double p[NC], sn[NC], sh[NC], dsh[NC], pc[NC], dpc[NC], khn[NC], dkhn[NC];
 #pragma unroll
       for (int l = 0; l < NC; ++l) {
         const int dx = bit(l, 0) - bit(cc, 0), dy = bit(l, 1) - bit(cc, 1);
@@ -193,14 +265,19 @@ __host__ __device__ __forceinline__ void accumulate_cells(const long long v, con
         } else if (pde >= pvl.x) {
           sh[l] = P.snr; dsh[l] = 0.0;
         } else {
-          const double ses = pow(pvl.x / pde, -lame);
+          const double ses = exp_fin(-lame * log_pos(pvl.x / pde));
           sh[l] = 1.0 - (P.swr + ses * P.D);
           dsh[l] = -P.D * (-lame * ses / pvl.x * pvl.y);
         }
         double se, dse;
         eff_sat(sh[l], P, se, dse);
-        pc[l] = pde * pow(se, -1.0 / lame);
-        dpc[l] = pc[l] * (-1.0 / lame) / se * dse * dsh[l];
+        const double t = root_lam(se, il);
+        pc[l] = pde / t;
+        dpc[l] = pc[l] * (-il) / se * dse * dsh[l];
+        // non-wetting mobility of the corner at its hat saturation (for upwinding)
+        double dk_dse;
+        krn_se(se, t, il, khn[l], dk_dse);
+        dkhn[l] = dk_dse * dse;
       }
       // storage of the sub-control volume (vertex, cell): only dM/dS_n is non-zero
       mwS -= phie * rw * P.scv * dsh[cc];
@@ -240,18 +317,17 @@ __host__ __device__ __forceinline__ void accumulate_cells(const long long v, con
         const double phw = cw * (dp - rw * ga);
         const bool upw0 = phw >= 0.0;
         double kw, dkw;
-        krw(upw0 ? sn[l0] : sn[l1], lame, P, kw, dkw);
+        krw(upw0 ? sn[l0] : sn[l1], il, P, kw, dkw);
         const double fw = rw * kw * phw;
         // non-wetting phase, upwinded hat saturation
         const double cn = -(Ke / P.mu_n) * area;
         const double phn = cn * (dp - rn * ga);
         const bool upn0 = phn >= 0.0;
-        double kn, dkn;
-        krn(upn0 ? sh[l0] : sh[l1], lame, P, kn, dkn);
+        const double kn = upn0 ? khn[l0] : khn[l1], dkn = upn0 ? dkhn[l0] : dkhn[l1];
         const double fn = rn * kn * phn;
         // capillary diffusion, central
         double kip, dkip;
-        krn(sip, lame, P, kip, dkip);
+        krn(sip, il, P, kip, dkip);
         const double cc_ = -rn * (Ke / P.mu_n) * area;
         const double fc = cc_ * kip * gpc;
         Fw += sgn * fw;

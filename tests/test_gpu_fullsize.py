@@ -24,6 +24,7 @@ import pytest
 
 import workloads as W
 from oracle import stage as ST
+from oracle.fv import FV
 from tests._window import local_index, row_window, sample_vertices, vertex_index, window
 
 pytestmark = pytest.mark.gpu
@@ -86,9 +87,9 @@ def check_fine_rows(scn, g, u, f, samples, mixed, label):
     for s, v in enumerate(samples):
         lo, hi = row_window(scn, v, 2)
         w = window(scn, lo, hi, u=u)
-        st = ST.Stage(w, levels=1)
-        Aw = st.assemble(w.u0.ravel(), H).tocsr()
-        Fw = st.residual(w.u0.ravel())
+        fv = FV(w)  # fine rows only: no hierarchy of the window
+        Aw = fv.stage_matrix(w.u0, H).tocsr()
+        Fw = fv.residual(w.u0).ravel()
         lv = local_index(lo, hi, v)
         Fref[s] = Fw[2 * lv:2 * lv + 2]
         for r in (0, 1):

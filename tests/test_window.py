@@ -10,6 +10,7 @@ import pytest
 
 import workloads as W
 from oracle import stage as ST
+from oracle.fv import FV
 from tests._window import local_index, row_window, sample_vertices, vertex_index, window
 
 CASES = [
@@ -35,9 +36,9 @@ def test_fine_rows_from_windows(full):
     for v in sample_vertices(scn, 6, seed=1):
         lo, hi = row_window(scn, v, 2)
         w = window(scn, lo, hi, u=u)
-        st = ST.Stage(w, levels=1)
-        Aw = st.assemble(w.u0.ravel(), 32.0).tocsr()
-        Fw = st.residual(w.u0.ravel())
+        fv = FV(w)
+        Aw = fv.stage_matrix(w.u0, 32.0).tocsr()
+        Fw = fv.residual(w.u0).ravel()
         gv, lv = vertex_index(scn, v), local_index(lo, hi, v)
         for r in (0, 1):
             np.testing.assert_allclose(Fw[2 * lv + r], full["F"][2 * gv + r], rtol=1e-13, atol=1e-13 * abs(full["F"]).max())
