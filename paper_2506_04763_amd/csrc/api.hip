@@ -132,7 +132,8 @@ void layout(const tpf_grid_desc *d, Layout &L) {
   for (int l = 0; l < L.L; ++l) {
     L.off_lv[l] = o;
     o += align_up((size_t)L.nst * 4 * L.Nl[l] * sizeof(double));
-    if (d->precision == TPF_MIXED) o += align_up((size_t)L.nst * 4 * L.Nl[l] * sizeof(float));
+    if (d->precision == TPF_MIXED)  // the finest FP32 copy is tiled (padded to whole tiles of 64)
+      o += align_up((size_t)(l == 0 ? tiled_blocks(L.Nl[0], L.nst) : L.nst * L.Nl[l]) * 4 * sizeof(float));
     o += align_up(2 * L.Nl[l] * sizeof(double));
     o += 4 * align_up(2 * L.Nl[l] * vsz);
   }
@@ -240,7 +241,8 @@ tpf_status tpf_create_grid(const tpf_grid_desc *d, void *arena, size_t arena_byt
     o = L.off_lv[l];
     lv.A64 = reinterpret_cast<double *>(base + o); o += align_up((size_t)L.nst * 4 * lv.N * sizeof(double));
     if (d->precision == TPF_MIXED) {
-      lv.A32 = reinterpret_cast<float *>(base + o); o += align_up((size_t)L.nst * 4 * lv.N * sizeof(float));
+      lv.A32 = reinterpret_cast<float *>(base + o);
+      o += align_up((size_t)(l == 0 ? tiled_blocks(lv.N, L.nst) : L.nst * lv.N) * 4 * sizeof(float));
     }
     lv.mst = reinterpret_cast<double *>(base + o); o += align_up(2 * lv.N * sizeof(double));
     lv.x = base + o; o += align_up(2 * lv.N * vsz);
@@ -399,6 +401,7 @@ tpf_status tpf_copy_matrix(tpf_grid *g, int32_t level, int32_t precision, void *
   if (precision == TPF_FP64) {
     TPF_HIP(hipMemcpyAsync(dst, lv.A64, cnt * sizeof(double), hipMemcpyDeviceToDevice, s));
   } else if (precision == TPF_MIXED && g->prec == TPF_MIXED) {
+    if (level == 0) return untile_matrix32(g, reinterpret_cast<float *>(dst), s);
     TPF_HIP(hipMemcpyAsync(dst, lv.A32, cnt * sizeof(float), hipMemcpyDeviceToDevice, s));
   } else {
     set_error("no FP32 matrix on an FP64 grid");

@@ -410,7 +410,7 @@ __host__ __device__ __forceinline__ void finish_vertex(const long long v, const 
     reinterpret_cast<double2 *>(dst)[1] = make_double2(acc[k][2], acc[k][3]);
     if (W32) {
       float4 f4 = make_float4((float)acc[k][0], (float)acc[k][1], (float)acc[k][2], (float)acc[k][3]);
-      *reinterpret_cast<float4 *>(A32 + ((long long)o * P.N + v) * 4) = f4;
+      *reinterpret_cast<float4 *>(A32 + tiled_block(o, v, DIM == 3 ? 27 : 9) * 4) = f4;
     }
   }
 }

@@ -48,7 +48,7 @@ __device__ __forceinline__ void load_block(const T *p, T (&b)[4]) {
 // Returns (A x)_v; the centre block is copied out for the smoother.  Neighbours
 // outside the grid have zero blocks; their x value is read at the clamped (valid)
 // position and masked to zero, so no load depends on a branch.
-template <int DIM, typename T, typename TX, bool NT = false>
+template <int DIM, typename T, typename TX, bool NT = false, bool TILED = false>
 __device__ __forceinline__ void row_apply(const Geo &G, long long v, const T *__restrict__ A,
                                           const TX *__restrict__ x, T &y0, T &y1, T (&dblk)[4]) {
   constexpr int NST = DIM == 3 ? 27 : 9;
@@ -75,7 +75,7 @@ __device__ __forceinline__ void row_apply(const Geo &G, long long v, const T *__
     for (int k = 0; k < GRP; ++k) {
       const int o = g0 + k;
       const int ax = o % 3, ay = (o / 3) % 3, az = DIM == 3 ? o / 9 : 1;
-      load_block<T, NT>(A + ((long long)o * G.N + v) * 4, b[k]);
+      load_block<T, NT>(A + (TILED ? tiled_block(o, v, NST) : (long long)o * G.N + v) * 4, b[k]);
       xv[k] = *reinterpret_cast<const X2 *>(x + 2 * (v + offx[ax] + offy[ay] + offz[az]));
     }
 #pragma unroll
@@ -155,20 +155,21 @@ __global__ void __launch_bounds__(BS) k_spmv64(const Geo G, const double *__rest
 
 // Damped block Jacobi update of one vertex: xo = xi + omega D^{-1} (b - A xi);
 // FIRST: xi = 0, so only the diagonal block is read.
-template <int DIM, typename T, typename TO, bool FIRST, bool NT = false>
+template <int DIM, typename T, typename TO, bool FIRST, bool NT = false, bool TILED = false>
 __device__ __forceinline__ void jacobi_vertex(const Geo &G, const T *__restrict__ A, const T *__restrict__ b,
                                               const T *__restrict__ xi, TO *__restrict__ xo, const T omega,
                                               long long v) {
   constexpr int CEN = DIM == 3 ? 13 : 4;
-  const auto bb = *reinterpret_cast<const typename Vec2<T>::type *>(b + 2 * v);
   T r0, r1, d[4], x0 = 0, x1 = 0;
   if (FIRST) {
-    Blk<T>::load(A + ((long long)CEN * G.N + v) * 4, d);
+    Blk<T>::load(A + (TILED ? tiled_block(CEN, v, DIM == 3 ? 27 : 9) : (long long)CEN * G.N + v) * 4, d);
+    const auto bb = *reinterpret_cast<const typename Vec2<T>::type *>(b + 2 * v);
     r0 = bb.x;
     r1 = bb.y;
   } else {
     T a0, a1;
-    row_apply<DIM, T, T, NT>(G, v, A, xi, a0, a1, d);
+    row_apply<DIM, T, T, NT, TILED>(G, v, A, xi, a0, a1, d);
+    const auto bb = *reinterpret_cast<const typename Vec2<T>::type *>(b + 2 * v);
     const auto xx = *reinterpret_cast<const typename Vec2<T>::type *>(xi + 2 * v);
     x0 = xx.x;
     x1 = xx.y;
@@ -183,28 +184,56 @@ __device__ __forceinline__ void jacobi_vertex(const Geo &G, const T *__restrict_
   *reinterpret_cast<typename Vec2<TO>::type *>(xo + 2 * v) = out;
 }
 
-template <int DIM, typename T, typename TO, bool FIRST, bool NT = false>
+template <int DIM, typename T, typename TO, bool FIRST, bool NT = false, bool TILED = false>
 __global__ void __launch_bounds__(BS) k_jacobi(const Geo G, const T *__restrict__ A,
                                                const T *__restrict__ b, const T *__restrict__ xi,
                                                TO *__restrict__ xo, const T omega) {
   const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
   const long long v = (long long)blk * BS + threadIdx.x;
   if (v >= G.N) return;
-  jacobi_vertex<DIM, T, TO, FIRST, NT>(G, A, b, xi, xo, omega, v);
+  jacobi_vertex<DIM, T, TO, FIRST, NT, TILED>(G, A, b, xi, xo, omega, v);
+}
+
+// The finest-level FP32 sweeps stream a matrix far larger than the caches: they
+// use non-temporal matrix loads and a register budget that keeps enough wavefronts
+// per SIMD in flight to cover HBM latency.
+#ifndef TPF_STREAM_WAVES
+#define TPF_STREAM_WAVES 0
+#endif
+#if TPF_STREAM_WAVES > 0
+#define TPF_STREAM_ATTR __attribute__((amdgpu_waves_per_eu(TPF_STREAM_WAVES, 8)))
+#else
+#define TPF_STREAM_ATTR
+#endif
+
+template <int DIM, typename T, typename TO>
+__global__ void __launch_bounds__(BS) TPF_STREAM_ATTR k_jacobi_stream(const Geo G, const T *__restrict__ A,
+                                                                      const T *__restrict__ b,
+                                                                      const T *__restrict__ xi,
+                                                                      TO *__restrict__ xo, const T omega) {
+  const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
+  const long long v = (long long)blk * BS + threadIdx.x;
+  if (v >= G.N) return;
+  jacobi_vertex<DIM, T, TO, false, true, true>(G, A, b, xi, xo, omega, v);
 }
 
 // r = b - A x at one vertex of a level.
-template <int DIM, typename T, bool NT = false>
+template <int DIM, typename T, bool NT = false, bool TILED = false>
 __device__ __forceinline__ void resid_vertex(const Geo &G, const T *__restrict__ A, const T *__restrict__ b,
                                              const T *__restrict__ x, T *__restrict__ r, long long v) {
   T a0, a1, d[4];
-  row_apply<DIM, T, T, NT>(G, v, A, x, a0, a1, d);
+  row_apply<DIM, T, T, NT, TILED>(G, v, A, x, a0, a1, d);
   const auto bb = *reinterpret_cast<const typename Vec2<T>::type *>(b + 2 * v);
   typename Vec2<T>::type o;
   o.x = bb.x - a0;
   o.y = bb.y - a1;
   *reinterpret_cast<typename Vec2<T>::type *>(r + 2 * v) = o;
 }
+
+template <int DIM, typename T>
+__global__ void __launch_bounds__(BS) TPF_STREAM_ATTR k_resid_stream(const Geo G, const T *__restrict__ A,
+                                                                     const T *__restrict__ b,
+                                                                     const T *__restrict__ x, T *__restrict__ r);
 
 template <int DIM, typename T, bool NT = false>
 __global__ void __launch_bounds__(BS) k_resid(const Geo G, const T *__restrict__ A, const T *__restrict__ b,
@@ -213,6 +242,16 @@ __global__ void __launch_bounds__(BS) k_resid(const Geo G, const T *__restrict__
   const long long v = (long long)blk * BS + threadIdx.x;
   if (v >= G.N) return;
   resid_vertex<DIM, T, NT>(G, A, b, x, r, v);
+}
+
+template <int DIM, typename T>
+__global__ void __launch_bounds__(BS) TPF_STREAM_ATTR k_resid_stream(const Geo G, const T *__restrict__ A,
+                                                                     const T *__restrict__ b,
+                                                                     const T *__restrict__ x, T *__restrict__ r) {
+  const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
+  const long long v = (long long)blk * BS + threadIdx.x;
+  if (v >= G.N) return;
+  resid_vertex<DIM, T, true, true>(G, A, b, x, r, v);
 }
 
 // Restriction bc = P^T rf.  Pressure component: (bi/tri)linear weights
@@ -445,6 +484,15 @@ __global__ void k_cast(const TI *__restrict__ a, TO *__restrict__ b, long long n
 
 inline Geo geo(const Level &L) { return Geo{L.n[0], L.n[1], L.n[2], L.N}; }
 
+// Tiled finest FP32 matrix -> [offset][vertex] layout, one thread per block.
+__global__ void k_untile(const float *__restrict__ src, float *__restrict__ dst, long long N, int nst) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)nst * N) return;
+  const int o = (int)(t / N);
+  const long long v = t % N;
+  *reinterpret_cast<float4 *>(dst + t * 4) = *reinterpret_cast<const float4 *>(src + tiled_block(o, v, nst) * 4);
+}
+
 // ---- V-cycle driver ----------------------------------------------------------
 template <int DIM, typename T>
 tpf_status vcycle_t(tpf_grid *g, const double *bin, double *xout, hipStream_t s) {
@@ -485,13 +533,16 @@ tpf_status vcycle_t(tpf_grid *g, const double *bin, double *xout, hipStream_t s)
     const unsigned nb = blocks_for(lv.N);
     T *X = reinterpret_cast<T *>(lv.x), *Y = reinterpret_cast<T *>(lv.y);
     int ps = prof_begin(g, l == 0 ? TPF_K_SMOOTH0_FIRST : TPF_K_COARSE_LEVELS, s);
-    k_jacobi<DIM, T, T, true><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], nullptr, X, om);
+    if (l == 0 && NT0)
+      k_jacobi<DIM, T, T, true, false, true><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], nullptr, X, om);
+    else
+      k_jacobi<DIM, T, T, true><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], nullptr, X, om);
     TPF_LAUNCH_CHECK();
     prof_end(g, ps, s);
     for (int k = 1; k < g->nu_pre; ++k) {
       ps = prof_begin(g, l == 0 ? TPF_K_SMOOTH0 : TPF_K_COARSE_LEVELS, s);
-      if (l == 0)
-        k_jacobi<DIM, T, T, false, NT0><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, Y, om);
+      if (l == 0 && NT0)
+        k_jacobi_stream<DIM, T, T><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, Y, om);
       else
         k_jacobi<DIM, T, T, false><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, Y, om);
       TPF_LAUNCH_CHECK();
@@ -501,8 +552,8 @@ tpf_status vcycle_t(tpf_grid *g, const double *bin, double *xout, hipStream_t s)
     cur[l] = X;
     T *R = reinterpret_cast<T *>(lv.r);
     ps = prof_begin(g, l == 0 ? TPF_K_RESID0 : TPF_K_COARSE_LEVELS, s);
-    if (l == 0)
-      k_resid<DIM, T, NT0><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, R);
+    if (l == 0 && NT0)
+      k_resid_stream<DIM, T><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, R);
     else
       k_resid<DIM, T><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, R);
     TPF_LAUNCH_CHECK();
@@ -539,14 +590,17 @@ tpf_status vcycle_t(tpf_grid *g, const double *bin, double *xout, hipStream_t s)
     for (int k = 0; k < nu; ++k) {
       ps = prof_begin(g, l == 0 ? TPF_K_SMOOTH0 : TPF_K_COARSE_LEVELS, s);
       if (l == 0 && k == nu - 1) {
-        k_jacobi<DIM, T, double, false, NT0><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, xout, om);
+        if (NT0)
+          k_jacobi_stream<DIM, T, double><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, xout, om);
+        else
+          k_jacobi<DIM, T, double, false><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, xout, om);
         TPF_LAUNCH_CHECK();
         prof_end(g, ps, s);
         X = nullptr;
         break;
       }
-      if (l == 0)
-        k_jacobi<DIM, T, T, false, NT0><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, Y, om);
+      if (l == 0 && NT0)
+        k_jacobi_stream<DIM, T, T><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, Y, om);
       else
         k_jacobi<DIM, T, T, false><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, Y, om);
       TPF_LAUNCH_CHECK();
@@ -601,6 +655,14 @@ tpf_status spmv_t(tpf_grid *g, int level, const double *x, double *y, hipStream_
 }
 
 }  // namespace
+
+tpf_status untile_matrix32(tpf_grid *g, float *dst, hipStream_t s) {
+  const Level &lv = g->lv[0];
+  const long long n = (long long)g->nst * lv.N;
+  k_untile<<<blocks_for(n), BS, 0, s>>>(lv.A32, dst, lv.N, g->nst);
+  TPF_LAUNCH_CHECK();
+  return TPF_OK;
+}
 
 tpf_status build_hierarchy(tpf_grid *g, hipStream_t s) {
   return g->dim == 3 ? hierarchy_t<3>(g, s) : hierarchy_t<2>(g, s);

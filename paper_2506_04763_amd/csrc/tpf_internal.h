@@ -129,6 +129,16 @@ void set_error(const char *fmt, ...);
 
 inline unsigned blocks_for(long long n, int bs = BS) { return (unsigned)((n + bs - 1) / bs); }
 
+// Block (o, v) of the finest level's FP32 matrix copy, which the smoother streams from
+// HBM every sweep: vertices in tiles of 64 (one wavefront), the 64 blocks of one
+// offset of a tile contiguous and a tile's offsets one after the other, so that the
+// whole row set a wavefront needs is one contiguous range (27 KB in 3D).  Every other
+// matrix is stored [offset][vertex] (block o * N + v).
+__host__ __device__ __forceinline__ long long tiled_block(int o, long long v, int nst) {
+  return (((v >> 6) * nst + o) << 6) + (v & 63);
+}
+__host__ __device__ __forceinline__ long long tiled_blocks(long long N, int nst) { return ((N + 63) >> 6) * 64 * nst; }
+
 // Logical block index of an XCD-aware launch: the hardware dispatches block k to
 // XCD k mod 8; this mapping gives every XCD one contiguous eighth of the grid so
 // that neighbouring rows (which share x entries) meet in the same L2.
@@ -147,6 +157,8 @@ tpf_status launch_apply_dirichlet(tpf_grid *g, double *u, hipStream_t s);
 
 // ---- launchers (mg.hip) ----
 tpf_status build_hierarchy(tpf_grid *g, hipStream_t s);
+// The finest FP32 matrix in the [offset][vertex] layout of the ABI (dst: nst*4*N floats).
+tpf_status untile_matrix32(tpf_grid *g, float *dst, hipStream_t s);
 tpf_status vcycle(tpf_grid *g, const double *b, double *x, hipStream_t s);
 // y = A x (FP64, level l); if dot_with != null also block partials of (dot_with, y)
 // and, if second != null, (second, y) and (y, y) as selected by mode.

@@ -49,9 +49,11 @@ def _bytes_expected(scn, prec_bytes, limex=0):
         n = [(v - 1) // 2 + 1 if a < scn.dim else 1 for a, v in enumerate(n)]
         sizes.append(tuple(n))
     tot = al(4 * scn.ncells * 8) + 2 * al(N * 8) + 3 * al(2 * N * 8) + al(N)
-    for s in sizes:
+    for lvl, s in enumerate(sizes):
         Nl = s[0] * s[1] * s[2]
-        tot += al(nst * 4 * Nl * 8) + (al(nst * 4 * Nl * 4) if prec_bytes == 4 else 0) + al(2 * Nl * 8)
+        # the finest FP32 copy is stored in whole tiles of 64 vertices
+        n32 = (Nl + 63) // 64 * 64 if lvl == 0 else Nl
+        tot += al(nst * 4 * Nl * 8) + (al(nst * 4 * n32 * 4) if prec_bytes == 4 else 0) + al(2 * Nl * 8)
         tot += 4 * al(2 * Nl * prec_bytes)
     nc = 2 * sizes[-1][0] * sizes[-1][1] * sizes[-1][2]
     tot += 2 * al(nc * nc * 8) + al(nc * 4)
