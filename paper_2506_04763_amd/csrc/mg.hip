@@ -371,58 +371,141 @@ __global__ void k_zero(double *p, long long n) {
     p[i] = 0.0;
 }
 
-// Right-looking LU with partial pivoting of a column-major n x n matrix in one
-// workgroup (the coarsest level has at most a few thousand unknowns).
-// One wavefront finds the pivot (shuffle arg-max, ties to the lowest row), the
-// multipliers of column k are staged in LDS, and the trailing update runs with 64
-// consecutive rows per wavefront and 16 wavefronts over the columns.  n <= 4096.
-__global__ void __launch_bounds__(1024) k_lu(double *__restrict__ a, int n, int *__restrict__ piv) {
-  __shared__ double lcol[4096];
+// Blocked right-looking LU with partial pivoting of the column-major n x n coarsest
+// matrix (P A = L U, L unit lower, both factors in place), in panels of LU_NB
+// columns: the panel is factored by one workgroup, its row interchanges are then
+// applied to the other columns, the block row of U is solved with the panel's unit
+// lower triangle and the trailing matrix updated by a tiled product.  The pivot of a
+// column is its largest magnitude below the diagonal, ties going to the lowest row.
+constexpr int LU_NB = 32;
+
+__global__ void __launch_bounds__(1024) k_lu_panel(double *__restrict__ a, int n, int j0, int w,
+                                                   int *__restrict__ piv) {
+  __shared__ double wbest[16];
+  __shared__ int wrow[16];
   __shared__ int sp;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  for (int k = 0; k < n; ++k) {
+  for (int c = 0; c < w; ++c) {
+    const int k = j0 + c;
     double *colk = a + (long long)k * n;
-    if (wv == 0) {
-      double best = -1.0;
-      int bi = k;
-      for (int i = k + lane; i < n; i += 64) {
-        const double vabs = fabs(colk[i]);
-        if (vabs > best) { best = vabs; bi = i; }
-      }
+    double best = -1.0;
+    int bi = k;  // a column without a comparable entry (NaN) keeps its own row
+    for (int i = k + tid; i < n; i += 1024) {  // ascending rows: strict > keeps the lowest
+      const double v = fabs(colk[i]);
+      if (v > best) { best = v; bi = i; }
+    }
 #pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ob = __shfl_down(best, off, 64);
-        const int oi = __shfl_down(bi, off, 64);
-        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-      }
-      if (lane == 0) {
-        sp = bi;
-        piv[k] = bi;
-      }
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ob = __shfl_down(best, off, 64);
+      const int oi = __shfl_down(bi, off, 64);
+      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    if (lane == 0) { wbest[wv] = best; wrow[wv] = bi; }
+    __syncthreads();
+    if (tid == 0) {
+      double b0 = wbest[0];
+      int r0 = wrow[0];
+      for (int q = 1; q < 16; ++q)
+        if (wbest[q] > b0 || (wbest[q] == b0 && wrow[q] < r0)) { b0 = wbest[q]; r0 = wrow[q]; }
+      sp = r0;
+      piv[k] = r0;
     }
     __syncthreads();
     const int p = sp;
-    if (p != k) {
-      for (int j = tid; j < n; j += 1024) {
-        const double t = a[(long long)j * n + k];
-        a[(long long)j * n + k] = a[(long long)j * n + p];
-        a[(long long)j * n + p] = t;
-      }
+    if (p != k && tid < w) {  // interchange rows k and p inside the panel
+      double *col = a + (long long)(j0 + tid) * n;
+      const double t = col[k];
+      col[k] = col[p];
+      col[p] = t;
     }
     __syncthreads();
     const double inv = 1.0 / colk[k];
     for (int i = k + 1 + tid; i < n; i += 1024) {
       const double l = colk[i] * inv;
       colk[i] = l;
-      lcol[i] = l;
+      for (int cc = c + 1; cc < w; ++cc) {
+        double *colj = a + (long long)(j0 + cc) * n;
+        colj[i] -= l * colj[k];
+      }
     }
     __syncthreads();
-    for (int j = k + 1 + wv; j < n; j += 16) {
-      double *colj = a + (long long)j * n;
-      const double u = colj[k];
-      for (int i = k + 1 + lane; i < n; i += 64) colj[i] -= lcol[i] * u;
+  }
+}
+
+// Row interchanges of panel j0..j0+w-1 applied, in order, to every column outside it.
+__global__ void __launch_bounds__(256) k_lu_swap(double *__restrict__ a, int n, int j0, int w,
+                                                 const int *__restrict__ piv) {
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= n || (col >= j0 && col < j0 + w)) return;
+  double *c = a + (long long)col * n;
+  for (int q = 0; q < w; ++q) {
+    const int k = j0 + q, p = piv[k];
+    if (p != k) {
+      const double t = c[k];
+      c[k] = c[p];
+      c[p] = t;
     }
-    __syncthreads();
+  }
+}
+
+// U12 = L11^{-1} A12: forward substitution with the panel's unit lower triangle, one
+// wavefront per column right of the panel (lane r holds row j0 + r).
+__global__ void __launch_bounds__(256) k_lu_trsm(double *__restrict__ a, int n, int j0, int w) {
+  __shared__ double L[LU_NB][LU_NB];
+  for (int t = threadIdx.x; t < w * w; t += blockDim.x) {
+    const int r = t % w, c = t / w;
+    L[r][c] = a[(long long)(j0 + c) * n + j0 + r];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int col = j0 + w + blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  if (col >= n) return;  // the whole wavefront leaves together
+  double *c = a + (long long)col * n + j0;
+  double x = lane < w ? c[lane] : 0.0;
+  for (int q = 0; q + 1 < w; ++q) {
+    const double xq = __shfl(x, q, 64);
+    if (lane > q && lane < w) x -= L[lane][q] * xq;
+  }
+  if (lane < w) c[lane] = x;
+}
+
+// A22 -= L21 U12 on the trailing matrix (rows and columns from j0 + w): 64 x 64
+// tiles per workgroup, 4 x 4 entries per thread, both operand tiles staged in LDS.
+__global__ void __launch_bounds__(256) k_lu_gemm(double *__restrict__ a, int n, int j0, int w) {
+  __shared__ double Lt[LU_NB][64];  // Lt[c][r] = L21(i0 + r, c)
+  __shared__ double Ut[LU_NB][64];  // Ut[c][q] = U12(c, jc0 + q)
+  const int base = j0 + w;
+  const int i0 = base + blockIdx.x * 64, jc0 = base + blockIdx.y * 64;
+  for (int t = threadIdx.x; t < LU_NB * 64; t += 256) {
+    const int c = t / 64, r = t % 64;
+    const int i = i0 + r, j = jc0 + r;
+    Lt[c][r] = (c < w && i < n) ? a[(long long)(j0 + c) * n + i] : 0.0;
+    Ut[c][r] = (c < w && j < n) ? a[(long long)j * n + j0 + c] : 0.0;
+  }
+  __syncthreads();
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  double acc[4][4] = {};
+  for (int c = 0; c < w; ++c) {
+    double l[4], u[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      l[q] = Lt[c][tx * 4 + q];
+      u[q] = Ut[c][ty * 4 + q];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[r][q] += l[r] * u[q];
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int j = jc0 + ty * 4 + q;
+    if (j >= n) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = i0 + tx * 4 + r;
+      if (i < n) a[(long long)j * n + i] -= acc[r][q];
+    }
   }
 }
 
@@ -636,8 +719,21 @@ tpf_status hierarchy_t(tpf_grid *g, hipStream_t s) {
   constexpr int NST = DIM == 3 ? 27 : 9;
   k_densify<DIM><<<blocks_for((long long)NST * lc.N), BS, 0, s>>>(geo(lc), lc.A64, g->lu, n);
   TPF_LAUNCH_CHECK();
-  k_lu<<<1, 1024, 0, s>>>(g->lu, n, g->piv);
-  TPF_LAUNCH_CHECK();
+  for (int j0 = 0; j0 < n; j0 += LU_NB) {
+    const int w = n - j0 < LU_NB ? n - j0 : LU_NB;
+    k_lu_panel<<<1, 1024, 0, s>>>(g->lu, n, j0, w, g->piv);
+    TPF_LAUNCH_CHECK();
+    k_lu_swap<<<blocks_for(n, 256), 256, 0, s>>>(g->lu, n, j0, w, g->piv);
+    TPF_LAUNCH_CHECK();
+    const int m = n - j0 - w;
+    if (m > 0) {
+      k_lu_trsm<<<(unsigned)((m + 3) / 4), 256, 0, s>>>(g->lu, n, j0, w);
+      TPF_LAUNCH_CHECK();
+      const unsigned t = (unsigned)((m + 63) / 64);
+      k_lu_gemm<<<dim3(t, t), 256, 0, s>>>(g->lu, n, j0, w);
+      TPF_LAUNCH_CHECK();
+    }
+  }
   k_lu_inverse<<<n, 64, (size_t)n * sizeof(double), s>>>(g->lu, g->piv, n, g->ainv);
   TPF_LAUNCH_CHECK();
   prof_end(g, pl, s);
