@@ -432,6 +432,78 @@ __global__ void __launch_bounds__(1024) k_lu_panel(double *__restrict__ a, int n
   }
 }
 
+// The same panel factorisation with the panel held in LDS (rows j0..n-1 of its w
+// columns, column by column), for panels of at most LU_LDS_ROWS rows.
+constexpr int LU_LDS_ROWS = 256;  // 256 x 32 doubles = 64 KB
+
+__global__ void __launch_bounds__(1024) k_lu_panel_lds(double *__restrict__ a, int n, int j0, int w,
+                                                       int *__restrict__ piv) {
+  __shared__ double P[LU_NB * LU_LDS_ROWS];
+  __shared__ double wbest[16];
+  __shared__ int wrow[16];
+  __shared__ int sp;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int m = n - j0;  // rows of the panel, <= LU_LDS_ROWS
+  const int row = tid & (LU_LDS_ROWS - 1), grp = tid / LU_LDS_ROWS;  // 4 groups of 256 rows
+  for (int t = tid; t < m * w; t += 1024) {
+    const int c = t / m, r = t % m;
+    P[c * m + r] = a[(long long)(j0 + c) * n + j0 + r];
+  }
+  __syncthreads();
+  for (int c = 0; c < w; ++c) {
+    double *colk = P + c * m;
+    double best = -1.0;
+    int bi = c;
+    if (tid >= c && tid < m) {  // m <= 256 < 1024: one row per thread
+      best = fabs(colk[tid]);
+      bi = tid;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ob = __shfl_down(best, off, 64);
+      const int oi = __shfl_down(bi, off, 64);
+      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    if (lane == 0) { wbest[wv] = best; wrow[wv] = bi; }
+    __syncthreads();
+    if (wv == 0) {  // 16 partial maxima reduced by the first wavefront
+      best = lane < 16 ? wbest[lane] : -1.0;
+      bi = lane < 16 ? wrow[lane] : c;
+#pragma unroll
+      for (int off = 8; off > 0; off >>= 1) {
+        const double ob = __shfl_down(best, off, 64);
+        const int oi = __shfl_down(bi, off, 64);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      if (lane == 0) {
+        sp = bi;
+        piv[j0 + c] = j0 + bi;
+      }
+    }
+    __syncthreads();
+    const int p = sp;
+    if (p != c && tid < w) {
+      const double t = P[tid * m + c];
+      P[tid * m + c] = P[tid * m + p];
+      P[tid * m + p] = t;
+    }
+    __syncthreads();
+    // rank-1 update of the panel's remaining columns: row `row`, columns c+1+grp, +4, ...
+    const double inv = 1.0 / colk[c];
+    if (row > c && row < m) {
+      const double l = colk[row] * inv;
+      for (int cc = c + 1 + grp; cc < w; cc += 4) P[cc * m + row] -= l * P[cc * m + c];
+    }
+    __syncthreads();
+    if (grp == 0 && row > c && row < m) colk[row] *= inv;  // multipliers (read again only after barriers)
+  }
+  __syncthreads();
+  for (int t = tid; t < m * w; t += 1024) {
+    const int c = t / m, r = t % m;
+    a[(long long)(j0 + c) * n + j0 + r] = P[c * m + r];
+  }
+}
+
 // Row interchanges of panel j0..j0+w-1 applied, in order, to every column outside it.
 __global__ void __launch_bounds__(256) k_lu_swap(double *__restrict__ a, int n, int j0, int w,
                                                  const int *__restrict__ piv) {
@@ -721,7 +793,10 @@ tpf_status hierarchy_t(tpf_grid *g, hipStream_t s) {
   TPF_LAUNCH_CHECK();
   for (int j0 = 0; j0 < n; j0 += LU_NB) {
     const int w = n - j0 < LU_NB ? n - j0 : LU_NB;
-    k_lu_panel<<<1, 1024, 0, s>>>(g->lu, n, j0, w, g->piv);
+    if (n - j0 <= LU_LDS_ROWS)
+      k_lu_panel_lds<<<1, 1024, 0, s>>>(g->lu, n, j0, w, g->piv);
+    else
+      k_lu_panel<<<1, 1024, 0, s>>>(g->lu, n, j0, w, g->piv);
     TPF_LAUNCH_CHECK();
     k_lu_swap<<<blocks_for(n, 256), 256, 0, s>>>(g->lu, n, j0, w, g->piv);
     TPF_LAUNCH_CHECK();
