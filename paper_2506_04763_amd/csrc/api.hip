@@ -52,7 +52,7 @@ tpf_status validate(const tpf_grid_desc *d) {
   }
   if (d->dim == 2 && d->n[2] != 1) BAD("2D grids need n[2] = 1");
   const double nv = (double)d->n[0] * d->n[1] * d->n[2];
-  if (nv > 4.0e9) BAD("grid too large");
+  if (nv > 2147483647.0) BAD("grid too large (at most 2^31 - 1 vertices)");
   for (int a = 0; a < 3; ++a)
     if (!finite(d->gravity[a])) BAD("gravity must be finite");
   for (int k = 0; k < 2; ++k) {

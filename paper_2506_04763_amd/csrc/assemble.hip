@@ -143,10 +143,8 @@ __global__ void __launch_bounds__(BS) k_setup(const Phys P, const double *__rest
                                               double *__restrict__ Q) {
   const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= P.N) return;
-  const int ix = (int)(v % P.nx);
-  const long long t = v / P.nx;
-  const int iy = (int)(t % P.ny);
-  const int iz = (int)(t / P.ny);
+  int ix, iy, iz;
+  grid_coords(v, P.nx, P.ny, ix, iy, iz);
   double best = 1.0e308;
   long long bestc = -1;
   // visit adjacent cells in increasing cell index so ties keep the lowest index
@@ -229,10 +227,8 @@ __host__ __device__ __forceinline__ void accumulate_cells(const long long v, con
                                                          double (&acc)[NSLOT][4], double &Fw, double &Fn,
                                                          double &mwS, double &mnS) {
   constexpr int NC = 1 << DIM;
-  const int ix = (int)(v % P.nx);
-  const long long tq = v / P.nx;
-  const int iy = (int)(tq % P.ny);
-  const int iz = (int)(tq / P.ny);
+  int ix, iy, iz;
+  grid_coords(v, P.nx, P.ny, ix, iy, iz);
   const long long sy = P.nx, sz = (long long)P.nx * P.ny;
   const double rw = P.rho_w, rn = P.rho_n;
 

@@ -41,10 +41,8 @@ __global__ void __launch_bounds__(BS) k_norms(const Phys P, const double *__rest
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   const long long sy = P.nx, sz = (long long)P.nx * P.ny;
   for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < P.N; v += (long long)gridDim.x * blockDim.x) {
-    const int ix = (int)(v % P.nx);
-    const long long t = v / P.nx;
-    const int iy = (int)(t % P.ny);
-    const int iz = (int)(t / P.ny);
+    int ix, iy, iz;
+    grid_coords(v, P.nx, P.ny, ix, iy, iz);
     // lumped saturation norm: dual-box volume times S_w^2
     double dual = P.h[0] * P.h[1] * (DIM == 3 ? P.h[2] : 1.0);
     if (ix == 0 || ix == P.nx - 1) dual *= 0.5;

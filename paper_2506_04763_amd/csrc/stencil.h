@@ -30,10 +30,7 @@ struct Geo {
 };
 
 __host__ __device__ __forceinline__ void vcoords(long long v, const Geo &G, int &ix, int &iy, int &iz) {
-  ix = (int)(v % G.nx);
-  const long long t = v / G.nx;
-  iy = (int)(t % G.ny);
-  iz = (int)(t / G.ny);
+  grid_coords(v, G.nx, G.ny, ix, iy, iz);
 }
 
 __host__ __device__ inline Geo geo_of(const int n[3], long long N) { return Geo{n[0], n[1], n[2], N}; }

@@ -129,6 +129,17 @@ void set_error(const char *fmt, ...);
 
 inline unsigned blocks_for(long long n, int bs = BS) { return (unsigned)((n + bs - 1) / bs); }
 
+// Grid coordinates of vertex v (x fastest).  Grids have fewer than 2^31 vertices
+// (validated), so 32-bit unsigned division suffices, far cheaper on the GPU than the
+// 64-bit one.
+__host__ __device__ __forceinline__ void grid_coords(long long v, int nx, int ny, int &ix, int &iy, int &iz) {
+  const unsigned u = (unsigned)v;
+  const unsigned t = u / (unsigned)nx;
+  ix = (int)(u - t * (unsigned)nx);
+  iz = (int)(t / (unsigned)ny);
+  iy = (int)(t - (unsigned)iz * (unsigned)ny);
+}
+
 // Block (o, v) of the finest level's FP32 matrix copy, which the smoother streams from
 // HBM every sweep: vertices in tiles of 64 (one wavefront), the 64 blocks of one
 // offset of a tile contiguous and a tile's offsets one after the other, so that the
