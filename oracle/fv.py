@@ -14,7 +14,7 @@ Paper passages followed (Section 2, Section 3):
     mobility and not to the wetting one (Eqs. krn_ip, krw_ip); p_dmin is a per-vertex
     constant computed once.
 
-Readings taken where the paper is silent (each listed in the design doc):
+Readings taken where the paper is silent:
   * unknowns (p_w, S_n): the convective part of the non-wetting flux is upwinded with
     v_n' = -K/mu_n (grad p_w - rho_n g); the capillary part -k_rn K/mu_n grad p_c is
     central and sits in the non-wetting balance;

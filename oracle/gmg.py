@@ -2,7 +2,7 @@
 
 The paper names a geometric multigrid preconditioner for BiCGSTAB (Section 1 and the
 solver settings opening Section 5) without giving its components.  Reading used
-here (listed in DESIGN.md):
+here:
   * levels by vertex halving n -> (n-1)/2 + 1 along every active axis;
   * prolongation P = per-component (bi/tri)linear interpolation from level l+1 to l;
     on the finest level the rows of P at Dirichlet components are zero;

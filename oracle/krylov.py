@@ -1,8 +1,8 @@
 """Right-preconditioned BiCGSTAB (van der Vorst 1992), FP64.
 
 The paper solves every stage system with BiCGSTAB preconditioned by geometric
-multigrid (Section 1; solver settings at the start of Section 5).  Variant used
-(listed in the design doc): x0 = 0, shadow residual r^ = r0 = b, stop when
+multigrid (Section 1; solver settings at the start of Section 5).  Variant used:
+x0 = 0, shadow residual r^ = r0 = b, stop when
 ||r||_2 <= rtol ||b||_2 on the recursively updated residual, then report the true
 residual ||b - A x|| / ||b|| recomputed from x.  A zero (t, t) gives omega = 0; a zero
 rho restarts once with r^ = r.

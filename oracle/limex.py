@@ -7,7 +7,7 @@ Paper passages followed:
   * step-size rule tau_new = (rho TOL / [[eps]])^(1/(q+1)) tau_old with q = 2;
   * error estimate [[eps]] = relative error in the scaled norm
     |||u|||^2 = alpha ||grad p||^2 + beta ||S_w||^2 (Eq. norm_u).
-Readings (listed in the design doc): harmonic stage sequence n_j = j, stage j takes j
+Readings: harmonic stage sequence n_j = j, stage j takes j
 substeps of H/j with M and J frozen at the step's initial state and F re-evaluated at
 every substep; Aitken-Neville extrapolation
   T_{j,l+1} = T_{j,l} + (T_{j,l} - T_{j-1,l}) / (n_j / n_{j-l} - 1);

@@ -16,8 +16,8 @@ Conventions (shared by every consumer):
     face measure (kg/(m^2 s) in 3D, kg/(m s) in 2D) of one phase into the domain.
 
 Recipes follow the paper's parameter tables (Section 5: Case-4 step control values,
-Case-5 geometry sizes) and the synthetic layered / log-normal reservoirs described
-in the design doc; the random field is a Gaussian field with exponential covariance drawn
+Case-5 geometry sizes) and synthetic layered / log-normal reservoirs standing in for
+the paper's; the random field is a Gaussian field with exponential covariance drawn
 by circulant embedding (Dietrich & Newsam 1997).
 """
 from __future__ import annotations
