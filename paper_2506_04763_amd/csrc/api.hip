@@ -33,7 +33,7 @@ struct Layout {
   int L, nst, nc;
   int n[MAXL][3];
   long long Nl[MAXL];
-  size_t off_cells, off_vert, off_lv[MAXL], off_coarse, off_kry, off_part, off_scal, off_lx, total;
+  size_t off_cells, off_vert, off_lv[MAXL], off_coarse, off_rapb, off_kry, off_part, off_scal, off_lx, total;
   long long npart;
 };
 
@@ -139,6 +139,8 @@ void layout(const tpf_grid_desc *d, Layout &L) {
   }
   L.off_coarse = o;
   o += 2 * align_up((size_t)L.nc * L.nc * sizeof(double)) + align_up(L.nc * sizeof(int));
+  L.off_rapb = o;  // A P of the Galerkin product, one level at a time (finest fine grid largest)
+  o += L.L > 1 ? align_up((size_t)L.nst * 4 * L.N * sizeof(double)) : 0;
   L.off_kry = o;
   o += 10 * align_up(2 * L.N * sizeof(double));
   L.npart = std::max<long long>(RED_BLOCKS, (L.N + BS - 1) / BS);
@@ -255,6 +257,7 @@ tpf_status tpf_create_grid(const tpf_grid_desc *d, void *arena, size_t arena_byt
   g->lu = reinterpret_cast<double *>(base + o); o += align_up((size_t)L.nc * L.nc * sizeof(double));
   g->ainv = reinterpret_cast<double *>(base + o); o += align_up((size_t)L.nc * L.nc * sizeof(double));
   g->piv = reinterpret_cast<int *>(base + o);
+  g->rapb = reinterpret_cast<double *>(base + L.off_rapb);
   o = L.off_kry;
   double **kv[10] = {&g->r, &g->rh, &g->p, &g->v, &g->s, &g->t, &g->ph, &g->sh, &g->w, &g->xb};
   for (int k = 0; k < 10; ++k) { *kv[k] = reinterpret_cast<double *>(base + o); o += align_up(2 * L.N * sizeof(double)); }

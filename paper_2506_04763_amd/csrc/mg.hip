@@ -779,7 +779,7 @@ tpf_status hierarchy_t(tpf_grid *g, hipStream_t s) {
     float *c32 = g->prec == TPF_MIXED ? c.A32 : nullptr;
     const int ps = prof_begin(g, TPF_K_RAP, s);
     const tpf_status st = launch_rap(g->dim, l == 0, f.n, f.N, c.n, c.N, f.A64, l == 0 ? g->dmask : nullptr, f.mst,
-                                     c.A64, c32, c.mst, s);
+                                     g->rapb, c.A64, c32, c.mst, s);
     if (st != TPF_OK) return st;
     prof_end(g, ps, s);
   }

@@ -79,6 +79,7 @@ struct tpf_grid {
   // coarsest level, dense
   int nc;
   double *lu, *ainv;
+  double *rapb;  // Galerkin-product scratch: NST * 4 * N (finest) doubles
   int *piv;
   // Krylov vectors (double[2N])
   double *r, *rh, *p, *v, *s, *t, *ph, *sh, *w, *xb;

@@ -57,6 +57,7 @@ def _bytes_expected(scn, prec_bytes, limex=0):
         tot += 4 * al(2 * Nl * prec_bytes)
     nc = 2 * sizes[-1][0] * sizes[-1][1] * sizes[-1][2]
     tot += 2 * al(nc * nc * 8) + al(nc * 4)
+    tot += al(nst * 4 * N * 8) if scn.levels > 1 else 0   # Galerkin-product scratch
     tot += 10 * al(2 * N * 8)
     tot += al(4 * max(1024, (N + 255) // 256) * 8) + al(32 * 8)
     tot += al(2 * N * 8) * (3 + (1 + limex if limex else 0))
