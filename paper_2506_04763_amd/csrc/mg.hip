@@ -48,12 +48,12 @@ __device__ __forceinline__ void load_block(const T *p, T (&b)[4]) {
 // Returns (A x)_v; the centre block is copied out for the smoother.  Neighbours
 // outside the grid have zero blocks; their x value is read at the clamped (valid)
 // position and masked to zero, so no load depends on a branch.
-template <int DIM, typename T, typename TX, bool NT = false, bool TILED = false>
+template <int DIM, typename T, typename TX, bool NT = false, bool TILED = false, int GROUP = 0>
 __device__ __forceinline__ void row_apply(const Geo &G, long long v, const T *__restrict__ A,
                                           const TX *__restrict__ x, T &y0, T &y1, T (&dblk)[4]) {
   constexpr int NST = DIM == 3 ? 27 : 9;
   constexpr int CEN = DIM == 3 ? 13 : 4;
-  constexpr int GRP0 = sizeof(T) == 4 ? TPF_ROW_GROUP32 : TPF_ROW_GROUP64;
+  constexpr int GRP0 = GROUP > 0 ? GROUP : (sizeof(T) == 4 ? TPF_ROW_GROUP32 : TPF_ROW_GROUP64);
   constexpr int GRP = GRP0 > NST ? NST : GRP0;
   static_assert(NST % GRP == 0, "group size must divide the stencil size");
   int ix, iy, iz;
@@ -155,17 +155,29 @@ __global__ void __launch_bounds__(BS) k_spmv64(const Geo G, const double *__rest
 
 // Damped block Jacobi update of one vertex: xo = xi + omega D^{-1} (b - A xi);
 // FIRST: xi = 0, so only the diagonal block is read.
-template <int DIM, typename T, typename TO, bool FIRST, bool NT = false, bool TILED = false>
+// LAT (the small, latency-bound coarse levels): all loads of the row are issued
+// together, before any is used, so a sweep costs one memory round trip.
+template <int DIM, typename T, typename TO, bool FIRST, bool NT = false, bool TILED = false, bool LAT = false>
 __device__ __forceinline__ void jacobi_vertex(const Geo &G, const T *__restrict__ A, const T *__restrict__ b,
                                               const T *__restrict__ xi, TO *__restrict__ xo, const T omega,
                                               long long v) {
   constexpr int CEN = DIM == 3 ? 13 : 4;
+  constexpr int NST = DIM == 3 ? 27 : 9;
   T r0, r1, d[4], x0 = 0, x1 = 0;
   if (FIRST) {
     Blk<T>::load(A + (TILED ? tiled_block(CEN, v, DIM == 3 ? 27 : 9) : (long long)CEN * G.N + v) * 4, d);
     const auto bb = *reinterpret_cast<const typename Vec2<T>::type *>(b + 2 * v);
     r0 = bb.x;
     r1 = bb.y;
+  } else if (LAT) {
+    const auto bb = *reinterpret_cast<const typename Vec2<T>::type *>(b + 2 * v);
+    const auto xx = *reinterpret_cast<const typename Vec2<T>::type *>(xi + 2 * v);
+    T a0, a1;
+    row_apply<DIM, T, T, NT, TILED, NST>(G, v, A, xi, a0, a1, d);
+    x0 = xx.x;
+    x1 = xx.y;
+    r0 = bb.x - a0;
+    r1 = bb.y - a1;
   } else {
     T a0, a1;
     row_apply<DIM, T, T, NT, TILED>(G, v, A, xi, a0, a1, d);
@@ -184,14 +196,14 @@ __device__ __forceinline__ void jacobi_vertex(const Geo &G, const T *__restrict_
   *reinterpret_cast<typename Vec2<TO>::type *>(xo + 2 * v) = out;
 }
 
-template <int DIM, typename T, typename TO, bool FIRST, bool NT = false, bool TILED = false>
+template <int DIM, typename T, typename TO, bool FIRST, bool NT = false, bool TILED = false, bool LAT = false>
 __global__ void __launch_bounds__(BS) k_jacobi(const Geo G, const T *__restrict__ A,
                                                const T *__restrict__ b, const T *__restrict__ xi,
                                                TO *__restrict__ xo, const T omega) {
   const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
   const long long v = (long long)blk * BS + threadIdx.x;
   if (v >= G.N) return;
-  jacobi_vertex<DIM, T, TO, FIRST, NT, TILED>(G, A, b, xi, xo, omega, v);
+  jacobi_vertex<DIM, T, TO, FIRST, NT, TILED, LAT>(G, A, b, xi, xo, omega, v);
 }
 
 // The finest-level FP32 sweeps stream a matrix far larger than the caches: they
@@ -218,12 +230,14 @@ __global__ void __launch_bounds__(BS) TPF_STREAM_ATTR k_jacobi_stream(const Geo 
 }
 
 // r = b - A x at one vertex of a level.
-template <int DIM, typename T, bool NT = false, bool TILED = false>
+template <int DIM, typename T, bool NT = false, bool TILED = false, bool LAT = false>
 __device__ __forceinline__ void resid_vertex(const Geo &G, const T *__restrict__ A, const T *__restrict__ b,
                                              const T *__restrict__ x, T *__restrict__ r, long long v) {
   T a0, a1, d[4];
-  row_apply<DIM, T, T, NT, TILED>(G, v, A, x, a0, a1, d);
-  const auto bb = *reinterpret_cast<const typename Vec2<T>::type *>(b + 2 * v);
+  typename Vec2<T>::type bb;
+  if (LAT) bb = *reinterpret_cast<const typename Vec2<T>::type *>(b + 2 * v);
+  row_apply<DIM, T, T, NT, TILED, LAT ? (DIM == 3 ? 27 : 9) : 0>(G, v, A, x, a0, a1, d);
+  if (!LAT) bb = *reinterpret_cast<const typename Vec2<T>::type *>(b + 2 * v);
   typename Vec2<T>::type o;
   o.x = bb.x - a0;
   o.y = bb.y - a1;
@@ -235,13 +249,13 @@ __global__ void __launch_bounds__(BS) TPF_STREAM_ATTR k_resid_stream(const Geo G
                                                                      const T *__restrict__ b,
                                                                      const T *__restrict__ x, T *__restrict__ r);
 
-template <int DIM, typename T, bool NT = false>
+template <int DIM, typename T, bool NT = false, bool LAT = false>
 __global__ void __launch_bounds__(BS) k_resid(const Geo G, const T *__restrict__ A, const T *__restrict__ b,
                                               const T *__restrict__ x, T *__restrict__ r) {
   const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
   const long long v = (long long)blk * BS + threadIdx.x;
   if (v >= G.N) return;
-  resid_vertex<DIM, T, NT>(G, A, b, x, r, v);
+  resid_vertex<DIM, T, NT, false, LAT>(G, A, b, x, r, v);
 }
 
 template <int DIM, typename T>
@@ -649,6 +663,10 @@ __global__ void k_untile(const float *__restrict__ src, float *__restrict__ dst,
 }
 
 // ---- V-cycle driver ----------------------------------------------------------
+// Levels up to this many vertices are latency-bound: their sweeps issue a row's
+// loads all at once (LAT) instead of in register-friendly groups.
+constexpr long long LAT_NMAX = 65536;
+
 template <int DIM, typename T>
 tpf_status vcycle_t(tpf_grid *g, const double *bin, double *xout, hipStream_t s) {
   const int L = g->L;
@@ -698,8 +716,10 @@ tpf_status vcycle_t(tpf_grid *g, const double *bin, double *xout, hipStream_t s)
       ps = prof_begin(g, l == 0 ? TPF_K_SMOOTH0 : TPF_K_COARSE_LEVELS, s);
       if (l == 0 && NT0)
         k_jacobi_stream<DIM, T, T><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, Y, om);
-      else
+      else if (lv.N > LAT_NMAX)
         k_jacobi<DIM, T, T, false><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, Y, om);
+      else
+        k_jacobi<DIM, T, T, false, false, false, true><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, Y, om);
       TPF_LAUNCH_CHECK();
       prof_end(g, ps, s);
       T *t = X; X = Y; Y = t;
@@ -709,8 +729,10 @@ tpf_status vcycle_t(tpf_grid *g, const double *bin, double *xout, hipStream_t s)
     ps = prof_begin(g, l == 0 ? TPF_K_RESID0 : TPF_K_COARSE_LEVELS, s);
     if (l == 0 && NT0)
       k_resid_stream<DIM, T><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, R);
-    else
+    else if (lv.N > LAT_NMAX)
       k_resid<DIM, T><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, R);
+    else
+      k_resid<DIM, T, false, true><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, R);
     TPF_LAUNCH_CHECK();
     prof_end(g, ps, s);
     Level &lc = g->lv[l + 1];
@@ -756,8 +778,10 @@ tpf_status vcycle_t(tpf_grid *g, const double *bin, double *xout, hipStream_t s)
       }
       if (l == 0 && NT0)
         k_jacobi_stream<DIM, T, T><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, Y, om);
-      else
+      else if (lv.N > LAT_NMAX)
         k_jacobi<DIM, T, T, false><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, Y, om);
+      else
+        k_jacobi<DIM, T, T, false, false, false, true><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, Y, om);
       TPF_LAUNCH_CHECK();
       prof_end(g, ps, s);
       T *t = X; X = Y; Y = t;
