@@ -10,7 +10,7 @@ The state is resident in HBM before the clock starts.
 Prints one JSON line.  Options:
   --gpus N      only N = 1 is supported (the path runs on one GPU)
   --steps K     timed steps (default 10)      --warmup W  untimed steps (default 2)
-  --no-cpu      skip the oracle CPU baseline  --no-fp64   skip the FP64 comparison
+  --no-cpu      skip the oracle CPU baseline  --no-fp64   skip the FP64 and FP16-coarse comparisons
   --serve       also run the continuous-batching serving workload (p50/p99)
   --limex-run K run the 257^3 LIMEX workload to K accepted steps (summary line only)
 """
@@ -96,7 +96,7 @@ def run(args):
     rtol = 1e-8
     results = {}
     hot = ("smooth0", "resid0", "spmv64", "assemble")  # level-0 matrix kernels
-    for prec in (["mixed"] if args.no_fp64 else ["mixed", "fp64"]):
+    for prec in (["mixed"] if args.no_fp64 else ["mixed", "fp64", "mixed16"]):
         g = tpf.Grid(scn, precision=prec, levels=6)
         u0 = g.initial_state()
         f = g.empty()
@@ -186,6 +186,10 @@ def run(args):
         line["fp64"] = {"solves_per_s": round(1e3 / r["ms"], 4), "ms_per_step": round(r["ms"], 3),
                         "iterations": r["iters"][-1], "rel_res_true": r["stats"]["rel_res_true"]}
         line["mixed_over_fp64"] = round(r["ms"] / mixed["ms"], 3)
+    if "mixed16" in results:  # coarse-level matrices in FP16 with row scales (optional mode)
+        r = results["mixed16"]
+        line["mixed16"] = {"solves_per_s": round(1e3 / r["ms"], 4), "ms_per_step": round(r["ms"], 3),
+                           "iterations": r["iters"][-1], "rel_res_true": r["stats"]["rel_res_true"]}
     sm = [kernels[k]["gbs"] for k in ("smooth0", "resid0") if k in kernels]
     line["spmv_smoother_gbs"] = {"spmv64": kernels.get("spmv64", {}).get("gbs"),
                                  "smoother_fp32": kernels.get("smooth0", {}).get("gbs"),

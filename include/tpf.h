@@ -63,7 +63,14 @@ enum {
   TPF_ESTATE = -5         /* call out of order (e.g. solve before assemble)    */
 };
 
-enum { TPF_FP64 = 0, TPF_MIXED = 1 };
+/* Precision of the multigrid preconditioner (the outer BiCGSTAB, the assembly, the
+ * Galerkin products, the coarsest LU and LIMEX are FP64 in every mode):
+ *   TPF_FP64     every level FP64;
+ *   TPF_MIXED    level matrices, smoother and transfers FP32;
+ *   TPF_MIXED16  as TPF_MIXED, but the matrices of the coarse levels (all but the
+ *                finest) are stored in FP16 with one FP32 scale per scalar row
+ *                (the row's largest magnitude), computed with in FP32. */
+enum { TPF_FP64 = 0, TPF_MIXED = 1, TPF_MIXED16 = 2 };
 
 /* Boundary injection patch: a rectangle on one face of the box with a mass rate
  * of one phase per unit face measure into the domain (kg/(m^2 s) in 3D,
@@ -103,7 +110,7 @@ typedef struct tpf_grid_desc {
   const tpf_patch *patches; /* host, n_patches entries                          */
   int32_t n_patches;     /* 0..TPF_MAX_PATCHES                                  */
   int32_t levels;        /* multigrid levels >= 1; each coarsening halves the cell count per axis */
-  int32_t precision;     /* TPF_FP64 or TPF_MIXED (FP32 multigrid levels)       */
+  int32_t precision;     /* TPF_FP64, TPF_MIXED or TPF_MIXED16 (see above)      */
   int32_t nu_pre;        /* pre-smoothing sweeps (>= 1)                         */
   int32_t nu_post;       /* post-smoothing sweeps (>= 0)                        */
   int32_t limex_stages;  /* largest LIMEX stage count used with this grid (0: none) */
@@ -208,7 +215,9 @@ tpf_status tpf_level_dims(const tpf_grid *g, int32_t level, int32_t n_out[3]);
 /* Copies the level's stencil matrix into dst (device): layout
  * [offset][vertex][4] with offset = (dx+1) + 3(dy+1) [+ 9(dz+1)], entries
  * (row w, col p), (row w, col S), (row n, col p), (row n, col S).
- * precision TPF_FP64 -> double, TPF_MIXED -> float (TPF_MIXED grids only). */
+ * precision TPF_FP64 -> double; TPF_MIXED -> float, the FP32 copy (TPF_MIXED grids,
+ * or the finest level of TPF_MIXED16 grids); TPF_MIXED16 -> float, the stored FP16
+ * entries times their row scales (coarse levels of TPF_MIXED16 grids). */
 tpf_status tpf_copy_matrix(tpf_grid *g, int32_t level, int32_t precision, void *dst, tpf_stream stream);
 
 /* y = A_level x with the FP64 level matrix; x, y device double[2 N_level]. */

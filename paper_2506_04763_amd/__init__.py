@@ -19,7 +19,7 @@ from ._lib import (TPF_EBREAKDOWN, TPF_EINVAL, TPF_ENOMEM, TPF_ESTATE, TPF_FP64,
 
 __all__ = ["Grid", "make_desc", "grid_bytes", "validate", "TPFError"]
 
-PRECISIONS = {"fp64": TPF_FP64, "mixed": TPF_MIXED}
+PRECISIONS = {"fp64": TPF_FP64, "mixed": TPF_MIXED, "mixed16": L.TPF_MIXED16}
 
 
 class _Desc:

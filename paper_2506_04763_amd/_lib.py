@@ -17,6 +17,7 @@ TPF_EBREAKDOWN = -4
 TPF_ESTATE = -5
 TPF_FP64 = 0
 TPF_MIXED = 1
+TPF_MIXED16 = 2
 TPF_MAX_PATCHES = 8
 
 STATUS_NAMES = {0: "TPF_OK", 1: "TPF_NOT_CONVERGED", 2: "TPF_STEP_REJECTED", -1: "TPF_EINVAL",

@@ -102,7 +102,8 @@ tpf_status validate(const tpf_grid_desc *d) {
     }
   const long long ncoarse = 2LL * n[0] * n[1] * n[2];
   if (ncoarse > 4096) BAD("coarsest level has %lld unknowns (max 4096): use more levels", ncoarse);
-  if (d->precision != TPF_FP64 && d->precision != TPF_MIXED) BAD("precision must be TPF_FP64 or TPF_MIXED");
+  if (d->precision != TPF_FP64 && d->precision != TPF_MIXED && d->precision != TPF_MIXED16)
+    BAD("precision must be TPF_FP64, TPF_MIXED or TPF_MIXED16");
   if (d->nu_pre < 1 || d->nu_post < 0 || d->nu_pre > 16 || d->nu_post > 16) BAD("need 1 <= nu_pre <= 16, 0 <= nu_post <= 16");
   if (!(d->omega > 0.0 && d->omega < 2.0)) BAD("omega must be in (0, 2)");
   if (d->limex_stages < 0 || d->limex_stages > MAXK) BAD("limex_stages must be in [0, %d]", MAXK);
@@ -121,7 +122,7 @@ void layout(const tpf_grid_desc *d, Layout &L) {
     L.Nl[l] = (long long)L.n[l][0] * L.n[l][1] * L.n[l][2];
   }
   L.nc = (int)(2 * L.Nl[L.L - 1]);
-  const size_t vsz = d->precision == TPF_MIXED ? sizeof(float) : sizeof(double);
+  const size_t vsz = d->precision != TPF_FP64 ? sizeof(float) : sizeof(double);
   size_t o = 0;
   L.off_cells = o;
   o += align_up(4 * L.ncells * sizeof(double));
@@ -132,8 +133,10 @@ void layout(const tpf_grid_desc *d, Layout &L) {
   for (int l = 0; l < L.L; ++l) {
     L.off_lv[l] = o;
     o += align_up((size_t)L.nst * 4 * L.Nl[l] * sizeof(double));
-    if (d->precision == TPF_MIXED)  // the finest FP32 copy is tiled (padded to whole tiles of 64)
+    if (d->precision == TPF_MIXED || (d->precision == TPF_MIXED16 && l == 0))  // finest FP32 copy tiled
       o += align_up((size_t)(l == 0 ? tiled_blocks(L.Nl[0], L.nst) : L.nst * L.Nl[l]) * 4 * sizeof(float));
+    if (d->precision == TPF_MIXED16 && l > 0)  // FP16 blocks + two FP32 row scales per vertex
+      o += align_up((size_t)L.nst * 4 * L.Nl[l] * sizeof(uint16_t)) + align_up(2 * L.Nl[l] * sizeof(float));
     o += align_up(2 * L.Nl[l] * sizeof(double));
     o += 4 * align_up(2 * L.Nl[l] * vsz);
   }
@@ -235,16 +238,25 @@ tpf_status tpf_create_grid(const tpf_grid_desc *d, void *arena, size_t arena_byt
   g->dval = reinterpret_cast<double *>(base + o); o += align_up(2 * L.N * sizeof(double));
   g->Q = reinterpret_cast<double *>(base + o); o += align_up(2 * L.N * sizeof(double));
   g->dmask = reinterpret_cast<uint8_t *>(base + o); o += align_up(L.N);
-  const size_t vsz = d->precision == TPF_MIXED ? sizeof(float) : sizeof(double);
+  const size_t vsz = d->precision != TPF_FP64 ? sizeof(float) : sizeof(double);
   for (int l = 0; l < L.L; ++l) {
     Level &lv = g->lv[l];
     for (int a = 0; a < 3; ++a) lv.n[a] = L.n[l][a];
     lv.N = L.Nl[l];
     o = L.off_lv[l];
     lv.A64 = reinterpret_cast<double *>(base + o); o += align_up((size_t)L.nst * 4 * lv.N * sizeof(double));
-    if (d->precision == TPF_MIXED) {
+    lv.A32 = nullptr;
+    lv.A16 = nullptr;
+    lv.s16 = nullptr;
+    if (d->precision == TPF_MIXED || (d->precision == TPF_MIXED16 && l == 0)) {
       lv.A32 = reinterpret_cast<float *>(base + o);
       o += align_up((size_t)(l == 0 ? tiled_blocks(lv.N, L.nst) : L.nst * lv.N) * 4 * sizeof(float));
+    }
+    if (d->precision == TPF_MIXED16 && l > 0) {
+      lv.A16 = reinterpret_cast<uint16_t *>(base + o);
+      o += align_up((size_t)L.nst * 4 * lv.N * sizeof(uint16_t));
+      lv.s16 = reinterpret_cast<float *>(base + o);
+      o += align_up(2 * lv.N * sizeof(float));
     }
     lv.mst = reinterpret_cast<double *>(base + o); o += align_up(2 * lv.N * sizeof(double));
     lv.x = base + o; o += align_up(2 * lv.N * vsz);
@@ -403,11 +415,13 @@ tpf_status tpf_copy_matrix(tpf_grid *g, int32_t level, int32_t precision, void *
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (precision == TPF_FP64) {
     TPF_HIP(hipMemcpyAsync(dst, lv.A64, cnt * sizeof(double), hipMemcpyDeviceToDevice, s));
-  } else if (precision == TPF_MIXED && g->prec == TPF_MIXED) {
+  } else if (precision == TPF_MIXED && (g->prec == TPF_MIXED || (g->prec == TPF_MIXED16 && level == 0))) {
     if (level == 0) return untile_matrix32(g, reinterpret_cast<float *>(dst), s);
     TPF_HIP(hipMemcpyAsync(dst, lv.A32, cnt * sizeof(float), hipMemcpyDeviceToDevice, s));
+  } else if (precision == TPF_MIXED16 && g->prec == TPF_MIXED16 && level > 0) {
+    return expand_matrix16(g, level, reinterpret_cast<float *>(dst), s);
   } else {
-    set_error("no FP32 matrix on an FP64 grid");
+    set_error("no matrix of that precision on this level");
     return TPF_EINVAL;
   }
   return TPF_OK;

@@ -544,7 +544,7 @@ tpf_status launch_assemble(tpf_grid *g, const double *u0, double h, double *f0, 
   k_vertex_pc<<<nb, BS, 0, s>>>(g->P, u0, g->pdmin, g->lamref, g->pv);
   TPF_LAUNCH_CHECK();
   double *A64 = g->lv[0].A64;
-  float *A32 = g->prec == TPF_MIXED ? g->lv[0].A32 : nullptr;
+  float *A32 = g->prec != TPF_FP64 ? g->lv[0].A32 : nullptr;
   double *mst = g->lv[0].mst;
   const double ih = 1.0 / h;
   const CellIn in = cell_in(g, u0);

@@ -27,6 +27,13 @@ namespace {
 
 typedef float tpf_f4 __attribute__((ext_vector_type(4)));
 typedef double tpf_d2 __attribute__((ext_vector_type(2)));
+typedef _Float16 tpf_h4 __attribute__((ext_vector_type(4)));
+
+// One FP16-stored 2x2 block (raw entries, before the row scales), as floats.
+__device__ __forceinline__ void load_block16(const uint16_t *p, float (&b)[4]) {
+  const tpf_h4 a = *reinterpret_cast<const tpf_h4 *>(p);
+  b[0] = (float)a.x; b[1] = (float)a.y; b[2] = (float)a.z; b[3] = (float)a.w;
+}
 
 // One 2x2 block; NT: non-temporal load for a matrix streamed once per sweep from HBM
 // (the finest level), which leaves the caches to the x gathers.
@@ -48,8 +55,8 @@ __device__ __forceinline__ void load_block(const T *p, T (&b)[4]) {
 // Returns (A x)_v; the centre block is copied out for the smoother.  Neighbours
 // outside the grid have zero blocks; their x value is read at the clamped (valid)
 // position and masked to zero, so no load depends on a branch.
-template <int DIM, typename T, typename TX, bool NT = false, bool TILED = false, int GROUP = 0>
-__device__ __forceinline__ void row_apply(const Geo &G, long long v, const T *__restrict__ A,
+template <int DIM, typename T, typename TX, bool NT = false, bool TILED = false, int GROUP = 0, typename AS = T>
+__device__ __forceinline__ void row_apply(const Geo &G, long long v, const AS *__restrict__ A,
                                           const TX *__restrict__ x, T &y0, T &y1, T (&dblk)[4]) {
   constexpr int NST = DIM == 3 ? 27 : 9;
   constexpr int CEN = DIM == 3 ? 13 : 4;
@@ -75,7 +82,10 @@ __device__ __forceinline__ void row_apply(const Geo &G, long long v, const T *__
     for (int k = 0; k < GRP; ++k) {
       const int o = g0 + k;
       const int ax = o % 3, ay = (o / 3) % 3, az = DIM == 3 ? o / 9 : 1;
-      load_block<T, NT>(A + (TILED ? tiled_block(o, v, NST) : (long long)o * G.N + v) * 4, b[k]);
+      if constexpr (sizeof(AS) == 2)
+        load_block16(A + ((long long)o * G.N + v) * 4, b[k]);
+      else
+        load_block<T, NT>(A + (TILED ? tiled_block(o, v, NST) : (long long)o * G.N + v) * 4, b[k]);
       xv[k] = *reinterpret_cast<const X2 *>(x + 2 * (v + offx[ax] + offy[ay] + offz[az]));
     }
 #pragma unroll
@@ -266,6 +276,94 @@ __global__ void __launch_bounds__(BS) TPF_STREAM_ATTR k_resid_stream(const Geo G
   const long long v = (long long)blk * BS + threadIdx.x;
   if (v >= G.N) return;
   resid_vertex<DIM, T, true, true>(G, A, b, x, r, v);
+}
+
+// Coarse levels stored in FP16 with a scale per scalar row (TPF_MIXED16): the raw
+// row product is multiplied by the row scales, and so is the diagonal block.
+template <int DIM, bool FIRST>
+__global__ void __launch_bounds__(BS) k_jacobi16(const Geo G, const uint16_t *__restrict__ A,
+                                                 const float *__restrict__ sc, const float *__restrict__ b,
+                                                 const float *__restrict__ xi, float *__restrict__ xo,
+                                                 const float omega) {
+  constexpr int CEN = DIM == 3 ? 13 : 4;
+  constexpr int NST = DIM == 3 ? 27 : 9;
+  const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
+  const long long v = (long long)blk * BS + threadIdx.x;
+  if (v >= G.N) return;
+  const float2 s = *reinterpret_cast<const float2 *>(sc + 2 * v);
+  const float2 bb = *reinterpret_cast<const float2 *>(b + 2 * v);
+  float d[4], r0, r1, x0 = 0.f, x1 = 0.f;
+  if (FIRST) {
+    load_block16(A + ((long long)CEN * G.N + v) * 4, d);
+    r0 = bb.x;
+    r1 = bb.y;
+  } else {
+    const float2 xx = *reinterpret_cast<const float2 *>(xi + 2 * v);
+    float a0, a1;
+    row_apply<DIM, float, float, false, false, NST, uint16_t>(G, v, A, xi, a0, a1, d);
+    x0 = xx.x;
+    x1 = xx.y;
+    r0 = bb.x - s.x * a0;
+    r1 = bb.y - s.y * a1;
+  }
+  d[0] *= s.x; d[1] *= s.x; d[2] *= s.y; d[3] *= s.y;
+  float z0, z1;
+  solve2<float>(d, r0, r1, z0, z1);
+  *reinterpret_cast<float2 *>(xo + 2 * v) = make_float2(x0 + omega * z0, x1 + omega * z1);
+}
+
+template <int DIM>
+__global__ void __launch_bounds__(BS) k_resid16(const Geo G, const uint16_t *__restrict__ A,
+                                                const float *__restrict__ sc, const float *__restrict__ b,
+                                                const float *__restrict__ x, float *__restrict__ r) {
+  constexpr int NST = DIM == 3 ? 27 : 9;
+  const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
+  const long long v = (long long)blk * BS + threadIdx.x;
+  if (v >= G.N) return;
+  const float2 s = *reinterpret_cast<const float2 *>(sc + 2 * v);
+  const float2 bb = *reinterpret_cast<const float2 *>(b + 2 * v);
+  float a0, a1, d[4];
+  row_apply<DIM, float, float, false, false, NST, uint16_t>(G, v, A, x, a0, a1, d);
+  *reinterpret_cast<float2 *>(r + 2 * v) = make_float2(bb.x - s.x * a0, bb.y - s.y * a1);
+}
+
+// FP64 level matrix -> FP16 blocks with one scale per scalar row (the row's largest
+// magnitude, 1 for an all-zero row), one thread per vertex.
+template <int DIM>
+__global__ void __launch_bounds__(BS) k_to16(const Geo G, const double *__restrict__ A, uint16_t *__restrict__ A16,
+                                             float *__restrict__ sc) {
+  constexpr int NST = DIM == 3 ? 27 : 9;
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= G.N) return;
+  double m0 = 0.0, m1 = 0.0;
+  for (int o = 0; o < NST; ++o) {
+    const double *p = A + ((long long)o * G.N + v) * 4;
+    m0 = fmax(m0, fmax(fabs(p[0]), fabs(p[1])));
+    m1 = fmax(m1, fmax(fabs(p[2]), fabs(p[3])));
+  }
+  const float s0 = m0 > 0.0 ? (float)m0 : 1.f, s1 = m1 > 0.0 ? (float)m1 : 1.f;
+  *reinterpret_cast<float2 *>(sc + 2 * v) = make_float2(s0, s1);
+  for (int o = 0; o < NST; ++o) {
+    const double *p = A + ((long long)o * G.N + v) * 4;
+    tpf_h4 h;
+    h.x = (_Float16)(float)(p[0] / s0);
+    h.y = (_Float16)(float)(p[1] / s0);
+    h.z = (_Float16)(float)(p[2] / s1);
+    h.w = (_Float16)(float)(p[3] / s1);
+    *reinterpret_cast<tpf_h4 *>(A16 + ((long long)o * G.N + v) * 4) = h;
+  }
+}
+
+// Stored FP16 entries times their row scales, [offset][vertex][4] floats.
+__global__ void k_expand16(const uint16_t *__restrict__ A16, const float *__restrict__ sc, float *__restrict__ dst,
+                           long long N, int nst) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)nst * N) return;
+  const long long v = t % N;
+  float b[4];
+  load_block16(A16 + t * 4, b);
+  const float2 s = *reinterpret_cast<const float2 *>(sc + 2 * v);
+  *reinterpret_cast<float4 *>(dst + t * 4) = make_float4(b[0] * s.x, b[1] * s.x, b[2] * s.y, b[3] * s.y);
 }
 
 // Restriction bc = P^T rf.  Pressure component: (bi/tri)linear weights
@@ -663,6 +761,36 @@ __global__ void k_untile(const float *__restrict__ src, float *__restrict__ dst,
 }
 
 // ---- V-cycle driver ----------------------------------------------------------
+// TPF_MIXED16 coarse levels: sweep (first: zero initial guess) and residual with the
+// FP16 matrix; return false where the level is not stored in FP16.
+template <int DIM, typename T>
+bool sweep16(tpf_grid *g, int l, bool first, const T *b, const T *xi, T *xo, T om, hipStream_t s) {
+  if constexpr (sizeof(T) != sizeof(float)) {
+    return false;
+  } else {
+    if (g->prec != TPF_MIXED16 || l == 0) return false;
+    const Level &lv = g->lv[l];
+    const unsigned nb = blocks_for(lv.N);
+    if (first)
+      k_jacobi16<DIM, true><<<nb, BS, 0, s>>>(geo(lv), lv.A16, lv.s16, b, nullptr, xo, om);
+    else
+      k_jacobi16<DIM, false><<<nb, BS, 0, s>>>(geo(lv), lv.A16, lv.s16, b, xi, xo, om);
+    return true;
+  }
+}
+
+template <int DIM, typename T>
+bool resid16(tpf_grid *g, int l, const T *b, const T *x, T *r, hipStream_t s) {
+  if constexpr (sizeof(T) != sizeof(float)) {
+    return false;
+  } else {
+    if (g->prec != TPF_MIXED16 || l == 0) return false;
+    const Level &lv = g->lv[l];
+    k_resid16<DIM><<<blocks_for(lv.N), BS, 0, s>>>(geo(lv), lv.A16, lv.s16, b, x, r);
+    return true;
+  }
+}
+
 // Levels up to this many vertices are latency-bound: their sweeps issue a row's
 // loads all at once (LAT) instead of in register-friendly groups.
 constexpr long long LAT_NMAX = 65536;
@@ -706,7 +834,8 @@ tpf_status vcycle_t(tpf_grid *g, const double *bin, double *xout, hipStream_t s)
     const unsigned nb = blocks_for(lv.N);
     T *X = reinterpret_cast<T *>(lv.x), *Y = reinterpret_cast<T *>(lv.y);
     int ps = prof_begin(g, l == 0 ? TPF_K_SMOOTH0_FIRST : TPF_K_COARSE_LEVELS, s);
-    if (l == 0 && NT0)
+    if (sweep16<DIM, T>(g, l, true, bl[l], nullptr, X, om, s)) {
+    } else if (l == 0 && NT0)
       k_jacobi<DIM, T, T, true, false, true><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], nullptr, X, om);
     else
       k_jacobi<DIM, T, T, true><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], nullptr, X, om);
@@ -714,7 +843,8 @@ tpf_status vcycle_t(tpf_grid *g, const double *bin, double *xout, hipStream_t s)
     prof_end(g, ps, s);
     for (int k = 1; k < g->nu_pre; ++k) {
       ps = prof_begin(g, l == 0 ? TPF_K_SMOOTH0 : TPF_K_COARSE_LEVELS, s);
-      if (l == 0 && NT0)
+      if (sweep16<DIM, T>(g, l, false, bl[l], X, Y, om, s)) {
+      } else if (l == 0 && NT0)
         k_jacobi_stream<DIM, T, T><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, Y, om);
       else if (lv.N > LAT_NMAX)
         k_jacobi<DIM, T, T, false><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, Y, om);
@@ -727,7 +857,8 @@ tpf_status vcycle_t(tpf_grid *g, const double *bin, double *xout, hipStream_t s)
     cur[l] = X;
     T *R = reinterpret_cast<T *>(lv.r);
     ps = prof_begin(g, l == 0 ? TPF_K_RESID0 : TPF_K_COARSE_LEVELS, s);
-    if (l == 0 && NT0)
+    if (resid16<DIM, T>(g, l, bl[l], X, R, s)) {
+    } else if (l == 0 && NT0)
       k_resid_stream<DIM, T><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, R);
     else if (lv.N > LAT_NMAX)
       k_resid<DIM, T><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, R);
@@ -776,7 +907,8 @@ tpf_status vcycle_t(tpf_grid *g, const double *bin, double *xout, hipStream_t s)
         X = nullptr;
         break;
       }
-      if (l == 0 && NT0)
+      if (sweep16<DIM, T>(g, l, false, bl[l], X, Y, om, s)) {
+      } else if (l == 0 && NT0)
         k_jacobi_stream<DIM, T, T><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, Y, om);
       else if (lv.N > LAT_NMAX)
         k_jacobi<DIM, T, T, false><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, Y, om);
@@ -805,6 +937,10 @@ tpf_status hierarchy_t(tpf_grid *g, hipStream_t s) {
     const tpf_status st = launch_rap(g->dim, l == 0, f.n, f.N, c.n, c.N, f.A64, l == 0 ? g->dmask : nullptr, f.mst,
                                      g->rapb, c.A64, c32, c.mst, s);
     if (st != TPF_OK) return st;
+    if (g->prec == TPF_MIXED16) {
+      k_to16<DIM><<<blocks_for(c.N), BS, 0, s>>>(geo(c), c.A64, c.A16, c.s16);
+      TPF_LAUNCH_CHECK();
+    }
     prof_end(g, ps, s);
   }
   Level &lc = g->lv[g->L - 1];
@@ -859,12 +995,20 @@ tpf_status untile_matrix32(tpf_grid *g, float *dst, hipStream_t s) {
   return TPF_OK;
 }
 
+tpf_status expand_matrix16(tpf_grid *g, int level, float *dst, hipStream_t s) {
+  const Level &lv = g->lv[level];
+  const long long n = (long long)g->nst * lv.N;
+  k_expand16<<<blocks_for(n), BS, 0, s>>>(lv.A16, lv.s16, dst, lv.N, g->nst);
+  TPF_LAUNCH_CHECK();
+  return TPF_OK;
+}
+
 tpf_status build_hierarchy(tpf_grid *g, hipStream_t s) {
   return g->dim == 3 ? hierarchy_t<3>(g, s) : hierarchy_t<2>(g, s);
 }
 
 tpf_status vcycle(tpf_grid *g, const double *b, double *x, hipStream_t s) {
-  if (g->prec == TPF_MIXED)
+  if (g->prec != TPF_FP64)
     return g->dim == 3 ? vcycle_t<3, float>(g, b, x, s) : vcycle_t<2, float>(g, b, x, s);
   return g->dim == 3 ? vcycle_t<3, double>(g, b, x, s) : vcycle_t<2, double>(g, b, x, s);
 }

@@ -58,7 +58,9 @@ struct Level {
   int n[3];
   long long N;
   double *A64;  // [nst][N][4]
-  float *A32;   // [nst][N][4] (mixed precision only)
+  float *A32;   // [nst][N][4] (mixed precision only; tiled on the finest level)
+  uint16_t *A16;  // [nst][N][4] FP16 bits (coarse levels of TPF_MIXED16)
+  float *s16;     // [N][2] row scales of A16
   double *mst;  // [N][2] storage part of the centre block, (w,S) and (n,S) entries
   void *x, *y, *b, *r;  // level vectors, 2N entries of the level type
 };
@@ -171,6 +173,8 @@ tpf_status launch_apply_dirichlet(tpf_grid *g, double *u, hipStream_t s);
 tpf_status build_hierarchy(tpf_grid *g, hipStream_t s);
 // The finest FP32 matrix in the [offset][vertex] layout of the ABI (dst: nst*4*N floats).
 tpf_status untile_matrix32(tpf_grid *g, float *dst, hipStream_t s);
+// A coarse level's FP16 matrix as floats (entries times row scales), [offset][vertex][4].
+tpf_status expand_matrix16(tpf_grid *g, int level, float *dst, hipStream_t s);
 tpf_status vcycle(tpf_grid *g, const double *b, double *x, hipStream_t s);
 // y = A x (FP64, level l); if dot_with != null also block partials of (dot_with, y)
 // and, if second != null, (second, y) and (y, y) as selected by mode.

@@ -38,10 +38,11 @@ def test_struct_layouts_match_header():
     assert C.sizeof(L.LimexStats) == 40
 
 
-def _bytes_expected(scn, prec_bytes, limex=0):
+def _bytes_expected(scn, prec, limex=0):
     """Independent re-derivation of the arena size from the documented layout."""
     al = lambda x: (x + 255) // 256 * 256  # noqa: E731
     nst = 27 if scn.dim == 3 else 9
+    vb = 8 if prec == "fp64" else 4  # level-vector entry bytes
     N = scn.nverts
     n = list(scn.n)
     sizes = [tuple(n)]
@@ -51,10 +52,15 @@ def _bytes_expected(scn, prec_bytes, limex=0):
     tot = al(4 * scn.ncells * 8) + 2 * al(N * 8) + 3 * al(2 * N * 8) + al(N)
     for lvl, s in enumerate(sizes):
         Nl = s[0] * s[1] * s[2]
-        # the finest FP32 copy is stored in whole tiles of 64 vertices
-        n32 = (Nl + 63) // 64 * 64 if lvl == 0 else Nl
-        tot += al(nst * 4 * Nl * 8) + (al(nst * 4 * n32 * 4) if prec_bytes == 4 else 0) + al(2 * Nl * 8)
-        tot += 4 * al(2 * Nl * prec_bytes)
+        tot += al(nst * 4 * Nl * 8)
+        if prec == "mixed" or (prec == "mixed16" and lvl == 0):
+            # FP32 copy; the finest one is stored in whole tiles of 64 vertices
+            n32 = (Nl + 63) // 64 * 64 if lvl == 0 else Nl
+            tot += al(nst * 4 * n32 * 4)
+        if prec == "mixed16" and lvl > 0:  # FP16 blocks and two FP32 row scales per vertex
+            tot += al(nst * 4 * Nl * 2) + al(2 * Nl * 4)
+        tot += al(2 * Nl * 8)
+        tot += 4 * al(2 * Nl * vb)
     nc = 2 * sizes[-1][0] * sizes[-1][1] * sizes[-1][2]
     tot += 2 * al(nc * nc * 8) + al(nc * 4)
     tot += al(nst * 4 * N * 8) if scn.levels > 1 else 0   # Galerkin-product scratch
@@ -64,13 +70,13 @@ def _bytes_expected(scn, prec_bytes, limex=0):
     return tot
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "mixed16"])
 def test_grid_bytes(prec):
     scn = W.small_cube(17, levels=3)
     nb = tpf.grid_bytes(scn, precision=prec)
-    assert nb == _bytes_expected(scn, 8 if prec == "fp64" else 4)
+    assert nb == _bytes_expected(scn, prec)
     scn2 = W.lens_2d()
-    assert tpf.grid_bytes(scn2, precision=prec, limex_stages=2) == _bytes_expected(scn2, 8 if prec == "fp64" else 4, 2)
+    assert tpf.grid_bytes(scn2, precision=prec, limex_stages=2) == _bytes_expected(scn2, prec, 2)
 
 
 def test_grid_bytes_c3_fits_hbm():

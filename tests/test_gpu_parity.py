@@ -170,6 +170,34 @@ def test_solve_mixed_precision(case):
     g.close()
 
 
+def test_solve_mixed16_coarse_levels(case):
+    """TPF_MIXED16: the coarse-level matrices are stored in FP16 with one scale per
+    scalar row (the row's largest magnitude); the finest level stays FP32."""
+    scn = case["scn"]
+    g = tpf.Grid(scn, precision="mixed16")
+    g.assemble_stage(torch.as_tensor(case["u"].ravel(), device="cuda"), case["h"])
+    a0 = g.matrix(0, "fp64").cpu().numpy()
+    np.testing.assert_array_equal(g.matrix(0, "mixed").cpu().numpy(), a0.astype(np.float32))
+    for l in range(1, scn.levels):
+        a64 = g.matrix(l, "fp64").cpu().numpy()
+        a16 = g.matrix(l, "mixed16").cpu().numpy().astype(np.float64)
+        for r in (0, 1):  # scalar row r of every vertex: entries 2r, 2r+1 of all blocks
+            rows64 = a64[:, :, 2 * r:2 * r + 2]
+            scale = np.abs(rows64).max(axis=(0, 2))
+            scale = np.where(scale > 0, scale, 1.0)
+            err = np.abs(a16[:, :, 2 * r:2 * r + 2] - rows64).max(axis=(0, 2))
+            # FP16 rounding of entries scaled into [-1, 1], plus the FP32 steps around it
+            assert np.all(err <= (2.0 ** -11 + 2.0 ** -21) * scale), (l, r, float((err / scale).max()))
+    x, st = g.solve_stage(torch.as_tensor(case["F"], device="cuda"), rtol=1e-8, maxit=400)
+    x_tight, _ = case["ref"].solve(case["F"], rtol=1e-13, maxit=400)
+    err = per_field(x.cpu().numpy(), x_tight)
+    print(case["name"], "mixed16", st, "err vs oracle", err, flush=True)
+    assert st["status"] == "TPF_OK"
+    assert st["rel_res_true"] <= 1e-8
+    assert err < 1e-5
+    g.close()
+
+
 def test_repeat_runs_bitwise_equal(case):
     scn = case["scn"]
     g = tpf.Grid(scn, precision="mixed")
