@@ -88,7 +88,8 @@ def hat_sn(sn, pdmin, lam_ref, pd_e, lam_e, swr, snr):
     p_vert = pdmin * eff_sat(sn, swr, snr) ** (-1.0 / lam_ref)
     case1 = pd_e == pdmin
     case2 = pd_e >= np.real(p_vert)
-    se_star = (p_vert / pd_e) ** (-lam_e)
+    with np.errstate(divide="ignore", invalid="ignore"):  # case 3 is unused where p_d,e = 0
+        se_star = (p_vert / pd_e) ** (-lam_e)
     sn3 = 1.0 - (swr + se_star * dd)
     return np.where(case1, sn, np.where(case2, snr + 0 * sn, sn3))
 

@@ -8,9 +8,24 @@ here:
     on the finest level the rows of P at Dirichlet components are zero;
   * restriction R = P^T; coarse operators are Galerkin products of the flux part
     plus a lumped storage part:
-        A_{l+1} = P^T (A_l - S_l) P + S_{l+1},
-        S_{l+1} = row-sum lumping of P^T S_l P placed on the S_n column,
-    where S_0 = M(u0)/h (zero on Dirichlet rows) is the box method's diagonal storage.
+        A_{l+1} = P^T (A'_l - S'_l) P + S_{l+1},
+        S_{l+1} = row-sum lumping of P^T S'_l P placed on the S_n column,
+    where S_0 = M(u0)/h (zero on Dirichlet rows) is the box method's diagonal storage,
+    A'_l = A_l and S'_l = S_l on the coarse levels, and on the finest level
+    A'_0 = T A_0, S'_0 = T S_0 with the volume-balance row transform T below;
+  * volume-balance form of the coarse-grid correction: T is block diagonal; at each
+    vertex without a Dirichlet component it replaces the wetting-phase mass balance
+    by itself plus rho_w/rho_n times the non-wetting one (rho_w times the balance of
+    pore volume, whose storage cancels for incompressible phases), other rows
+    unchanged.  The restriction of the finest residual is P^T T r.  The pairing of the
+    linear P with the wetting equation needs the equation that carries the pressure
+    Laplacian: with the mass balances as they stand, a region where the wetting phase
+    is immobile (k_rw = 0, e.g. ahead of a displacement front) leaves the pressure only
+    in the non-wetting equation, restricted by aggregation, and the coarse operators
+    become singular; the volume balance carries the total-mobility Laplacian wherever
+    either phase moves.  Block Jacobi is invariant under a block-diagonal row
+    transform ((TD)^{-1} T (b - A x) = D^{-1} (b - A x)), so the finest level is
+    smoothed with A_0 itself;
     The plain product P^T A P turns the diagonal storage into a 27-point
     consistent-mass block whose Jacobi spectrum reaches 27/8 > 2/omega; keeping
     the coarse storage lumped, as the box method has it on the fine grid, keeps the
@@ -107,19 +122,37 @@ def lumped_storage(P, S):
     return sp.csr_matrix((d, (rows, cols)), shape=(n2, n2))
 
 
+def volume_balance(dir_mask, rho) -> sp.csr_matrix:
+    """The row transform T of the coarse-grid correction (module docstring): identity,
+    plus rho_w/rho_n in the (w, n) position of every vertex without a Dirichlet
+    component."""
+    N = dir_mask.size
+    free = np.nonzero(dir_mask == 0)[0]
+    rows = np.concatenate([np.arange(2 * N), 2 * free])
+    cols = np.concatenate([np.arange(2 * N), 2 * free + 1])
+    vals = np.concatenate([np.ones(2 * N), np.full(free.size, rho[0] / rho[1])])
+    return sp.csr_matrix((vals, (rows, cols)), shape=(2 * N, 2 * N))
+
+
 class Hierarchy:
-    def __init__(self, A0, n, dim, levels, dir_mask, omega=2.0 / 3.0, nu1=2, nu2=2, S0=None):
-        """S0: storage part of A0 (block diagonal, S_n column only); None means zero."""
+    def __init__(self, A0, n, dim, levels, dir_mask, omega=2.0 / 3.0, nu1=2, nu2=2, S0=None, T0=None):
+        """S0: storage part of A0 (block diagonal, S_n column only); None means zero.
+        T0: row transform of the finest level for the coarse-grid correction (None:
+        identity)."""
         self.sizes = level_sizes(n, dim, levels)
         self.A = [sp.csr_matrix(A0)]
         S = sp.csr_matrix(A0.shape) if S0 is None else sp.csr_matrix(S0)
         self.S = [S]
+        self.T0 = sp.identity(A0.shape[0], format="csr") if T0 is None else sp.csr_matrix(T0)
         self.P = []
         for l in range(levels - 1):
             P = prolongation(self.sizes[l], dim, dir_mask if l == 0 else None)
             self.P.append(P)
-            Sc = lumped_storage(P, self.S[-1])
-            Ac = P.T @ (self.A[-1] - self.S[-1]) @ P + Sc
+            Af, Sf = self.A[-1], self.S[-1]
+            if l == 0:
+                Af, Sf = self.T0 @ Af, self.T0 @ Sf
+            Sc = lumped_storage(P, Sf)
+            Ac = P.T @ (Af - Sf) @ P + Sc
             # coarse DoFs whose prolongation column is empty (an aggregate made only
             # of Dirichlet components) are decoupled: give them a unit diagonal
             empty = np.asarray(abs(P).sum(axis=0)).ravel() == 0.0
@@ -144,6 +177,8 @@ class Hierarchy:
             return sla.lu_solve(self.lu, b)
         x = self.smooth(l, np.zeros_like(b), b, self.nu1)
         r = b - self.A[l] @ x
+        if l == 0:
+            r = self.T0 @ r
         e = self.vcycle(self.P[l].T @ r, l + 1)
         x = x + self.P[l] @ e
         return self.smooth(l, x, b, self.nu2)

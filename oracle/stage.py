@@ -26,8 +26,9 @@ class Stage:
     def assemble(self, u0, h):
         self.A = self.fv.stage_matrix(u0.reshape(-1, 2), h)
         S0 = self.fv.storage_part(u0.reshape(-1, 2), h)
+        T0 = _gmg.volume_balance(self.fv.dir_mask, self.scn.rho)
         self.H = _gmg.Hierarchy(self.A, self.scn.n, self.scn.dim, self.levels, self.fv.dir_mask,
-                                self.omega, self.nu1, self.nu2, S0=S0)
+                                self.omega, self.nu1, self.nu2, S0=S0, T0=T0)
         return self.A
 
     def solve(self, f, rtol=1e-10, maxit=500):

@@ -326,12 +326,20 @@ def test_galerkin_and_two_grid_contraction():
     H = st.H
     P = H.P[0].toarray()
     S0 = H.S[0].toarray()
+    # the row transform of the finest level, built here from its definition: the
+    # wetting row of each vertex without Dirichlet components gains rho_w/rho_n times
+    # the non-wetting row
+    T = np.eye(A.shape[0])
+    for v in np.nonzero(scn.dir_mask == 0)[0]:
+        T[2 * v, 2 * v + 1] = scn.rho[0] / scn.rho[1]
+    np.testing.assert_array_equal(H.T0.toarray(), T)
     # flux part: exact Galerkin product of the fine flux part, plus a unit diagonal on
     # coarse unknowns whose prolongation column is empty (all-Dirichlet aggregates)
     empty = np.abs(P).sum(axis=0) == 0
     assert empty.sum() > 0 and np.all(np.nonzero(empty)[0] % 2 == 1)
-    np.testing.assert_allclose((H.A[1] - H.S[1]).toarray(), P.T @ (A.toarray() - S0) @ P + np.diag(empty * 1.0),
+    np.testing.assert_allclose((H.A[1] - H.S[1]).toarray(), P.T @ T @ (A.toarray() - S0) @ P + np.diag(empty * 1.0),
                                rtol=0, atol=1e-12 * np.abs(A).max())
+    S0 = T @ S0
     # lumped coarse storage: diagonal blocks, S_n column only, total storage conserved
     Sc = H.S[1].toarray()
     off = Sc.copy()
@@ -457,6 +465,55 @@ def test_integration_point_exact_for_bilinear_pressure(dim):
     # inflow into b_0 = K/mu rho * (int_{x-face} dp/dx + int_{y-face} dp/dy); z-face: dp/dz = 0
     expect = 1000.0 * 2e-11 / 1e-3 * 1e3 * (dy ** 2 / 8 + dx ** 2 / 8) * depth
     assert F[0, 0] == pytest.approx(expect, rel=1e-12)
+
+
+def test_volume_balance_has_no_storage_and_leaves_block_jacobi_unchanged():
+    """The transformed wetting row is rho_w times the pore-volume balance: its storage
+    part vanishes for incompressible phases (to rounding), on every cell of a
+    heterogeneous interface case.  A block-diagonal row transform T leaves damped
+    block Jacobi unchanged, (TD)^{-1}(Tb - TAx) = D^{-1}(b - Ax), which is why the
+    finest level may be smoothed with A itself."""
+    scn = W.lens_2d(17, 9)
+    scn.rho = (1000.0, 1460.0)
+    st = ST.Stage(scn, levels=2)
+    u = W.perturbed_state(scn, 5, sn_lo=0.05, sn_hi=0.5)
+    A = st.assemble(u.ravel(), 32.0)
+    T = st.H.T0
+    S0 = st.fv.storage_part(u, 32.0)
+    TS = (T @ S0).toarray()
+    free = np.nonzero(scn.dir_mask == 0)[0]
+    assert np.abs(TS[2 * free]).max() <= 1e-15 * np.abs(S0).max()
+    np.testing.assert_array_equal(TS[1::2], S0.toarray()[1::2])
+    assert np.abs(S0.toarray()[2 * free]).max() > 0.0
+    rng = np.random.default_rng(1)
+    x0, b = rng.standard_normal(A.shape[0]), rng.standard_normal(A.shape[0])
+    Ht = G.Hierarchy(T @ A, scn.n, scn.dim, 1, scn.dir_mask)
+    H1 = G.Hierarchy(A, scn.n, scn.dim, 1, scn.dir_mask)
+    xa = Ht.smooth(0, x0, T @ b, 3)
+    xb = H1.smooth(0, x0, b, 3)
+    assert np.linalg.norm(xa - xb) <= 1e-12 * np.linalg.norm(xb)
+
+
+def test_coarse_operators_regular_when_the_wetting_phase_is_immobile():
+    """Case 1 of Section 5 at its initial state: ahead of the front S_w = 0, so only
+    the non-wetting equation holds the pressure.  With the mass balances restricted as
+    they stand, the aggregation restriction of that equation leaves the coarse
+    operators singular; in volume-balance form they are regular, and GMG-BiCGSTAB
+    reproduces the sparse direct solution."""
+    import scipy.sparse.linalg as ssl
+    scn = W.buckley_leverett(32)
+    st = ST.Stage(scn)
+    u = scn.u0.ravel()
+    A = st.assemble(u, 1.0)
+    f = st.residual(u)
+    plain = G.Hierarchy(A, scn.n, scn.dim, st.levels, scn.dir_mask, S0=st.fv.storage_part(scn.u0, 1.0))
+    assert np.linalg.cond(plain.A[-1].toarray()) > 1e14
+    assert np.linalg.cond(st.H.A[-1].toarray()) < 1e10
+    x, info = st.solve(f, rtol=1e-12, maxit=50)
+    xd = ssl.spsolve(A.tocsc(), f)
+    assert info["iters"] <= 10
+    for c in range(2):
+        assert np.linalg.norm(x[c::2] - xd[c::2]) <= 1e-9 * np.linalg.norm(xd[c::2])
 
 
 def test_vcycle_is_a_contraction_on_a_heterogeneous_cube():

@@ -181,6 +181,50 @@ def lens_2d(nx: int = 65, ny: int = 33) -> Scenario:
     return scn
 
 
+BL_LENGTH, BL_HEIGHT = 300.0, 75.0
+BL_PORO, BL_PERM, BL_LAMBDA = 0.2, 1e-7, 2.0
+BL_P_LEFT = 2e5          # Pa, Dirichlet p_n = p_w at x = 0
+BL_OUTFLOW = 3e-4        # kg/(m^2 s) of the non-wetting phase leaving through x = 300 m
+BL_T_END = 1500 * 86400.0
+
+
+def buckley_leverett(elements: int = 64, levels: Optional[int] = None) -> Scenario:
+    """Case 1 of Section 5 (Buckley-Leverett displacement, Table case1).
+
+    A 300 m x 75 m strip of `elements` x elements/4 square cells; porosity 0.2,
+    K = 1e-7 m^2; equal densities (1000 kg/m^3) and viscosities (1e-3 Pa s); no
+    residual saturations; no capillary pressure (entry pressure 0); Brooks-Corey
+    lambda = 2; no gravity (the two densities are equal and the displacement is
+    horizontal).  x = 0: Dirichlet S_w = 1 (S_n = 0) and p_n = p_w = 2e5 Pa.
+    x = 300 m: the non-wetting phase leaves at 3e-4 kg/(m^2 s) per unit depth.  Other
+    faces are closed.  Initially S_w = 0; the initial p_w is the steady single-phase
+    profile of that outflow (p_w is algebraic, so only its consistency matters)."""
+    if elements % 4:
+        raise ValueError("elements must be a multiple of 4")
+    nx, ny = elements + 1, elements // 4 + 1
+    scn = _empty(f"bl_{elements}", 2, (nx, ny, 1), (BL_LENGTH, BL_HEIGHT, 1.0), (0.0, 0.0, 0.0))
+    scn.rho = (1000.0, 1000.0)
+    scn.mu = (1e-3, 1e-3)
+    nc = scn.ncells
+    scn.perm = np.full(nc, BL_PERM)
+    scn.poro = np.full(nc, BL_PORO)
+    scn.entry_p = np.zeros(nc)
+    scn.bc_lambda = np.full(nc, BL_LAMBDA)
+    x, _, _ = scn.vertex_coords()
+    darcy = BL_OUTFLOW / scn.rho[1]                      # m/s
+    p = BL_P_LEFT - darcy * scn.mu[1] / BL_PERM * x
+    left = np.isclose(x, 0.0)
+    scn.dir_mask = np.where(left, 3, 0).astype(np.uint8)
+    scn.dir_value = np.stack([np.full_like(x, BL_P_LEFT), np.zeros_like(x)], axis=1)
+    scn.patches = [Patch(axis=0, side=1, lo=(0.0, 0.0), hi=(BL_HEIGHT, 0.0), rate=-BL_OUTFLOW, phase=1)]
+    sn = np.where(left, 0.0, 1.0)
+    scn.u0 = np.stack([np.where(left, BL_P_LEFT, p), sn], axis=1)
+    scn.levels = default_levels(ny) if levels is None else levels
+    scn.meta = dict(case="buckley_leverett", elements=elements, t_end=BL_T_END, dt0=1.0,
+                    dt_max=100 * 86400.0, tol=5e-2, safety=0.25, stages=2)
+    return scn
+
+
 def _empty(name, dim, n, extent, gravity) -> Scenario:
     N = int(n[0] * n[1] * n[2])
     return Scenario(name=name, dim=dim, n=tuple(int(v) for v in n), extent=tuple(map(float, extent)),
