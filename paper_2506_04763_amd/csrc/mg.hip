@@ -369,11 +369,14 @@ __global__ void k_expand16(const uint16_t *__restrict__ A16, const float *__rest
 // Restriction bc = P^T rf.  Pressure component: (bi/tri)linear weights
 // (1/2)^{|d|_1} over the 3^d fine neighbours of vertex 2I.  Saturation component:
 // piecewise-constant aggregation, the sum over fine vertices 2I + d, d in {-1, 0}^d.
-// Fine Dirichlet components (finest level) are excluded.
+// On the finest level (fmask given) Dirichlet components are excluded and the
+// residual enters in the volume-balance form of the Galerkin product: at vertices
+// without Dirichlet components the wetting entry becomes r_w + vr r_n.
 template <int DIM, typename T>
 __host__ __device__ __forceinline__ void restrict_vertex(long long I, const Geo &F, const Geo &C,
                                                         const T *__restrict__ rf,
-                                                        const uint8_t *__restrict__ fmask, T *__restrict__ bc) {
+                                                        const uint8_t *__restrict__ fmask, const T vr,
+                                                        T *__restrict__ bc) {
   int cx, cy, cz;
   vcoords(I, C, cx, cy, cz);
   const int fx = 2 * cx, fy = 2 * cy, fz = DIM == 3 ? 2 * cz : 0;
@@ -390,6 +393,7 @@ __host__ __device__ __forceinline__ void restrict_vertex(long long I, const Geo 
         T r0 = rv.x, r1 = rv.y;
         if (fmask) {
           const uint8_t m = fmask[i];
+          if (!m) r0 += vr * r1;
           if (m & 1) r0 = 0;
           if (m & 2) r1 = 0;
         }
@@ -404,10 +408,11 @@ __host__ __device__ __forceinline__ void restrict_vertex(long long I, const Geo 
 
 template <int DIM, typename T>
 __global__ void __launch_bounds__(BS) k_restrict(const Geo F, const Geo C, const T *__restrict__ rf,
-                                                 const uint8_t *__restrict__ fmask, T *__restrict__ bc) {
+                                                 const uint8_t *__restrict__ fmask, const T vr,
+                                                 T *__restrict__ bc) {
   const long long I = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (I >= C.N) return;
-  restrict_vertex<DIM, T>(I, F, C, rf, fmask, bc);
+  restrict_vertex<DIM, T>(I, F, C, rf, fmask, vr, bc);
 }
 
 // Prolongation and correction xf += P ec: linear interpolation of the pressure
@@ -869,7 +874,8 @@ tpf_status vcycle_t(tpf_grid *g, const double *bin, double *xout, hipStream_t s)
     Level &lc = g->lv[l + 1];
     T *bc = reinterpret_cast<T *>(lc.b);
     ps = prof_begin(g, l == 0 ? TPF_K_TRANSFER0 : TPF_K_COARSE_LEVELS, s);
-    k_restrict<DIM, T><<<blocks_for(lc.N), BS, 0, s>>>(G, geo(lc), R, l == 0 ? g->dmask : nullptr, bc);
+    k_restrict<DIM, T><<<blocks_for(lc.N), BS, 0, s>>>(G, geo(lc), R, l == 0 ? g->dmask : nullptr,
+                                                       (T)(g->P.rho_w / g->P.rho_n), bc);
     TPF_LAUNCH_CHECK();
     prof_end(g, ps, s);
     bl[l + 1] = bc;
@@ -935,7 +941,7 @@ tpf_status hierarchy_t(tpf_grid *g, hipStream_t s) {
     float *c32 = g->prec == TPF_MIXED ? c.A32 : nullptr;
     const int ps = prof_begin(g, TPF_K_RAP, s);
     const tpf_status st = launch_rap(g->dim, l == 0, f.n, f.N, c.n, c.N, f.A64, l == 0 ? g->dmask : nullptr, f.mst,
-                                     g->rapb, c.A64, c32, c.mst, s);
+                                     g->P.rho_w / g->P.rho_n, g->rapb, c.A64, c32, c.mst, s);
     if (st != TPF_OK) return st;
     if (g->prec == TPF_MIXED16) {
       k_to16<DIM><<<blocks_for(c.N), BS, 0, s>>>(geo(c), c.A64, c.A16, c.s16);

@@ -5,7 +5,14 @@
 // S_f the storage part of the fine centre blocks.  P interpolates each component
 // separately: (bi/tri)linearly for the pressure, by piecewise-constant aggregation
 // (coarse I <- fine 2I-1, 2I per axis) for the saturation; on the finest level the
-// rows of P at Dirichlet components are zero.  The product is formed in two passes
+// rows of P at Dirichlet components are zero.  On the finest level the rows enter
+// in volume-balance form: at a vertex without Dirichlet components the wetting
+// row becomes itself plus vr = rho_w/rho_n times the non-wetting row (storage and
+// flux parts alike), so that the row restricted by the linear P carries the
+// total-mobility pressure Laplacian even where the wetting phase is immobile; the
+// smoother is unaffected (block Jacobi is invariant under a block-diagonal row
+// transform) and the restriction of the finest residual applies the same transform.
+// The product is formed in two passes
 // through a scratch array (A P first, then P^T (A P); see below).  A coarse unknown
 // whose prolongation column is empty (an aggregate made only of Dirichlet
 // components) is decoupled and gets a unit diagonal.
@@ -23,8 +30,8 @@ __host__ __device__ __forceinline__ double agg_row(int d) { return d <= 0 ? 1.0 
 template <int DIM, bool MASK>
 __host__ __device__ __forceinline__ void rap_storage(long long I, const Geo &F, const Geo &C,
                                                     const uint8_t *__restrict__ fmask,
-                                                    const double *__restrict__ mf, double &ms0, double &ms1,
-                                                    bool &live0, bool &live1) {
+                                                    const double *__restrict__ mf, double vr, double &ms0,
+                                                    double &ms1, bool &live0, bool &live1) {
   int cx, cy, cz;
   vcoords(I, C, cx, cy, cz);
   const long long sy = F.nx, sz = (long long)F.nx * F.ny;
@@ -40,9 +47,10 @@ __host__ __device__ __forceinline__ void rap_storage(long long I, const Geo &F, 
         const long long i = fx + sy * fy + sz * fz;
         const double wl = lin_row(dx) * lin_row(dy) * (DIM == 3 ? lin_row(dz) : 1.0);
         const double wa = agg_row(dx) * agg_row(dy) * (DIM == 3 ? agg_row(dz) : 1.0);
-        double k0 = 1.0, k1 = 1.0;
+        double k0 = 1.0, k1 = 1.0, s0 = mf[2 * i];
         if (MASK) {
           const uint8_t m = fmask[i];
+          if (!m) s0 += vr * mf[2 * i + 1];   // volume-balance row
           if (m & 2) { k0 = 0.0; k1 = 0.0; }  // keep_S(i) = 0: no lumped storage at i
           if (m & 1) k0 = 0.0;                 // keep_p(i) = 0
           if (!(m & 1)) live0 = true;
@@ -51,7 +59,7 @@ __host__ __device__ __forceinline__ void rap_storage(long long I, const Geo &F, 
           live0 = true;
           if (wa != 0.0) live1 = true;
         }
-        ms0 += wl * k0 * mf[2 * i];
+        ms0 += wl * k0 * s0;
         ms1 += wa * k1 * mf[2 * i + 1];
       }
 }
@@ -76,7 +84,7 @@ template <int DIM, bool MASK>
 __host__ __device__ __forceinline__ void rap_ap_entry(long long i, int slot, const Geo &F, const Geo &C,
                                                      const double *__restrict__ Af,
                                                      const uint8_t *__restrict__ fmask,
-                                                     const double *__restrict__ mf, double (&b)[4]) {
+                                                     const double *__restrict__ mf, double vr, double (&b)[4]) {
   constexpr int CEN = DIM == 3 ? 13 : 4;
   b[0] = b[1] = b[2] = b[3] = 0.0;
   int fx, fy, fz;
@@ -119,6 +127,10 @@ __host__ __device__ __forceinline__ void rap_ap_entry(long long i, int slot, con
         b[3] += e3 * wa;
       }
     }
+  }
+  if (MASK && !fmask[i]) {  // volume-balance row of a vertex without Dirichlet components
+    b[0] += vr * b[2];
+    b[1] += vr * b[3];
   }
 }
 
@@ -170,7 +182,7 @@ template <int DIM, bool MASK>
 __host__ __device__ __forceinline__ void rap_block(long long I, int T, const Geo &F, const Geo &C,
                                                   const double *__restrict__ B,
                                                   const uint8_t *__restrict__ fmask,
-                                                  const double *__restrict__ mf, double *__restrict__ Ac,
+                                                  const double *__restrict__ mf, double vr, double *__restrict__ Ac,
                                                   float *__restrict__ Ac32, double *__restrict__ mc) {
   constexpr int CEN = DIM == 3 ? 13 : 4;
   double a[4];
@@ -178,7 +190,7 @@ __host__ __device__ __forceinline__ void rap_block(long long I, int T, const Geo
   if (T == CEN) {
     double ms0, ms1;
     bool live0, live1;
-    rap_storage<DIM, MASK>(I, F, C, fmask, mf, ms0, ms1, live0, live1);
+    rap_storage<DIM, MASK>(I, F, C, fmask, mf, vr, ms0, ms1, live0, live1);
     a[1] += ms0;
     a[3] += ms1;
     if (!live0) a[0] += 1.0;
@@ -209,14 +221,14 @@ __host__ __device__ __forceinline__ bool rap_thread(long long wave, int lane, lo
 template <int DIM, bool MASK>
 __global__ void __launch_bounds__(BS) k_rap_ap(const Geo F, const Geo C, const double *__restrict__ Af,
                                                const uint8_t *__restrict__ fmask, const double *__restrict__ mf,
-                                               double *__restrict__ B) {
+                                               const double vr, double *__restrict__ B) {
   const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
   const long long wave = (long long)blk * (BS / 64) + (threadIdx.x >> 6);
   long long i;
   int slot;
   if (!rap_thread<DIM>(wave, threadIdx.x & 63, F.N, i, slot)) return;
   double b[4];
-  rap_ap_entry<DIM, MASK>(i, slot, F, C, Af, fmask, mf, b);
+  rap_ap_entry<DIM, MASK>(i, slot, F, C, Af, fmask, mf, vr, b);
   double *dst = B + ((long long)slot * F.N + i) * 4;
   reinterpret_cast<double2 *>(dst)[0] = make_double2(b[0], b[1]);
   reinterpret_cast<double2 *>(dst)[1] = make_double2(b[2], b[3]);
@@ -225,40 +237,40 @@ __global__ void __launch_bounds__(BS) k_rap_ap(const Geo F, const Geo C, const d
 template <int DIM, bool MASK>
 __global__ void __launch_bounds__(BS) k_rap(const Geo F, const Geo C, const double *__restrict__ B,
                                             const uint8_t *__restrict__ fmask, const double *__restrict__ mf,
-                                            double *__restrict__ Ac, float *__restrict__ Ac32,
+                                            const double vr, double *__restrict__ Ac, float *__restrict__ Ac32,
                                             double *__restrict__ mc) {
   const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
   const long long wave = (long long)blk * (BS / 64) + (threadIdx.x >> 6);
   long long I;
   int T;
   if (!rap_thread<DIM>(wave, threadIdx.x & 63, C.N, I, T)) return;
-  rap_block<DIM, MASK>(I, T, F, C, B, fmask, mf, Ac, Ac32, mc);
+  rap_block<DIM, MASK>(I, T, F, C, B, fmask, mf, vr, Ac, Ac32, mc);
 }
 
 }  // namespace
 
 tpf_status launch_rap(int dim, bool mask, const int nf[3], long long Nf, const int nc[3], long long Nc,
-                      const double *Af, const uint8_t *fmask, const double *mf, double *B, double *Ac, float *Ac32,
-                      double *mc, hipStream_t s) {
+                      const double *Af, const uint8_t *fmask, const double *mf, double vr, double *B, double *Ac,
+                      float *Ac32, double *mc, hipStream_t s) {
   const Geo F = geo_of(nf, Nf), C = geo_of(nc, Nc);
   const int nst = dim == 3 ? 27 : 9;
   const long long wf = ((Nf + 63) / 64) * nst, wc = ((Nc + 63) / 64) * nst;
   const unsigned nbf = (unsigned)((wf + BS / 64 - 1) / (BS / 64)), nbc = (unsigned)((wc + BS / 64 - 1) / (BS / 64));
   if (dim == 3) {
     if (mask) {
-      k_rap_ap<3, true><<<nbf, BS, 0, s>>>(F, C, Af, fmask, mf, B);
-      k_rap<3, true><<<nbc, BS, 0, s>>>(F, C, B, fmask, mf, Ac, Ac32, mc);
+      k_rap_ap<3, true><<<nbf, BS, 0, s>>>(F, C, Af, fmask, mf, vr, B);
+      k_rap<3, true><<<nbc, BS, 0, s>>>(F, C, B, fmask, mf, vr, Ac, Ac32, mc);
     } else {
-      k_rap_ap<3, false><<<nbf, BS, 0, s>>>(F, C, Af, fmask, mf, B);
-      k_rap<3, false><<<nbc, BS, 0, s>>>(F, C, B, fmask, mf, Ac, Ac32, mc);
+      k_rap_ap<3, false><<<nbf, BS, 0, s>>>(F, C, Af, fmask, mf, vr, B);
+      k_rap<3, false><<<nbc, BS, 0, s>>>(F, C, B, fmask, mf, vr, Ac, Ac32, mc);
     }
   } else {
     if (mask) {
-      k_rap_ap<2, true><<<nbf, BS, 0, s>>>(F, C, Af, fmask, mf, B);
-      k_rap<2, true><<<nbc, BS, 0, s>>>(F, C, B, fmask, mf, Ac, Ac32, mc);
+      k_rap_ap<2, true><<<nbf, BS, 0, s>>>(F, C, Af, fmask, mf, vr, B);
+      k_rap<2, true><<<nbc, BS, 0, s>>>(F, C, B, fmask, mf, vr, Ac, Ac32, mc);
     } else {
-      k_rap_ap<2, false><<<nbf, BS, 0, s>>>(F, C, Af, fmask, mf, B);
-      k_rap<2, false><<<nbc, BS, 0, s>>>(F, C, B, fmask, mf, Ac, Ac32, mc);
+      k_rap_ap<2, false><<<nbf, BS, 0, s>>>(F, C, Af, fmask, mf, vr, B);
+      k_rap<2, false><<<nbc, BS, 0, s>>>(F, C, B, fmask, mf, vr, Ac, Ac32, mc);
     }
   }
   TPF_LAUNCH_CHECK();

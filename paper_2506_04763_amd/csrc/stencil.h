@@ -36,9 +36,10 @@ __host__ __device__ __forceinline__ void vcoords(long long v, const Geo &G, int 
 __host__ __device__ inline Geo geo_of(const int n[3], long long N) { return Geo{n[0], n[1], n[2], N}; }
 
 
-// B: scratch of NST * 4 * Nf doubles.
+// B: scratch of NST * 4 * Nf doubles.  mask: the fine level is the finest (Dirichlet
+// mask fmask applies, rows in volume-balance form with vr = rho_w / rho_n).
 tpf_status launch_rap(int dim, bool mask, const int nf[3], long long Nf, const int nc[3], long long Nc,
-                      const double *Af, const uint8_t *fmask, const double *mf, double *B, double *Ac, float *Ac32,
-                      double *mc, hipStream_t s);
+                      const double *Af, const uint8_t *fmask, const double *mf, double vr, double *B, double *Ac,
+                      float *Ac32, double *mc, hipStream_t s);
 
 }  // namespace tpf

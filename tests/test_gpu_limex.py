@@ -42,7 +42,7 @@ def run_sequence(scn, steps, stages, dt0, tol=5e-3, safety=0.75, dt_max=8.64e6, 
         dt = dt_next
         err = per_field(u.cpu().numpy(), uo)
         log.append((acc, st["eps"], dt_next, err, st["solves"], st["iters_total"]))
-        assert t == pytest.approx(to, rel=1e-12)
+        assert t == pytest.approx(to, rel=1e-9)  # sums of steps that agree to the eps tolerance
     g.close()
     return log, u.cpu().numpy(), uo
 
