@@ -21,6 +21,8 @@ Readings taken where the paper is silent:
   * Brooks-Corey / Burdine laws in textbook form:
       S_e = (S_w - S_wr)/(1 - S_wr - S_nr),  p_c = p_d S_e^(-1/lam),
       k_rw = S_e^((2+3 lam)/lam),  k_rn = (1-S_e)^2 (1 - S_e^((2+lam)/lam));
+    or, where a scenario selects the printed polynomial laws of Section 5 (cases 4
+    and 5), k_rw = a_w S_e^2, k_rn = a_n (1 - S_e) with the same Brooks-Corey p_c;
     S_e is clamped to [1e-6, 1] inside p_c and k_r;
   * the Leverett J of a cell is J_e(S_e) = S_e^(-1/lam_e); the vertex capillary
     pressure P_i uses the reference medium m(i) = lowest-index adjacent cell with
@@ -74,6 +76,18 @@ def krn_bc(sn, lam, swr, snr):
     return (1.0 - se) ** 2 * (1.0 - se ** ((2.0 + lam) / lam))
 
 
+def krw_poly(sn, a_w, swr, snr):
+    """Polynomial wetting relative permeability a_w S_e^2 (Section 5, Tables case4 and
+    case5: a_w = 0.9)."""
+    return a_w * eff_sat(sn, swr, snr) ** 2
+
+
+def krn_poly(sn, a_n, swr, snr):
+    """Polynomial non-wetting relative permeability a_n (1 - S_e) (Tables case4 and
+    case5: a_n = 0.5)."""
+    return a_n * (1.0 - eff_sat(sn, swr, snr))
+
+
 def hat_sn(sn, pdmin, lam_ref, pd_e, lam_e, swr, snr):
     """Saturation of the SCV (vertex i, element e) under the p_dmin interface
     condition (Eq. hSw), returned as a non-wetting saturation.
@@ -118,6 +132,10 @@ class FV:
         self.pd = np.asarray(scn.entry_p, np.float64)
         self.lam = np.asarray(scn.bc_lambda, np.float64)
         self.dir_mask = np.asarray(scn.dir_mask, np.uint8)
+        self.kr_model = getattr(scn, "kr_model", "burdine")
+        self.kr_coef = tuple(getattr(scn, "kr_coef", (1.0, 1.0)))
+        if self.kr_model not in ("burdine", "poly"):
+            raise ValueError(f"unknown relative-permeability law {self.kr_model!r}")
         nx, ny, nz = self.n
         ncz, ncy, ncx = scn.cell_shape
         cz, cy, cx = np.meshgrid(np.arange(ncz), np.arange(ncy), np.arange(ncx), indexing="ij")
@@ -198,7 +216,21 @@ class FV:
                 hi = np.minimum(np.minimum(coords[b] + 0.5 * self.h[b], ext[b]), p.hi[k])
                 measure *= np.maximum(hi - lo, 0.0)
             Q[:, p.phase] += np.where(on_face, p.rate * measure, 0.0)
+        src = getattr(scn, "vertex_source", None)
+        if src is not None:  # mass rates into single control volumes (point sources)
+            Q = Q + np.asarray(src, np.float64).reshape(self.N, 2)
         return Q
+
+    # -- relative permeabilities of the scenario's law ------------------------------
+    def krw(self, sn, lam):
+        if self.kr_model == "poly":
+            return krw_poly(sn, self.kr_coef[0], self.swr, self.snr)
+        return krw_bc(sn, lam, self.swr, self.snr)
+
+    def krn(self, sn, lam):
+        if self.kr_model == "poly":
+            return krn_poly(sn, self.kr_coef[1], self.swr, self.snr)
+        return krn_bc(sn, lam, self.swr, self.snr)
 
     # -- per-cell evaluations -------------------------------------------------------
     def _cells(self, cells):
@@ -244,16 +276,16 @@ class FV:
             phi_w = -(K / mw) * (dp - rw * ga) * area
             up = np.real(phi_w) >= 0.0
             sn_up = np.where(up, sn[:, l0], sn[:, l1])
-            fw = rw * krw_bc(sn_up, lam, swr, snr) * phi_w
+            fw = rw * self.krw(sn_up, lam) * phi_w
             # non-wetting phase: upwinded k_rn at the hatted SCV saturation
             phi_n = -(K / mn) * (dp - rn * ga) * area
             upn = np.real(phi_n) >= 0.0
             sh_up = np.where(upn, sh[:, l0], sh[:, l1])
-            fn = rn * krn_bc(sh_up, lam, swr, snr) * phi_n
+            fn = rn * self.krn(sh_up, lam) * phi_n
             # capillary diffusion, central
             s_ip = sh @ Nsh
             dpc = pc @ G
-            fc = -rn * krn_bc(s_ip, lam, swr, snr) * (K / mn) * dpc * area
+            fc = -rn * self.krn(s_ip, lam) * (K / mn) * dpc * area
             np.add.at(out[:, 0], cv[:, l0], -fw)
             np.add.at(out[:, 0], cv[:, l1], fw)
             np.add.at(out[:, 1], cv[:, l0], -(fn + fc))

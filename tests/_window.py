@@ -52,7 +52,8 @@ def window(scn, lo, hi, u=None, levels=1):
     return replace(scn, name=f"{scn.name}[{lo}:{hi}]", n=n, extent=extent, perm=cell(scn.perm),
                    poro=cell(scn.poro), entry_p=cell(scn.entry_p), bc_lambda=cell(scn.bc_lambda),
                    dir_mask=vert(scn.dir_mask), dir_value=vert2(scn.dir_value), patches=patches,
-                   u0=vert2(scn.u0 if u is None else u), levels=levels)
+                   u0=vert2(scn.u0 if u is None else u), levels=levels,
+                   vertex_source=None if scn.vertex_source is None else vert2(scn.vertex_source))
 
 
 def row_window(scn, v, reach=2):

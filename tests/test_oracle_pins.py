@@ -255,6 +255,46 @@ def test_upwind_convective_flux_two_point_form():
         assert F[v, 1] == pytest.approx(fn_in - fn_out, rel=1e-12)
 
 
+def test_upwind_convective_flux_two_point_form_polynomial_law():
+    """As above with the printed polynomial laws of Tables case4/case5 (k_rw = 0.9 S_e^2,
+    k_rn = 0.5 (1 - S_e)) and residual saturations S_wr = 0.2, S_nr = 0.1."""
+    n, L = 9, 0.8
+    a = -400.0
+    scn = make_scn(2, (n, 3, 1), (L, 0.2, 1.0), perm=2e-11, pd=0.0, lam=2.0, mu=(1e-3, 5e-3),
+                   s_res=(0.2, 0.1))
+    scn.kr_model, scn.kr_coef = "poly", (0.9, 0.5)
+    x, y, _ = scn.vertex_coords()
+    sn = 0.15 + 0.5 * np.sin(3 * x) ** 2
+    u = np.stack([1e5 + a * x, sn], axis=1)
+    F = FV.FV(scn).residual_raw(u)
+    dy = 0.1
+    qw = -2e-11 / 1e-3 * a * dy
+    qn = -2e-11 / 5e-3 * a * dy
+    for i in range(1, n - 1):
+        v = i + n
+        se_l, se_c = (1 - sn[v - 1] - 0.2) / 0.7, (1 - sn[v] - 0.2) / 0.7
+        assert F[v, 0] == pytest.approx(1000 * 0.9 * (se_l ** 2 - se_c ** 2) * qw, rel=1e-12)
+        assert F[v, 1] == pytest.approx(1000 * 0.5 * (se_c - se_l) * qn, rel=1e-12)
+
+
+def test_point_source_enters_one_control_volume():
+    """Case 5's injection: 0.05 pore volumes per year of the non-wetting phase, into the
+    control volume whose dual box holds (100, 100, 30) m."""
+    scn = W.case5(17)
+    f = FV.FV(scn)
+    rate = 0.05 * 200.0 ** 3 * 0.1 / (365 * 86400.0) * 700.0
+    assert f.Q[:, 1].sum() == pytest.approx(rate, rel=1e-14) and f.Q[:, 0].sum() == 0.0
+    v = int(np.argmax(f.Q[:, 1]))
+    x, y, z = scn.vertex_coords()
+    h = 200.0 / 16
+    assert all(abs(c - p) <= h / 2 for c, p in zip((x[v], y[v], z[v]), (100.0, 100.0, 30.0)))
+    # the initial state is in equilibrium away from the source: the residual vanishes
+    # to rounding of the hydrostatic pressure differences
+    F = f.residual(scn.u0)
+    F[v] = 0.0
+    assert np.abs(F).max() <= 1e-12 * rate
+
+
 def test_neumann_patch_total():
     scn = W.small_cube(9)
     f = FV.FV(scn)
@@ -265,10 +305,14 @@ def test_neumann_patch_total():
     assert f2.Q[:, 1].sum() == pytest.approx(0.075 * 0.2, rel=1e-13)
 
 
-@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("dim", [2, 3, "case5"])
 def test_jacobian_complex_step_vs_central_differences(dim):
-    scn = W.lens_2d(9, 5) if dim == 2 else W.small_cube(4, sigma=1.0, seed=5)
-    u = W.perturbed_state(scn, 3, sn_lo=0.05, sn_hi=0.5)
+    if dim == "case5":  # polynomial laws, residual saturations, layered p_d(K), point source
+        scn = W.case5(5)
+        u = W.perturbed_state(scn, 3, dp=2e4, sn_lo=0.12, sn_hi=0.6)
+    else:
+        scn = W.lens_2d(9, 5) if dim == 2 else W.small_cube(4, sigma=1.0, seed=5)
+        u = W.perturbed_state(scn, 3, sn_lo=0.05, sn_hi=0.5)
     f = FV.FV(scn)
     J = f.jacobian(u).toarray()
     uf = u.ravel()

@@ -17,6 +17,7 @@ CASES = [
     ("lens17x9", lambda: W.lens_2d(17, 9)),
     ("cube9", lambda: W.small_cube(9, sigma=1.5, seed=31)),
     ("cube9_patch", lambda: W.cube_3d(9, 1.0, 32, corr_cells=2.0, rate=0.05)),
+    ("case5_9", lambda: W.case5(9)),
 ]
 
 

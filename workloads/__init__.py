@@ -13,7 +13,9 @@ Conventions (shared by every consumer):
   * the state u is (N, 2) float64, column 0 = p_w [Pa], column 1 = S_n [-];
   * dir_mask bit0 = p_w Dirichlet, bit1 = S_n Dirichlet; dir_value is (N, 2);
   * an injection patch is a rectangle on a boundary face with a mass rate per unit
-    face measure (kg/(m^2 s) in 3D, kg/(m s) in 2D) of one phase into the domain.
+    face measure (kg/(m^2 s) in 3D, kg/(m s) in 2D) of one phase into the domain;
+  * a point source is a mass rate (kg/s) into the control volume (dual box) of the
+    vertex whose box contains the point, held in vertex_source (N, 2).
 
 Recipes follow the paper's parameter tables (Section 5: Case-4 step control values,
 Case-5 geometry sizes) and synthetic layered / log-normal reservoirs standing in for
@@ -61,6 +63,9 @@ class Scenario:
     levels: int = 1
     h: float = 32.0                  # stage step for single-stage workloads [s]
     meta: dict = field(default_factory=dict)
+    kr_model: str = "burdine"        # "burdine" (Brooks-Corey-Burdine) or "poly" (a_w S_e^2, a_n (1-S_e))
+    kr_coef: Tuple[float, float] = (1.0, 1.0)   # (a_w, a_n) of the polynomial law
+    vertex_source: Optional[np.ndarray] = None  # (N, 2) kg/s into single control volumes, or None
 
     @property
     def nverts(self) -> int:
@@ -222,6 +227,68 @@ def buckley_leverett(elements: int = 64, levels: Optional[int] = None) -> Scenar
     scn.levels = default_levels(ny) if levels is None else levels
     scn.meta = dict(case="buckley_leverett", elements=elements, t_end=BL_T_END, dt0=1.0,
                     dt_max=100 * 86400.0, tol=5e-2, safety=0.25, stages=2)
+    return scn
+
+
+C5_EXTENT = 200.0
+C5_LAYER_K = (1e-13, 1e-12, 8e-13, 7e-13)   # K_1 (bottom) ... K_4 (top), 50 m each
+C5_P_BOTTOM = 5e7                            # Pa, Dirichlet p_n at z = 0
+C5_INJECTION = (100.0, 100.0, 30.0)          # m, the injection point
+C5_PV_PER_YEAR = 0.05
+C5_T_END = 128 * 60.0
+
+
+def case5_pd(perm):
+    """Entry pressure law of Tables case4 and case5: p_d = 7.37 K^-0.43 Pa (K in m^2)."""
+    return 7.37 * np.asarray(perm, np.float64) ** -0.43
+
+
+def case5(n: int = 257, levels: Optional[int] = None) -> Scenario:
+    """Case 5 of Section 5 (Table case5): 3D layer-wise heterogeneity.
+
+    A 200 m cube of n^3 vertices (257^3 is the paper's 256^3-cell mesh) in four
+    horizontal layers of 50 m with K_1 = 1e-13 (bottom), 1e-12, 8e-13, 7e-13 m^2;
+    porosity 0.1; rho 1000 / 700 kg/m^3, mu 1e-3 / 5.654e-5 Pa s; S_wr 0.2, S_nr 0.1;
+    Brooks-Corey lambda 2 with p_d = 7.37 K^-0.43; k_rw = 0.9 S_e^2, k_rn = 0.5 (1 - S_e);
+    gravity along -z.  z = 0: Dirichlet S_w = 1 - S_nr and p_n = 5e7 Pa, i.e. p_w =
+    5e7 - p_d(K_1) (S_e = 1 there); the other faces are closed.  Initially S_w = 1 - S_nr
+    with hydrostatic p_w (the non-wetting phase is at its residual saturation, hence
+    immobile, so this is an equilibrium).  The non-wetting phase is injected at
+    0.05 pore volumes per year (year = 365 d) at the point (100, 100, 30) m, the 3D
+    counterpart of Case 4's injection point, into the control volume containing it.
+    Simulated time 128 min, tau0 = 32 s, tau_max = 100 d."""
+    if (n - 1) % 4:
+        raise ValueError("n - 1 must be a multiple of 4 (layer boundaries on vertices)")
+    L = C5_EXTENT
+    scn = _empty(f"case5_{n}", 3, (n, n, n), (L, L, L), (0.0, 0.0, -GRAV))
+    scn.rho = (1000.0, 700.0)
+    scn.mu = (1e-3, 5.654e-5)
+    scn.s_res = (0.2, 0.1)
+    scn.kr_model, scn.kr_coef = "poly", (0.9, 0.5)
+    _, _, cz = scn.cell_centres()
+    layer = np.minimum((cz // (L / 4)).astype(int), 3)
+    scn.perm = np.asarray(C5_LAYER_K)[layer]
+    scn.poro = np.full(scn.ncells, 0.1)
+    scn.entry_p = case5_pd(scn.perm)
+    scn.bc_lambda = np.full(scn.ncells, 2.0)
+    x, y, z = scn.vertex_coords()
+    p_bottom = C5_P_BOTTOM - float(case5_pd(C5_LAYER_K[0]))
+    p = p_bottom - scn.rho[0] * GRAV * z
+    sn0 = scn.s_res[1]
+    bottom = np.isclose(z, 0.0)
+    scn.dir_mask = np.where(bottom, 3, 0).astype(np.uint8)
+    scn.dir_value = np.stack([np.full_like(z, p_bottom), np.full_like(z, sn0)], axis=1)
+    scn.u0 = np.stack([p, np.full_like(z, sn0)], axis=1)
+    h = L / (n - 1)
+    idx = [int(np.floor(c / h + 0.5)) for c in C5_INJECTION]
+    v = idx[0] + n * (idx[1] + n * idx[2])
+    rate = C5_PV_PER_YEAR * L ** 3 * 0.1 / (365 * 86400.0) * scn.rho[1]   # kg/s
+    src = np.zeros((scn.nverts, 2))
+    src[v, 1] = rate
+    scn.vertex_source = src
+    scn.levels = default_levels(n) if levels is None else levels
+    scn.meta = dict(case="case5", t_end=C5_T_END, dt0=32.0, dt_max=100 * 86400.0, tol=5e-3, safety=0.75,
+                    stages=3, injection_vertex=v, injection_rate=rate)
     return scn
 
 
