@@ -13,6 +13,14 @@ Prints one JSON line.  Options:
   --no-cpu      skip the oracle CPU baseline  --no-fp64   skip the FP64 and FP16-coarse comparisons
   --no-serve    skip the continuous-batching serving workload (p50/p99 latency)
   --limex-run K run the 257^3 LIMEX workload to K accepted steps (summary line only)
+  --case5       Section 5's case 5 at the paper's mesh (257^3 vertices, 33,949,186 DoF)
+                to 128 minutes of simulated time: total time, LIMEX steps and time per
+                step, linear solves and time per solve beside the paper's Table
+                case5_strong (summary line only)
+  --case1       the Buckley-Leverett validation (Section 5, Case 1) on 64 ... 512
+                elements: error norms against the Welge solution, convergence rates,
+                LIMEX step counts and run times beside the paper's Table error1
+                (summary line only)
 """
 from __future__ import annotations
 
@@ -241,6 +249,103 @@ def limex_run(accepted_target=20, max_attempts=80):
             "dt_sequence": [round(s["dt"], 3) for s in steps]}
 
 
+# Table case5_strong: PE -> (T_total s, LIMEX steps accepted + rejected, t_LIMEX s, N_linear, t_linear s)
+PAPER_CASE5 = {256: (1182.3, "67+2", 17.13, 458, 0.335), 512: (640.0, "67+2", 9.28, 489, 0.194),
+               1024: (372.2, "67+2", 5.39, 478, 0.146)}
+
+
+def case5_run(max_attempts=400, precision="mixed", rtol=1e-8):
+    """Section 5, case 5 on one GPU: adaptive LIMEX (k = 3, TOL 5e-3, safety 0.75,
+    tau0 32 s, tau_max 100 d) from t = 0 to 128 min on the 257^3-vertex layered cube,
+    FP32 multigrid inside FP64 BiCGSTAB to rtol, every step timed on the host around
+    the device work (inputs resident; the state never leaves the GPU).  One progress
+    line per attempted step on stderr."""
+    import torch
+
+    import paper_2506_04763_amd as tpf
+    import workloads as W
+    scn = W.case5(257)
+    m = scn.meta
+    t_setup = time.perf_counter()
+    g = tpf.Grid(scn, precision=precision, limex_stages=m["stages"])
+    u = g.initial_state()
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t_setup
+    t, dt = 0.0, m["dt0"]
+    steps = []
+    t0 = time.perf_counter()
+    while t < m["t_end"] * (1 - 1e-14) and len(steps) < max_attempts:
+        dt = min(dt, m["t_end"] - t)
+        ts = time.perf_counter()
+        acc, t, dt_next, st = g.limex_step(u, t, dt, stages=m["stages"], tol=m["tol"], safety=m["safety"],
+                                           dt_max=m["dt_max"], rtol=rtol)
+        torch.cuda.synchronize()
+        rec = dict(accepted=bool(acc), t=t, dt=dt, eps=st["eps"], solves=st["solves"], iters=st["iters_total"],
+                   unconverged=st["unconverged"], seconds=time.perf_counter() - ts)
+        steps.append(rec)
+        print(json.dumps({"case5_step": len(steps), **rec}), file=sys.stderr, flush=True)
+        dt = dt_next
+    wall = time.perf_counter() - t0
+    sn_max = float(u.reshape(-1, 2)[:, 1].max())
+    g.close()
+    acc = sum(1 for s in steps if s["accepted"])
+    solves = sum(s["solves"] for s in steps)
+    iters = sum(s["iters"] for s in steps)
+    return {"workload": "case5_257^3_layered_poly_kr_point_injection_128min", "dof": 2 * scn.nverts,
+            "levels": scn.levels, "precision": precision, "rtol": rtol, "stages": m["stages"],
+            "t_end_s": t, "reached_t_end": bool(t >= m["t_end"] * (1 - 1e-14)),
+            "T_total_s": round(wall, 2), "setup_s": round(setup_s, 2),
+            "N_limex": f"{acc}+{len(steps) - acc}", "t_limex_s": round(wall / max(len(steps), 1), 3),
+            "N_linear_solves": solves, "t_linear_solve_s": round(wall / max(solves, 1), 4),
+            "bicgstab_iterations": iters, "unconverged_solves": sum(s["unconverged"] for s in steps),
+            "sn_max": sn_max,
+            "paper_table_case5_strong": {str(k): {"T_total_s": v[0], "N_limex": v[1], "t_limex_s": v[2],
+                                                  "N_linear": v[3], "t_linear_s": v[4]}
+                                         for k, v in PAPER_CASE5.items()},
+            "dt_sequence": [round(s["dt"], 3) for s in steps]}
+
+
+def case1_run(elements=(64, 128, 256, 512)):
+    """Case 1 of Section 5: adaptive LIMEX (k = 2, TOL 5e-2, safety 0.25, tau0 1 s,
+    tau_max 100 d) to 1500 days on the 300 m x 75 m strip, FP64 multigrid inside FP64
+    BiCGSTAB to 1e-10, at each resolution; the L1 / L2 norms of S_w - S_wh against
+    the analytic Welge solution and their rates, beside the paper's Table error1."""
+    import torch
+
+    import paper_2506_04763_amd as tpf
+    import workloads as W
+    from tests import buckley_leverett as BL
+    rows, l1s, l2s = [], [], []
+    for el in elements:
+        scn = W.buckley_leverett(el)
+        g = tpf.Grid(scn, precision="fp64", limex_stages=scn.meta["stages"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u, st = BL.run_gpu(g, scn)
+        wall = time.perf_counter() - t0
+        g.close()
+        sw = 1.0 - u[:, 1].reshape(scn.n[1], scn.n[0])
+        l1, l2 = BL.error_norms(sw, el)
+        l1s.append(l1)
+        l2s.append(l2)
+        p = BL.PAPER_LIMEX[el]
+        rows.append({"elements": el, "vertices": [scn.n[0], scn.n[1]], "dof": 2 * scn.nverts,
+                     "levels": scn.levels, "steps": f"{st['accepted']}+{st['rejected']}",
+                     "solves": st["solves"], "bicgstab_iterations": st["iterations"],
+                     "unconverged": st["unconverged"], "wall_s": round(wall, 3),
+                     "ms_per_step": round(1e3 * wall / max(st["accepted"] + st["rejected"], 1), 3),
+                     "L1": round(l1, 4), "L2": round(l2, 4),
+                     "paper_limex": {"steps": p[0], "L1": p[1], "L2": p[2]}})
+        print(json.dumps({"case1": rows[-1]}), file=sys.stderr, flush=True)
+    r1, r2 = BL.rates(l1s), BL.rates(l2s)
+    pr1 = BL.rates([BL.PAPER_LIMEX[e][1] for e in elements])
+    pr2 = BL.rates([BL.PAPER_LIMEX[e][2] for e in elements])
+    return {"workload": "case1_buckley_leverett_300x75m_1500d", "precision": "fp64", "rtol": 1e-10,
+            "rows": rows, "rate_L1": [round(r, 3) for r in r1], "rate_L2": [round(r, 3) for r in r2],
+            "paper_rate_L1": [round(r, 3) for r in pr1], "paper_rate_L2": [round(r, 3) for r in pr2],
+            "front_speed_m_per_s": BL.front_speed()}
+
+
 def counters_driver(cycles=4, copy_bytes=1 << 30):
     """Short workload for hardware-counter runs: one 129^3 mixed-precision stage
     assembly, `cycles` V-cycles (4 fine-level smoother sweeps each), and a plain
@@ -297,9 +402,19 @@ def main():
                     help="run the short hardware-counter workload instead of the benchmark")
     ap.add_argument("--limex-run", type=int, default=0, metavar="K",
                     help="run the 257^3 LIMEX workload until K steps are accepted instead of the benchmark")
+    ap.add_argument("--case1", action="store_true",
+                    help="run the Buckley-Leverett validation instead of the benchmark")
+    ap.add_argument("--case5", action="store_true",
+                    help="run Section 5's case 5 at 257^3 to 128 minutes instead of the benchmark")
     args = ap.parse_args()
     if args.counters:
         counters_driver()
+        return
+    if args.case1:
+        print(json.dumps(case1_run()), flush=True)
+        return
+    if args.case5:
+        print(json.dumps(case5_run()), flush=True)
         return
     if args.limex_run:
         print(json.dumps(limex_run(args.limex_run)), flush=True)

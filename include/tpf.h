@@ -89,6 +89,13 @@ typedef struct tpf_patch {
 
 #define TPF_MAX_PATCHES 8
 
+/* Relative-permeability laws (the capillary pressure is Brooks-Corey in both):
+ *   TPF_KR_BURDINE  k_rw = S_e^((2+3 lam)/lam), k_rn = (1-S_e)^2 (1 - S_e^((2+lam)/lam))
+ *                   (Brooks-Corey-Burdine, the law of Section 5's cases 1-3);
+ *   TPF_KR_POLY     k_rw = kr_coef[0] S_e^2, k_rn = kr_coef[1] (1 - S_e)
+ *                   (the printed laws of Tables case4 and case5: 0.9 and 0.5). */
+enum { TPF_KR_BURDINE = 0, TPF_KR_POLY = 1 };
+
 /* Scenario: the problem statement of Section 2 (domain, per-element porosity,
  * isotropic permeability and Brooks-Corey parameters, fluids, gravity, Dirichlet
  * and Neumann data) plus the multigrid settings.  Host pointers are read during
@@ -115,6 +122,12 @@ typedef struct tpf_grid_desc {
   int32_t nu_post;       /* post-smoothing sweeps (>= 0)                        */
   int32_t limex_stages;  /* largest LIMEX stage count used with this grid (0: none) */
   double omega;          /* block-Jacobi damping in (0, 2)                      */
+  int32_t kr_model;      /* TPF_KR_BURDINE or TPF_KR_POLY                       */
+  int32_t reserved;      /* 0                                                   */
+  double kr_coef[2];     /* TPF_KR_POLY: a_w, a_n > 0 (ignored otherwise)       */
+  const double *vertex_source; /* host, 2 per vertex (w, n), kg/s into the vertex's
+                                  control volume (point sources such as case 5's
+                                  injection point), or NULL for none           */
 } tpf_grid_desc;
 
 typedef struct tpf_solve_stats {

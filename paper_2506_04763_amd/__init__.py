@@ -65,6 +65,13 @@ class _Desc:
         d.nu_pre, d.nu_post = int(nu_pre), int(nu_post)
         d.omega = float(omega)
         d.limex_stages = int(limex_stages)
+        model = getattr(scn, "kr_model", "burdine")
+        d.kr_model = {"burdine": L.TPF_KR_BURDINE, "poly": L.TPF_KR_POLY}[model]
+        coef = getattr(scn, "kr_coef", (1.0, 1.0))
+        d.kr_coef[0], d.kr_coef[1] = float(coef[0]), float(coef[1])
+        src = getattr(scn, "vertex_source", None)
+        if src is not None:
+            d.vertex_source = arr(src, np.float64, C.c_double)
         self.desc = d
 
 

@@ -19,6 +19,8 @@ TPF_FP64 = 0
 TPF_MIXED = 1
 TPF_MIXED16 = 2
 TPF_MAX_PATCHES = 8
+TPF_KR_BURDINE = 0
+TPF_KR_POLY = 1
 
 STATUS_NAMES = {0: "TPF_OK", 1: "TPF_NOT_CONVERGED", 2: "TPF_STEP_REJECTED", -1: "TPF_EINVAL",
                 -2: "TPF_ENOMEM", -3: "TPF_EDEVICE", -4: "TPF_EBREAKDOWN", -5: "TPF_ESTATE"}
@@ -37,7 +39,8 @@ class GridDesc(C.Structure):
                 ("dir_mask", C.POINTER(C.c_uint8)), ("dir_value", C.POINTER(C.c_double)),
                 ("patches", C.POINTER(Patch)), ("n_patches", C.c_int32), ("levels", C.c_int32),
                 ("precision", C.c_int32), ("nu_pre", C.c_int32), ("nu_post", C.c_int32),
-                ("limex_stages", C.c_int32), ("omega", C.c_double)]
+                ("limex_stages", C.c_int32), ("omega", C.c_double), ("kr_model", C.c_int32),
+                ("reserved", C.c_int32), ("kr_coef", C.c_double * 2), ("vertex_source", C.POINTER(C.c_double))]
 
 
 class SolveStats(C.Structure):

@@ -107,6 +107,13 @@ tpf_status validate(const tpf_grid_desc *d) {
   if (d->nu_pre < 1 || d->nu_post < 0 || d->nu_pre > 16 || d->nu_post > 16) BAD("need 1 <= nu_pre <= 16, 0 <= nu_post <= 16");
   if (!(d->omega > 0.0 && d->omega < 2.0)) BAD("omega must be in (0, 2)");
   if (d->limex_stages < 0 || d->limex_stages > MAXK) BAD("limex_stages must be in [0, %d]", MAXK);
+  if (d->kr_model != TPF_KR_BURDINE && d->kr_model != TPF_KR_POLY) BAD("kr_model must be TPF_KR_BURDINE or TPF_KR_POLY");
+  if (d->kr_model == TPF_KR_POLY)
+    for (int k = 0; k < 2; ++k)
+      if (!(d->kr_coef[k] > 0.0) || !finite(d->kr_coef[k])) BAD("kr_coef[%d] must be positive and finite", k);
+  if (d->vertex_source)
+    for (long long v = 0; v < 2 * N; ++v)
+      if (!finite(d->vertex_source[v])) BAD("vertex_source[%lld] is not finite", v);
   return TPF_OK;
 }
 
@@ -219,6 +226,10 @@ tpf_status tpf_create_grid(const tpf_grid_desc *d, void *arena, size_t arena_byt
   P.rho_w = d->rho[0]; P.rho_n = d->rho[1]; P.mu_w = d->mu[0]; P.mu_n = d->mu[1];
   P.swr = d->s_res[0]; P.snr = d->s_res[1];
   P.D = (1.0 - P.swr) - P.snr;
+  P.kr_model = d->kr_model;
+  P.pad_ = 0;
+  P.kr_aw = d->kr_model == TPF_KR_POLY ? d->kr_coef[0] : 0.0;
+  P.kr_an = d->kr_model == TPF_KR_POLY ? d->kr_coef[1] : 0.0;
   P.vol = P.h[0] * P.h[1] * (d->dim == 3 ? P.h[2] : 1.0);
   P.scv = P.vol / (1 << d->dim);
   for (int a = 0; a < 3; ++a) P.area[a] = (a < d->dim) ? P.vol / ((1 << (d->dim - 1)) * P.h[a]) : 0.0;
@@ -315,6 +326,13 @@ tpf_status tpf_create_grid(const tpf_grid_desc *d, void *arena, size_t arena_byt
     UP(g->dval, d->dir_value, 2 * L.N * sizeof(double));
   } else {
     st = fill_zero(g->dval, 2 * L.N, s);
+    if (st != TPF_OK) return fail(st);
+  }
+  // vertex sources first; the setup kernel adds the integrated patches to them
+  if (d->vertex_source) {
+    UP(g->Q, d->vertex_source, 2 * L.N * sizeof(double));
+  } else {
+    st = fill_zero(g->Q, 2 * L.N, s);
     if (st != TPF_OK) return fail(st);
   }
 #undef UP

@@ -17,7 +17,8 @@
 // velocity -K/mu_n (grad p_w - rho_n g) and the capillary flux -k_rn K/mu_n grad p_c
 // is central, k_rn taken at the Q1-interpolated hat saturation of the integration
 // point; Brooks-Corey p_c = p_d S_e^(-1/lam) and Burdine k_rw = S_e^((2+3 lam)/lam),
-// k_rn = (1-S_e)^2 (1 - S_e^((2+lam)/lam)), S_e clamped to [1e-6, 1]; storage of each
+// k_rn = (1-S_e)^2 (1 - S_e^((2+lam)/lam)) (or the polynomial laws a_w S_e^2,
+// a_n (1 - S_e) of Section 5's cases 4 and 5), S_e clamped to [1e-6, 1]; storage of each
 // sub-control volume uses its hat saturation; SCVF oriented from lower to higher
 // vertex index with ties upwinded to the lower one; integration point at the face
 // barycentre.
@@ -104,30 +105,42 @@ __host__ __device__ __forceinline__ double root_lam(double se, double inv_lam) {
   return exp_fin(log_pos(se) * inv_lam);
 }
 
-// Burdine wetting relative permeability and its derivative w.r.t. S_n.
+// Wetting relative permeability and its derivative w.r.t. S_n: Burdine, or the
+// polynomial law a_w S_e^2 of Tables case4/case5 (the law is uniform over a launch).
 __host__ __device__ __forceinline__ void krw(double sn, double inv_lam, const Phys &P, double &k, double &dk) {
   double se, dse;
   eff_sat(sn, P, se, dse);
+  if (P.kr_model == TPF_KR_POLY) {
+    k = P.kr_aw * se * se;
+    dk = 2.0 * P.kr_aw * se * dse;
+    return;
+  }
   const double t = root_lam(se, inv_lam);
   k = se * se * se * t * t;
   dk = (3.0 + 2.0 * inv_lam) * (k / se) * dse;
 }
 
-// Burdine non-wetting relative permeability from S_e and t = S_e^(1/lam), and its
-// derivative w.r.t. S_e.
-__host__ __device__ __forceinline__ void krn_se(double se, double t, double inv_lam, double &k, double &dk_dse) {
+// Non-wetting relative permeability from S_e (and, for Burdine, t = S_e^(1/lam)),
+// and its derivative w.r.t. S_e: Burdine, or the polynomial law a_n (1 - S_e).
+__host__ __device__ __forceinline__ void krn_se(double se, double t, double inv_lam, const Phys &P, double &k,
+                                               double &dk_dse) {
+  if (P.kr_model == TPF_KR_POLY) {
+    k = P.kr_an * (1.0 - se);
+    dk_dse = -P.kr_an;
+    return;
+  }
   const double sa = se * t * t;
   const double om = 1.0 - se;
   k = om * om * (1.0 - sa);
   dk_dse = -2.0 * om * (1.0 - sa) - om * om * (1.0 + 2.0 * inv_lam) * t * t;
 }
 
-// Burdine non-wetting relative permeability and its derivative w.r.t. S_n.
+// Non-wetting relative permeability and its derivative w.r.t. S_n.
 __host__ __device__ __forceinline__ void krn(double sn, double inv_lam, const Phys &P, double &k, double &dk) {
   double se, dse;
   eff_sat(sn, P, se, dse);
   double dk_dse;
-  krn_se(se, root_lam(se, inv_lam), inv_lam, k, dk_dse);
+  krn_se(se, P.kr_model == TPF_KR_POLY ? 1.0 : root_lam(se, inv_lam), inv_lam, P, k, dk_dse);
   dk = dk_dse * dse;
 }
 
@@ -178,8 +191,8 @@ __global__ void __launch_bounds__(BS) k_setup(const Phys P, const double *__rest
     }
     q[pa.phase] += pa.rate * meas;
   }
-  Q[2 * v] = q[0];
-  Q[2 * v + 1] = q[1];
+  Q[2 * v] += q[0];  // on top of the vertex sources uploaded at creation
+  Q[2 * v + 1] += q[1];
 }
 
 // Vertex capillary pressure in the reference medium, P_i = p_dmin,i J(S_i), and its
@@ -272,7 +285,7 @@ __host__ __device__ __forceinline__ void accumulate_cells(const long long v, con
         dpc[l] = pc[l] * (-il) / se * dse * dsh[l];
         // non-wetting mobility of the corner at its hat saturation (for upwinding)
         double dk_dse;
-        krn_se(se, t, il, khn[l], dk_dse);
+        krn_se(se, t, il, P, khn[l], dk_dse);
         dkhn[l] = dk_dse * dse;
       }
       // storage of the sub-control volume (vertex, cell): only dM/dS_n is non-zero

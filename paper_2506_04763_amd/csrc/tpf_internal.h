@@ -35,6 +35,8 @@ struct Phys {
   double swr, snr, D; // D = (1 - S_wr) - S_nr
   double vol, scv;    // cell volume, sub-control-volume volume
   double area[3];     // SCVF area of an edge along each axis
+  int kr_model, pad_; // TPF_KR_BURDINE or TPF_KR_POLY
+  double kr_aw, kr_an;  // coefficients of TPF_KR_POLY
 };
 
 struct PatchDev {

@@ -32,7 +32,9 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts_match_header():
     # offsets follow natural C alignment of the header's field order
     assert C.sizeof(L.Patch) == 56
-    assert L.GridDesc.omega.offset == 192 and C.sizeof(L.GridDesc) == 200
+    assert L.GridDesc.omega.offset == 192 and L.GridDesc.kr_model.offset == 200
+    assert L.GridDesc.kr_coef.offset == 208 and L.GridDesc.vertex_source.offset == 224
+    assert C.sizeof(L.GridDesc) == 232
     assert C.sizeof(L.SolveStats) == 32
     assert C.sizeof(L.LimexOpts) == 40
     assert C.sizeof(L.LimexStats) == 40
@@ -102,6 +104,9 @@ def _desc_ok():
     (lambda s: setattr(s, "s_res", (0.6, 0.5)), "S_wr"),
     (lambda s: s.dir_value.__setitem__((0, 0), np.inf), "dir_value"),
     (lambda s: setattr(s, "n", (9, 9, 8)), ""),
+    (lambda s: setattr(s, "kr_model", "poly") or setattr(s, "kr_coef", (0.9, 0.0)), "kr_coef[1]"),
+    (lambda s: setattr(s, "kr_model", "poly") or setattr(s, "kr_coef", (np.nan, 0.5)), "kr_coef[0]"),
+    (lambda s: setattr(s, "vertex_source", np.full((s.nverts, 2), np.inf)), "vertex_source"),
 ])
 def test_invalid_descriptors_rejected(mutate, msg):
     scn = _desc_ok()

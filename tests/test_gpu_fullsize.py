@@ -232,3 +232,39 @@ def test_cube257_limex_first_step():
         assert t == 0.0 and bool(torch.equal(u, u0))
     g.close()
     torch.cuda.empty_cache()
+
+
+def test_case5_257_first_step():
+    """Section 5 case 5 at the paper's mesh (256^3 cells, 257^3 vertices): sampled
+    stage-matrix rows, the injection vertex among them, at the initial state and at a
+    perturbed state, and one LIMEX step with k = 3 from tau0 = 32 s."""
+    scn = W.case5(257)
+    print(f"[fullsize] case5 n={scn.n} levels={scn.levels}", flush=True)
+    g = tpf.Grid(scn, precision="mixed", limex_stages=3)
+    u0 = g.initial_state()
+    f = g.empty()
+    g.assemble_stage(u0, H, f0_out=f)
+    v = scn.meta["injection_vertex"]
+    inj = (v % 257, (v // 257) % 257, v // 257 ** 2)
+    samples = sample_vertices(scn, 10, seed=8) + [inj]
+    check_fine_rows(scn, g, scn.u0.reshape(-1, 2), f, samples, True, "case5 257")
+    up = W.perturbed_state(scn, 4, dp=2e3, sn_lo=0.1, sn_hi=0.5)
+    fp = g.empty()
+    g.assemble_stage(torch.as_tensor(up.ravel(), device="cuda"), H, f0_out=fp)
+    check_fine_rows(scn, g, up.reshape(-1, 2), fp, sample_vertices(scn, 6, seed=9) + [inj], True,
+                    "case5 257 perturbed")
+    u = u0.clone()
+    m = scn.meta
+    acc, t, dt_next, st = g.limex_step(u, 0.0, m["dt0"], stages=3, tol=m["tol"], safety=m["safety"],
+                                       dt_max=m["dt_max"], rtol=1e-8)
+    print(f"[fullsize] case5 LIMEX step: accepted={acc} eps={st['eps']:.3e} dt_next={dt_next:.4g} "
+          f"solves={st['solves']} iterations={st['iters_total']}", flush=True)
+    assert st["solves"] == 6 and st["unconverged"] == 0
+    want = m["dt_max"] if st["eps"] == 0.0 else min(m["dt_max"], m["dt0"] * (m["safety"] * m["tol"] / st["eps"]) ** (1 / 3))
+    assert dt_next == pytest.approx(want, rel=1e-12)
+    assert acc == (st["eps"] <= m["tol"])
+    # the injected non-wetting mass appears at the injection vertex
+    if acc:
+        assert float(u.reshape(-1, 2)[v, 1]) > scn.s_res[1]
+    g.close()
+    torch.cuda.empty_cache()
