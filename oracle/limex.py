@@ -40,23 +40,35 @@ def step_size(H, eps, tol, safety, dt_max, q=2):
     return min(dt_max, H * (safety * tol / max(eps, 1e-300)) ** (1.0 / (q + 1)))
 
 
+class StageSolveFailed(Exception):
+    """A stage solve missed its tolerance within its iteration cap or broke down."""
+
+
 def limex_step(u0, H, k, rhs, stage_solve, err_ratio, tol, safety, dt_max):
     """Generic LIMEX step.
 
     rhs(v)            -> F(v)
-    stage_solve(h)    -> callable solving (M(u0)/h - J(u0)) x = f
+    stage_solve(h)    -> callable solving (M(u0)/h - J(u0)) x = f; raises
+                         StageSolveFailed when the linear solve fails
     err_ratio(kk, km) -> eps
     Returns (u_new_or_u0, accepted, eps, dt_next, T_kk).
+
+    A failed stage solve rejects the step (the paper gives no rule for it; a
+    linearly implicit step that cannot be solved is treated as too long): eps = inf,
+    the next step is a quarter of this one, and the remaining stages are skipped.
     """
     F0 = rhs(u0)
     T1 = []
-    for j in range(1, k + 1):
-        solve = stage_solve(H / j)
-        v = u0.copy()
-        for m in range(j):
-            f = F0 if m == 0 else rhs(v)
-            v = v + solve(f)
-        T1.append(v)
+    try:
+        for j in range(1, k + 1):
+            solve = stage_solve(H / j)
+            v = u0.copy()
+            for m in range(j):
+                f = F0 if m == 0 else rhs(v)
+                v = v + solve(f)
+            T1.append(v)
+    except StageSolveFailed:
+        return u0, False, float("inf"), min(dt_max, 0.25 * H), None
     kk, km = extrapolate(T1)
     eps = err_ratio(kk, km)
     acc = eps <= tol

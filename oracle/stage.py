@@ -46,6 +46,8 @@ class Stage:
                 x, st = self.solve(f, rtol, maxit)
                 info["iters"].append(st["iters"])
                 info["solves"] += 1
+                if not np.all(np.isfinite(x)) or not st["rel_res"] <= rtol:
+                    raise _lx.StageSolveFailed()
                 return x
             return solve
 

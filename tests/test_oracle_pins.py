@@ -468,6 +468,19 @@ def test_limex_observed_order(k, order):
     assert min(rates) > order + 0.75
 
 
+def test_failed_stage_solve_rejects_the_step():
+    """A stage solve that cannot reach rtol within maxit (forced: one iteration to
+    1e-12) rejects the step: state returned unchanged, eps = inf, a quarter step next."""
+    scn = W.lens_2d(17, 9)
+    scn.levels = 2
+    st = ST.Stage(scn)
+    u = scn.u0.ravel().copy()
+    out, info = st.limex_step(u, 32.0, stages=2, rtol=1e-12, maxit=1)
+    assert not info["accepted"] and info["eps"] == float("inf")
+    assert info["dt_next"] == 8.0 and info["solves"] == 1
+    np.testing.assert_array_equal(out, u)
+
+
 def test_step_size_rule_by_hand():
     assert LX.step_size(10.0, 0.001, 5e-3, 0.75, 1e9) == pytest.approx(10.0 * (3.75) ** (1 / 3), rel=1e-15)
     assert LX.step_size(10.0, 0.0, 5e-3, 0.75, 100.0) == 100.0
