@@ -12,11 +12,15 @@ Prints one JSON line.  Options:
   --steps K     timed steps (default 10)      --warmup W  untimed steps (default 2)
   --no-cpu      skip the oracle CPU baseline  --no-fp64   skip the FP64 and FP16-coarse comparisons
   --no-serve    skip the continuous-batching serving workload (p50/p99 latency)
+  --no-cases    skip the summaries of the paper's case 1 (Buckley-Leverett errors) and
+                case 5 (257^3 layered run to 128 min) that the default line carries
   --limex-run K run the 257^3 LIMEX workload to K accepted steps (summary line only)
   --case5       Section 5's case 5 at the paper's mesh (257^3 vertices, 33,949,186 DoF)
                 to 128 minutes of simulated time: total time, LIMEX steps and time per
                 step, linear solves and time per solve beside the paper's Table
                 case5_strong (summary line only)
+  --case4       the same for Section 5's 2D case 4 at the mesh of Table case4_strong
+                (4096 x 2048 cells, 16,789,506 DoF)
   --case1       the Buckley-Leverett validation (Section 5, Case 1) on 64 ... 512
                 elements: error norms against the Welge solution, convergence rates,
                 LIMEX step counts and run times beside the paper's Table error1
@@ -207,6 +211,26 @@ def run(args):
         sv = SV.run_benchmark(count=args.serve_requests, quiet=True)
         line["serving"] = sv
         line["p50_ms"], line["p99_ms"] = sv["p50_ms"], sv["p99_ms"]
+    if not args.no_cases:
+        # the paper's own workloads, summarised (full records: --case1, --case5)
+        try:
+            c1 = case1_run()
+            line["case1"] = {"L1": [r["L1"] for r in c1["rows"]], "L2": [r["L2"] for r in c1["rows"]],
+                             "elements": [r["elements"] for r in c1["rows"]],
+                             "steps": [r["steps"] for r in c1["rows"]], "rate_L1": c1["rate_L1"],
+                             "rate_L2": c1["rate_L2"], "wall_s": [r["wall_s"] for r in c1["rows"]],
+                             "paper_L1": [r["paper_limex"]["L1"] for r in c1["rows"]],
+                             "paper_L2": [r["paper_limex"]["L2"] for r in c1["rows"]]}
+        except Exception as e:  # reported, never fatal to the benchmark line
+            line["case1"] = {"error": repr(e)}
+        try:
+            c5 = layered_run("case5")
+            line["case5"] = {k: c5[k] for k in ("dof", "reached_t_end", "T_total_s", "N_limex", "t_limex_s",
+                                                 "N_linear_solves", "t_linear_solve_s", "bicgstab_iterations",
+                                                 "unconverged_solves")}
+            line["case5"]["paper_256pe"] = c5["paper_table_case5_strong"]["256"]
+        except Exception as e:
+            line["case5"] = {"error": repr(e)}
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(mixed["iters"][-1])
     return line
@@ -254,17 +278,24 @@ PAPER_CASE5 = {256: (1182.3, "67+2", 17.13, 458, 0.335), 512: (640.0, "67+2", 9.
                1024: (372.2, "67+2", 5.39, 478, 0.146)}
 
 
-def case5_run(max_attempts=400, precision="mixed", rtol=1e-8):
-    """Section 5, case 5 on one GPU: adaptive LIMEX (k = 3, TOL 5e-3, safety 0.75,
-    tau0 32 s, tau_max 100 d) from t = 0 to 128 min on the 257^3-vertex layered cube,
-    FP32 multigrid inside FP64 BiCGSTAB to rtol, every step timed on the host around
-    the device work (inputs resident; the state never leaves the GPU).  One progress
-    line per attempted step on stderr."""
+# Table case4_strong, LIMEX rows: PE -> (T_total s, steps, t_LIMEX s (T_total / steps), N_linear, t_linear s)
+PAPER_CASE4 = {64: (487.4, "47+1", 487.4 / 48, 307, 0.290), 128: (267.3, "47+1", 267.3 / 48, 307, 0.140),
+               256: (130.7, "47+1", 130.7 / 48, 307, 0.067), 512: (65.0, "47+1", 65.0 / 48, 311, 0.033)}
+
+
+def layered_run(case="case5", max_attempts=400, precision="mixed", rtol=1e-8, maxit=200):
+    """Section 5, case 5 (257^3 layered cube) or case 4 (4096 x 2048 layered section)
+    on one GPU: adaptive LIMEX (k = 3, TOL 5e-3, safety 0.75, tau0 32 s, tau_max
+    100 d) from t = 0 to 128 min, FP32 multigrid inside FP64 BiCGSTAB to rtol with at
+    most maxit iterations per stage solve (a stage solve that fails rejects the step),
+    every step timed on the host around the device work (inputs resident; the state
+    never leaves the GPU).  One progress line per attempted step on stderr."""
     import torch
 
     import paper_2506_04763_amd as tpf
     import workloads as W
-    scn = W.case5(257)
+    scn = W.case5(257) if case == "case5" else W.case4(4096)
+    paper = PAPER_CASE5 if case == "case5" else PAPER_CASE4
     m = scn.meta
     t_setup = time.perf_counter()
     g = tpf.Grid(scn, precision=precision, limex_stages=m["stages"])
@@ -278,12 +309,12 @@ def case5_run(max_attempts=400, precision="mixed", rtol=1e-8):
         dt = min(dt, m["t_end"] - t)
         ts = time.perf_counter()
         acc, t, dt_next, st = g.limex_step(u, t, dt, stages=m["stages"], tol=m["tol"], safety=m["safety"],
-                                           dt_max=m["dt_max"], rtol=rtol)
+                                           dt_max=m["dt_max"], rtol=rtol, maxit=maxit)
         torch.cuda.synchronize()
         rec = dict(accepted=bool(acc), t=t, dt=dt, eps=st["eps"], solves=st["solves"], iters=st["iters_total"],
                    unconverged=st["unconverged"], seconds=time.perf_counter() - ts)
         steps.append(rec)
-        print(json.dumps({"case5_step": len(steps), **rec}), file=sys.stderr, flush=True)
+        print(json.dumps({f"{case}_step": len(steps), **rec}), file=sys.stderr, flush=True)
         dt = dt_next
     wall = time.perf_counter() - t0
     sn_max = float(u.reshape(-1, 2)[:, 1].max())
@@ -291,17 +322,19 @@ def case5_run(max_attempts=400, precision="mixed", rtol=1e-8):
     acc = sum(1 for s in steps if s["accepted"])
     solves = sum(s["solves"] for s in steps)
     iters = sum(s["iters"] for s in steps)
-    return {"workload": "case5_257^3_layered_poly_kr_point_injection_128min", "dof": 2 * scn.nverts,
-            "levels": scn.levels, "precision": precision, "rtol": rtol, "stages": m["stages"],
+    name = ("case5_257^3_layered_poly_kr_point_injection_128min" if case == "case5"
+            else "case4_4097x2049_layered_poly_kr_point_injection_128min")
+    return {"workload": name, "dof": 2 * scn.nverts,
+            "levels": scn.levels, "precision": precision, "rtol": rtol, "maxit": maxit, "stages": m["stages"],
             "t_end_s": t, "reached_t_end": bool(t >= m["t_end"] * (1 - 1e-14)),
             "T_total_s": round(wall, 2), "setup_s": round(setup_s, 2),
             "N_limex": f"{acc}+{len(steps) - acc}", "t_limex_s": round(wall / max(len(steps), 1), 3),
             "N_linear_solves": solves, "t_linear_solve_s": round(wall / max(solves, 1), 4),
             "bicgstab_iterations": iters, "unconverged_solves": sum(s["unconverged"] for s in steps),
             "sn_max": sn_max,
-            "paper_table_case5_strong": {str(k): {"T_total_s": v[0], "N_limex": v[1], "t_limex_s": v[2],
-                                                  "N_linear": v[3], "t_linear_s": v[4]}
-                                         for k, v in PAPER_CASE5.items()},
+            f"paper_table_{case}_strong": {str(k): {"T_total_s": v[0], "N_limex": v[1],
+                                                    "t_limex_s": round(v[2], 3), "N_linear": v[3],
+                                                    "t_linear_s": v[4]} for k, v in paper.items()},
             "dt_sequence": [round(s["dt"], 3) for s in steps]}
 
 
@@ -397,6 +430,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-cases", action="store_true",
+                    help="leave out the case-1 and case-5 summaries of the default line")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--counters", action="store_true",
                     help="run the short hardware-counter workload instead of the benchmark")
@@ -406,6 +441,8 @@ def main():
                     help="run the Buckley-Leverett validation instead of the benchmark")
     ap.add_argument("--case5", action="store_true",
                     help="run Section 5's case 5 at 257^3 to 128 minutes instead of the benchmark")
+    ap.add_argument("--case4", action="store_true",
+                    help="run Section 5's case 4 at 4096 x 2048 cells to 128 minutes instead of the benchmark")
     args = ap.parse_args()
     if args.counters:
         counters_driver()
@@ -413,8 +450,8 @@ def main():
     if args.case1:
         print(json.dumps(case1_run()), flush=True)
         return
-    if args.case5:
-        print(json.dumps(case5_run()), flush=True)
+    if args.case5 or args.case4:
+        print(json.dumps(layered_run("case5" if args.case5 else "case4")), flush=True)
         return
     if args.limex_run:
         print(json.dumps(limex_run(args.limex_run)), flush=True)

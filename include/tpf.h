@@ -151,7 +151,7 @@ typedef struct tpf_limex_stats {
   int32_t accepted;      /* 1 accepted, 0 rejected                               */
   int32_t solves;        /* stage solves performed                              */
   int32_t iters_total;   /* BiCGSTAB iterations summed over the solves          */
-  int32_t unconverged;   /* stage solves that hit maxit                          */
+  int32_t unconverged;   /* failed stage solves (0 or 1: the first one rejects)  */
   double eps;            /* error estimate [[eps]]                               */
   double dt_used;        /* step attempted                                       */
   double dt_next;        /* proposed next step                                   */
@@ -215,6 +215,11 @@ tpf_status tpf_solve_stage(tpf_grid *g, const double *f, double *x, double rtol,
  * eps <= tol; next step min(dt_max, dt (safety tol / eps)^(1/3)).
  * On accept u <- T_kk, *t += *dt; on reject u and *t are unchanged.  Either way
  * *dt <- the proposed next step.  Requires opts->stages <= desc.limex_stages.
+ * A stage solve that misses opts->rtol within opts->maxit iterations, or breaks
+ * down on finite data, rejects the step at once (the paper gives no rule for a
+ * failed linear solve): the remaining stages are skipped, stats->eps = +inf,
+ * stats->unconverged = 1, and the next step is min(dt_max, dt / 4).  A
+ * non-finite F(u) (non-finite input) is TPF_EBREAKDOWN.
  * Returns TPF_OK, TPF_STEP_REJECTED or an error. */
 tpf_status tpf_limex_step(tpf_grid *g, double *u, double *t, double *dt, const tpf_limex_opts *opts,
                           tpf_limex_stats *stats, tpf_stream stream);

@@ -8,6 +8,8 @@
 // eps^2 = (e_p^2 + e_S^2)/2 balances pressure and saturation errors; ||grad p||^2 is
 // the exact integral of the Q1 interpolant (closed-form element stiffness of a
 // box), ||S_w||^2 the lumped (dual-box) L2 norm.
+#include <cmath>
+
 #include "tpf_internal.h"
 
 namespace tpf {
@@ -148,14 +150,15 @@ tpf_status limex_step(tpf_grid *g, double *u, double *t, double *dt, const tpf_l
   tpf_limex_stats ls{};
   ls.dt_used = H;
   TPF_TRY(copy_vec(g->u0, u, n, s));
-  for (int j = 1; j <= k; ++j) {
+  bool failed = false;  // a stage solve missed rtol within maxit or broke down
+  for (int j = 1; j <= k && !failed; ++j) {
     TPF_TRY(launch_assemble(g, g->u0, H / j, g->f0, s));
     TPF_TRY(build_hierarchy(g, s));
     g->assembled = true;
     g->has_f0 = true;
     double *Tj = g->T[j - 1];
     TPF_TRY(copy_vec(Tj, g->u0, n, s));
-    for (int m = 0; m < j; ++m) {
+    for (int m = 0; m < j && !failed; ++m) {
       const double *rhs = g->f0;
       if (m > 0) {
         TPF_TRY(launch_residual(g, Tj, g->fv, s));
@@ -163,13 +166,28 @@ tpf_status limex_step(tpf_grid *g, double *u, double *t, double *dt, const tpf_l
       }
       tpf_solve_stats st{};
       const tpf_status rs = bicgstab(g, rhs, g->xb, o->rtol, o->maxit, &st, s);
-      if (rs < 0) return rs;
-      if (rs == TPF_NOT_CONVERGED) ls.unconverged++;
       ls.solves++;
       ls.iters_total += st.iters;
+      // a non-finite right-hand side is bad input, and device errors are hard errors;
+      // a solve that fails on finite data asks for a shorter step
+      if (rs < 0 && (rs != TPF_EBREAKDOWN || !std::isfinite(st.fnorm))) return rs;
+      if (rs != TPF_OK) {
+        ls.unconverged++;
+        failed = true;
+        break;
+      }
       k_axpy<<<RED_BLOCKS, BS, 0, s>>>(n, Tj, g->xb);
       TPF_LAUNCH_CHECK();
     }
+  }
+  if (failed) {  // reject: u and t unchanged, a quarter of the step next
+    ls.eps = INFINITY;
+    ls.accepted = 0;
+    ls.dt_next = fmin(o->dt_max, 0.25 * H);
+    *dt = ls.dt_next;
+    if (stats) *stats = ls;
+    TPF_HIP(hipStreamSynchronize(s));
+    return TPF_STEP_REJECTED;
   }
   // Aitken-Neville tableau in place: pass l builds column l+1 for rows k..l+1
   for (int l = 1; l <= k - 1; ++l) {

@@ -1,9 +1,10 @@
 """Full-size parity of the HIP path, in the configuration the benchmark times.
 
 Workloads: the 129^3 log-normal cube (sigma_lnK 2, mixed precision, 6 levels, rtol
-1e-8: the benchmark's stage), the 65^3 cube (sigma_lnK 1, FP64, 5 levels, rtol 1e-10)
-and the 257^3 layered cube (mixed, 6 levels, LIMEX k = 3).  These grids are too large
-for the whole-grid oracle inside a test, so
+1e-8: the benchmark's stage), the 65^3 cube (sigma_lnK 1, FP64, 5 levels, rtol 1e-10),
+the 257^3 layered cube (mixed, 6 levels, LIMEX k = 3), and the paper's case 5 (257^3)
+and case 4 (4097 x 2049, the 2D path) at the meshes of its scaling tables.  These grids
+are too large for the whole-grid oracle inside a test, so
 
   * residual and stage-matrix rows are compared at sampled vertices (corners, edges,
     faces, injection-patch edges, next to Dirichlet faces, seeded interior vertices)
@@ -78,7 +79,7 @@ def check_fine_rows(scn, g, u, f, samples, mixed, label):
     stage matrix against the windowed oracle at state u (host (N, 2))."""
     gidx = torch.as_tensor([vertex_index(scn, v) for v in samples], device="cuda")
     A = g.matrix(0)
-    blocks = A[:, gidx, :].cpu().numpy()                      # (27, S, 4)
+    blocks = A[:, gidx, :].cpu().numpy()                      # (27 or 9, S, 4)
     del A
     blocks32 = g.matrix(0, "mixed")[:, gidx, :].cpu().numpy() if mixed else None
     F = f.reshape(-1, 2)[gidx].cpu().numpy()
@@ -94,8 +95,8 @@ def check_fine_rows(scn, g, u, f, samples, mixed, label):
         Fref[s] = Fw[2 * lv:2 * lv + 2]
         for r in (0, 1):
             scale = abs(Aw[2 * lv + r].data).max()
-            for o in range(27):
-                d = (o % 3 - 1, (o // 3) % 3 - 1, o // 9 - 1)
+            for o in range(blocks.shape[0]):
+                d = (o % 3 - 1, (o // 3) % 3 - 1, o // 9 - 1 if scn.dim == 3 else 0)
                 nb = [v[a] + d[a] for a in range(3)]
                 inside = all(0 <= nb[a] < scn.n[a] for a in range(3))
                 for c in (0, 1):
@@ -147,8 +148,8 @@ def test_sampled_coarse_rows(stage):
         li = (I[0] - clo[0]) + ncw[0] * ((I[1] - clo[1]) + ncw[1] * (I[2] - clo[2]))
         for r in (0, 1):
             scale = abs(A1[2 * li + r].data).max()
-            for o in range(27):
-                d = (o % 3 - 1, (o // 3) % 3 - 1, o // 9 - 1)
+            for o in range(blocks.shape[0]):
+                d = (o % 3 - 1, (o // 3) % 3 - 1, o // 9 - 1 if scn.dim == 3 else 0)
                 J = [I[a] + d[a] for a in range(3)]
                 if not all(0 <= J[a] < nc[a] for a in range(3)):
                     assert blocks[o, s, 2 * r] == 0.0 and blocks[o, s, 2 * r + 1] == 0.0
@@ -264,6 +265,40 @@ def test_case5_257_first_step():
     assert dt_next == pytest.approx(want, rel=1e-12)
     assert acc == (st["eps"] <= m["tol"])
     # the injected non-wetting mass appears at the injection vertex
+    if acc:
+        assert float(u.reshape(-1, 2)[v, 1]) > scn.s_res[1]
+    g.close()
+    torch.cuda.empty_cache()
+
+
+def test_case4_full_mesh_first_step():
+    """Section 5 case 4 at the mesh of Table case4_strong (4096 x 2048 cells,
+    16,789,506 DoF), the 2D path: sampled rows (the injection vertex among them) at the
+    initial and a perturbed state, and one LIMEX step with k = 3 from tau0 = 32 s."""
+    scn = W.case4(4096)
+    print(f"[fullsize] case4 n={scn.n} levels={scn.levels}", flush=True)
+    g = tpf.Grid(scn, precision="mixed", limex_stages=3)
+    u0 = g.initial_state()
+    f = g.empty()
+    g.assemble_stage(u0, H, f0_out=f)
+    v = scn.meta["injection_vertex"]
+    inj = (v % scn.n[0], v // scn.n[0], 0)
+    check_fine_rows(scn, g, scn.u0.reshape(-1, 2), f, sample_vertices(scn, 10, seed=10) + [inj], True, "case4")
+    up = W.perturbed_state(scn, 4, dp=2e3, sn_lo=0.1, sn_hi=0.5)
+    fp = g.empty()
+    g.assemble_stage(torch.as_tensor(up.ravel(), device="cuda"), H, f0_out=fp)
+    check_fine_rows(scn, g, up.reshape(-1, 2), fp, sample_vertices(scn, 6, seed=11) + [inj], True,
+                    "case4 perturbed")
+    u = u0.clone()
+    m = scn.meta
+    acc, t, dt_next, st = g.limex_step(u, 0.0, m["dt0"], stages=3, tol=m["tol"], safety=m["safety"],
+                                       dt_max=m["dt_max"], rtol=1e-8)
+    print(f"[fullsize] case4 LIMEX step: accepted={acc} eps={st['eps']:.3e} dt_next={dt_next:.4g} "
+          f"solves={st['solves']} iterations={st['iters_total']}", flush=True)
+    assert st["solves"] == 6 and st["unconverged"] == 0
+    want = m["dt_max"] if st["eps"] == 0.0 else min(m["dt_max"], m["dt0"] * (m["safety"] * m["tol"] / st["eps"]) ** (1 / 3))
+    assert dt_next == pytest.approx(want, rel=1e-12)
+    assert acc == (st["eps"] <= m["tol"])
     if acc:
         assert float(u.reshape(-1, 2)[v, 1]) > scn.s_res[1]
     g.close()

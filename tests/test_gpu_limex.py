@@ -100,3 +100,24 @@ def test_limex_case5_three_stages():
     print(log)
     assert per_field(ug, uo) < 1e-8
     assert sum(1 for l in log if l[0]) >= 4
+
+
+def test_failed_stage_solve_rejects_step():
+    """A stage solve forced to fail from the host (one iteration allowed, rtol 1e-12)
+    rejects the step on both sides: u and t unchanged, eps = inf, a quarter step next,
+    the remaining stages skipped."""
+    scn = W.lens_2d()
+    g = tpf.Grid(scn, precision="fp64", limex_stages=2)
+    u = torch.as_tensor(scn.u0.ravel().copy(), device="cuda")
+    u_before = u.clone()
+    acc, t, dt_next, st = g.limex_step(u, 100.0, 32.0, stages=2, rtol=1e-12, maxit=1)
+    assert not acc and t == 100.0 and dt_next == 8.0
+    assert st["unconverged"] == 1 and st["solves"] == 1 and st["eps"] == float("inf")
+    assert bool(torch.equal(u, u_before))
+    out, info = ST.Stage(scn).limex_step(scn.u0.ravel().copy(), 32.0, stages=2, rtol=1e-12, maxit=1)
+    assert not info["accepted"] and info["dt_next"] == dt_next and info["solves"] == st["solves"]
+    # the grid stays usable: a normal step from the same state is accepted as before
+    acc2, t2, _, st2 = g.limex_step(u, 100.0, 32.0, stages=2, rtol=1e-10, maxit=400)
+    assert acc2 and t2 == 132.0 and st2["unconverged"] == 0
+    g.close()
+

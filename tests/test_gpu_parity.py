@@ -54,10 +54,11 @@ CASES = [
     ("cube17", lambda: W.small_cube(17, sigma=2.0, seed=23), 3),
     # Section 5 case 5: polynomial k_r, residual saturations, layered p_d(K), point source
     ("case5_17", lambda: W.case5(17), 3),
+    ("case4_64x32", lambda: W.case4(64), 4),
 ]
 # pressure perturbation of the parity state: the case-5 pressures are ~5e7 Pa, so a
 # 50 Pa perturbation would leave F below the rounding of its own 5e7-sized terms
-DP = {"case5_17": 2e4}
+DP = {"case5_17": 2e4, "case4_64x32": 2e4}
 
 
 @pytest.fixture(scope="module", params=CASES, ids=[c[0] for c in CASES])

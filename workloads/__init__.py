@@ -292,6 +292,57 @@ def case5(n: int = 257, levels: Optional[int] = None) -> Scenario:
     return scn
 
 
+C4_EXTENT = (500.0, 200.0)
+C4_INJECTION = (250.0, 30.0)
+
+
+def case4(cells_x: int = 4096, levels: Optional[int] = None) -> Scenario:
+    """Case 4 of Section 5 (Table case4, Fig. Ap): 2D layer-wise heterogeneity.
+
+    A 500 m x 200 m section of cells_x x cells_x/2 cells (4096 x 2048 is the mesh of
+    Table case4_strong, 16,789,506 DoF) in four horizontal layers of 50 m with the
+    permeabilities, fluids, residual saturations, p_d(K) and polynomial k_r of case 5;
+    gravity along -y.  y = 0: Dirichlet S_w = 1 - S_nr, p_n = 5e7 Pa; other sides
+    closed.  Initially S_w = 1 - S_nr with hydrostatic p_w.  Non-wetting injection of
+    0.05 pore volumes per year (per metre of depth) at the point (250, 30) m, into the
+    control volume containing it.  The scaling runs simulate 128 min from tau0 = 32 s
+    (tau_max 100 d, TOL 5e-3, safety 0.75)."""
+    if cells_x % 8:
+        raise ValueError("cells_x must be a multiple of 8 (layer boundaries on vertices)")
+    Lx, Ly = C4_EXTENT
+    nx, ny = cells_x + 1, cells_x // 2 + 1
+    scn = _empty(f"case4_{cells_x}x{cells_x // 2}", 2, (nx, ny, 1), (Lx, Ly, 1.0), (0.0, -GRAV, 0.0))
+    scn.rho = (1000.0, 700.0)
+    scn.mu = (1e-3, 5.654e-5)
+    scn.s_res = (0.2, 0.1)
+    scn.kr_model, scn.kr_coef = "poly", (0.9, 0.5)
+    _, cy, _ = scn.cell_centres()
+    layer = np.minimum((cy // (Ly / 4)).astype(int), 3)
+    scn.perm = np.asarray(C5_LAYER_K)[layer]
+    scn.poro = np.full(scn.ncells, 0.1)
+    scn.entry_p = case5_pd(scn.perm)
+    scn.bc_lambda = np.full(scn.ncells, 2.0)
+    x, y, _ = scn.vertex_coords()
+    p_bottom = C5_P_BOTTOM - float(case5_pd(C5_LAYER_K[0]))
+    p = p_bottom - scn.rho[0] * GRAV * y
+    sn0 = scn.s_res[1]
+    bottom = np.isclose(y, 0.0)
+    scn.dir_mask = np.where(bottom, 3, 0).astype(np.uint8)
+    scn.dir_value = np.stack([np.full_like(y, p_bottom), np.full_like(y, sn0)], axis=1)
+    scn.u0 = np.stack([p, np.full_like(y, sn0)], axis=1)
+    dx, dy, _ = scn.spacing
+    ix, iy = int(np.floor(C4_INJECTION[0] / dx + 0.5)), int(np.floor(C4_INJECTION[1] / dy + 0.5))
+    v = ix + nx * iy
+    rate = C5_PV_PER_YEAR * Lx * Ly * 0.1 / (365 * 86400.0) * scn.rho[1]   # kg/s per metre of depth
+    src = np.zeros((scn.nverts, 2))
+    src[v, 1] = rate
+    scn.vertex_source = src
+    scn.levels = default_levels(ny) if levels is None else levels
+    scn.meta = dict(case="case4", t_end=C5_T_END, dt0=32.0, dt_max=100 * 86400.0, tol=5e-3, safety=0.75,
+                    stages=3, injection_vertex=v, injection_rate=rate)
+    return scn
+
+
 def _empty(name, dim, n, extent, gravity) -> Scenario:
     N = int(n[0] * n[1] * n[2])
     return Scenario(name=name, dim=dim, n=tuple(int(v) for v in n), extent=tuple(map(float, extent)),
