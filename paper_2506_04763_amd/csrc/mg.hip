@@ -405,29 +405,43 @@ __host__ __device__ __forceinline__ void restrict_vertex(long long I, const Geo 
                                                         const T *__restrict__ rf,
                                                         const uint8_t *__restrict__ fmask, const T vr,
                                                         T *__restrict__ bc) {
+  // branch-free: all 3^d neighbours are loaded (out-of-grid ones at a clamped, valid
+  // position, with weight 0) before any is used; summation order dz, dy, dx
+  constexpr int NP = DIM == 3 ? 27 : 9;
   int cx, cy, cz;
   vcoords(I, C, cx, cy, cz);
   const int fx = 2 * cx, fy = 2 * cy, fz = DIM == 3 ? 2 * cz : 0;
+  typename Vec2<T>::type rv[NP];
+  uint8_t mk[NP];
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    const int dx = k % 3 - 1, dy = (k / 3) % 3 - 1, dz = DIM == 3 ? k / 9 - 1 : 0;
+    const int xr = fx + dx, yr = fy + dy, zr = fz + dz;
+    const int x = xr < 0 ? 0 : (xr >= F.nx ? F.nx - 1 : xr);
+    const int y = yr < 0 ? 0 : (yr >= F.ny ? F.ny - 1 : yr);
+    const int z = zr < 0 ? 0 : (zr >= F.nz ? F.nz - 1 : zr);
+    const long long i = x + (long long)F.nx * (y + (long long)F.ny * z);
+    rv[k] = *reinterpret_cast<const typename Vec2<T>::type *>(rf + 2 * i);
+    mk[k] = fmask ? fmask[i] : (uint8_t)0;
+  }
   T s0 = 0, s1 = 0;
-  for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0); ++dz)
-    for (int dy = -1; dy <= 1; ++dy)
-      for (int dx = -1; dx <= 1; ++dx) {
-        const int x = fx + dx, y = fy + dy, z = fz + dz;
-        if (x < 0 || y < 0 || z < 0 || x >= F.nx || y >= F.ny || z >= F.nz) continue;
-        const T wl = (T)((dx ? 0.5 : 1.0) * (dy ? 0.5 : 1.0) * (dz ? 0.5 : 1.0));
-        const T wc = (dx <= 0 && dy <= 0 && dz <= 0) ? (T)1 : (T)0;
-        const long long i = x + (long long)F.nx * (y + (long long)F.ny * z);
-        const auto rv = *reinterpret_cast<const typename Vec2<T>::type *>(rf + 2 * i);
-        T r0 = rv.x, r1 = rv.y;
-        if (fmask) {
-          const uint8_t m = fmask[i];
-          if (!m) r0 += vr * r1;
-          if (m & 1) r0 = 0;
-          if (m & 2) r1 = 0;
-        }
-        s0 += wl * r0;
-        s1 += wc * r1;
-      }
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    const int dx = k % 3 - 1, dy = (k / 3) % 3 - 1, dz = DIM == 3 ? k / 9 - 1 : 0;
+    const bool in = fx + dx >= 0 && fx + dx < F.nx && fy + dy >= 0 && fy + dy < F.ny && fz + dz >= 0 &&
+                    fz + dz < F.nz;
+    T r0 = rv[k].x, r1 = rv[k].y;
+    if (fmask) {
+      const uint8_t m = mk[k];
+      if (!m) r0 += vr * r1;
+      if (m & 1) r0 = 0;
+      if (m & 2) r1 = 0;
+    }
+    const T wl = in ? (T)((dx ? 0.5 : 1.0) * (dy ? 0.5 : 1.0) * (dz ? 0.5 : 1.0)) : (T)0;
+    const T wc = (in && dx <= 0 && dy <= 0 && dz <= 0) ? (T)1 : (T)0;
+    s0 += wl * r0;
+    s1 += wc * r1;
+  }
   typename Vec2<T>::type o;
   o.x = s0;
   o.y = s1;
@@ -450,32 +464,36 @@ template <int DIM, typename T>
 __host__ __device__ __forceinline__ void prolong_vertex(long long i, const Geo &F, const Geo &C,
                                                        const T *__restrict__ ec,
                                                        const uint8_t *__restrict__ fmask, T *__restrict__ xf) {
+  // branch-free: x and the mask first, then the 2^d coarse pressure values (an even
+  // fine index takes the same coarse vertex twice, once with weight 0)
+  auto xv = *reinterpret_cast<typename Vec2<T>::type *>(xf + 2 * i);
+  const uint8_t m = fmask ? fmask[i] : (uint8_t)0;
   int x, y, z;
   vcoords(i, F, x, y, z);
   const int xl = x >> 1, xh = (x + 1) >> 1, yl = y >> 1, yh = (y + 1) >> 1;
   const int zl = DIM == 3 ? z >> 1 : 0, zh = DIM == 3 ? (z + 1) >> 1 : 0;
-  T s0 = 0;
-  for (int kz = 0; kz < (DIM == 3 ? 2 : 1); ++kz)
-    for (int ky = 0; ky < 2; ++ky)
-      for (int kx = 0; kx < 2; ++kx) {
-        const int X = kx ? xh : xl, Y = ky ? yh : yl, Z = kz ? zh : zl;
-        // each axis contributes weight 1 (even index: both picks coincide, count once) or 1/2
-        const T wx = (x & 1) ? (T)0.5 : (kx ? (T)0 : (T)1);
-        const T wy = (y & 1) ? (T)0.5 : (ky ? (T)0 : (T)1);
-        const T wz = DIM == 3 ? ((z & 1) ? (T)0.5 : (kz ? (T)0 : (T)1)) : (T)1;
-        const T w = wx * wy * wz;
-        if (w == (T)0) continue;
-        const long long J = X + (long long)C.nx * (Y + (long long)C.ny * Z);
-        s0 += w * ec[2 * J];
-      }
-  const long long Ja = xh + (long long)C.nx * (yh + (long long)C.ny * zh);
-  T s1 = ec[2 * Ja + 1];
-  if (fmask) {
-    const uint8_t m = fmask[i];
-    if (m & 1) s0 = 0;
-    if (m & 2) s1 = 0;
+  // per axis: weight of the lower and the upper coarse vertex
+  const T hx = (x & 1) ? (T)0.5 : (T)1, hy = (y & 1) ? (T)0.5 : (T)1;
+  const T hz = (DIM == 3 && (z & 1)) ? (T)0.5 : (T)1;
+  const T ox = (x & 1) ? (T)0.5 : (T)0, oy = (y & 1) ? (T)0.5 : (T)0;
+  const T oz = (DIM == 3 && (z & 1)) ? (T)0.5 : (T)0;
+  const long long sy = C.nx, sz = (long long)C.nx * C.ny;
+  constexpr int NK = DIM == 3 ? 8 : 4;
+  T v[NK];
+#pragma unroll
+  for (int k = 0; k < NK; ++k) {
+    const int X = (k & 1) ? xh : xl, Y = (k & 2) ? yh : yl, Z = (k & 4) ? zh : zl;
+    v[k] = ec[2 * (X + sy * Y + sz * Z)];
   }
-  auto xv = *reinterpret_cast<typename Vec2<T>::type *>(xf + 2 * i);
+  T s1 = ec[2 * (xh + sy * yh + sz * zh) + 1];  // saturation: the aggregating coarse vertex
+  T s0 = 0;
+#pragma unroll
+  for (int k = 0; k < NK; ++k) {
+    const T w = ((k & 1) ? ox : hx) * ((k & 2) ? oy : hy) * (DIM == 3 ? ((k & 4) ? oz : hz) : (T)1);
+    s0 += w * v[k];
+  }
+  if (m & 1) s0 = 0;
+  if (m & 2) s1 = 0;
   xv.x += s0;
   xv.y += s1;
   *reinterpret_cast<typename Vec2<T>::type *>(xf + 2 * i) = xv;
