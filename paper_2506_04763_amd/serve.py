@@ -9,6 +9,15 @@ different requests overlap on the device; the library's per-iteration host
 synchronisation blocks only the worker that issued it.  Every kernel reduces in a
 fixed order, so a request's result does not depend on what else runs beside it.
 
+The server allocates no device memory while it runs.  At start-up it takes one slab
+of its whole budget (one allocation, outside any timed region) and carves grid
+arenas out of it with a first-fit extent list that merges neighbouring free extents;
+an admission that finds no hole large enough evicts idle grids, least recently used
+first, until one appears.  Device allocations in the middle of a run (a grid arena
+of several GB on memory the driver has just taken back) were measured to stall every
+stream for up to seconds.  At shutdown the slab returns to PyTorch's cache as one
+block, which the next server of the same budget gets back without an allocation.
+
 Latency is measured from a request's arrival time to its solution being back in
 host memory.
 """
@@ -54,10 +63,42 @@ class StageResult:
 
 
 class _Resident:
-    __slots__ = ("grid", "nbytes", "busy", "last_used")
+    __slots__ = ("grid", "nbytes", "busy", "last_used", "offset")
 
-    def __init__(self, grid, nbytes):
+    def __init__(self, grid, nbytes, offset):
         self.grid, self.nbytes, self.busy, self.last_used = grid, nbytes, False, time.perf_counter()
+        self.offset = offset  # where the grid's arena starts in the server's slab
+
+
+_ALIGN = 1 << 20  # arenas start on MiB boundaries of the slab
+
+
+class _Extents:
+    """First-fit allocator of [0, size) with coalescing free extents (host side)."""
+
+    def __init__(self, size: int):
+        self.free = [(0, size)]  # sorted (offset, length), no two adjacent
+
+    def take(self, n: int) -> Optional[int]:
+        for k, (off, length) in enumerate(self.free):
+            if length >= n:
+                if length == n:
+                    del self.free[k]
+                else:
+                    self.free[k] = (off + n, length - n)
+                return off
+        return None
+
+    def give(self, off: int, n: int):
+        import bisect
+        k = bisect.bisect_left(self.free, (off, 0))
+        self.free.insert(k, (off, n))
+        if k + 1 < len(self.free) and off + n == self.free[k + 1][0]:  # merge with the next
+            self.free[k] = (off, n + self.free[k + 1][1])
+            del self.free[k + 1]
+        if k > 0 and self.free[k - 1][0] + self.free[k - 1][1] == off:  # and with the previous
+            self.free[k - 1] = (self.free[k - 1][0], self.free[k - 1][1] + self.free[k][1])
+            del self.free[k]
 
 
 class Server:
@@ -66,7 +107,10 @@ class Server:
         import torch
         self.torch = torch
         self.device = torch.device(device)
-        self.budget = int(budget_bytes)
+        self.budget = int(budget_bytes) // _ALIGN * _ALIGN
+        with torch.cuda.device(self.device):
+            self._slab = torch.empty(self.budget, dtype=torch.uint8, device=self.device)
+        self._extents = _Extents(self.budget)
         self.precision = precision
         self.keep_resident = keep_resident
         self.levels_of = levels_of
@@ -107,32 +151,41 @@ class Server:
             t.join(timeout=60)
         with self._lock:
             for r in self._resident.values():
-                r.grid.close()
+                if r.grid is not None:
+                    r.grid.close()
             self._resident.clear()
             self._used = 0
+            self._extents = _Extents(self.budget)
+            self._slab = None
 
     # -- scheduling ------------------------------------------------------------------
     def _levels(self, scn):
         return self.levels_of(scn) if self.levels_of else scn.levels
 
     def _bytes(self, req):
-        return grid_bytes(req.scenario, precision=self.precision, levels=self._levels(req.scenario))
+        n = grid_bytes(req.scenario, precision=self.precision, levels=self._levels(req.scenario))
+        return (n + _ALIGN - 1) // _ALIGN * _ALIGN
 
-    def _make_room(self, need) -> bool:
-        """Evict idle resident grids (least recently used first) until `need` fits."""
-        if self._used + need <= self.budget:
-            return True
-        for key in list(self._resident.keys()):
-            r = self._resident[key]
-            if r.busy:
-                continue
-            r.grid.close()
-            self._used -= r.nbytes
-            del self._resident[key]
-            self.evictions += 1
-            if self._used + need <= self.budget:
-                return True
-        return self._used + need <= self.budget
+    def _evict(self, key):
+        """Close an idle resident grid and return its extent to the slab."""
+        r = self._resident.pop(key)
+        if r.grid is not None:
+            r.grid.close()  # synchronises the grid's stream: the extent is idle afterwards
+        self._extents.give(r.offset, r.nbytes)
+        self._used -= r.nbytes
+        self.evictions += 1
+
+    def _place(self, need) -> Optional[int]:
+        """An extent of `need` bytes in the slab, evicting idle grids (least recently
+        used first) until a large enough hole appears; None if none can be made."""
+        while True:
+            off = self._extents.take(need)
+            if off is not None:
+                return off
+            idle = [k for k, r in self._resident.items() if not r.busy]
+            if not idle:
+                return None
+            self._evict(idle[0])
 
     def _dispatch(self):
         while True:
@@ -150,12 +203,16 @@ class Server:
                         self._waiting.popleft()
                         fut.set_exception(MemoryError(f"request {req.rid} needs {need} bytes > budget {self.budget}"))
                         continue
-                    if not self._make_room(need):
+                    if key in self._resident:  # busy with an earlier request: wait for it
+                        self._lock.wait(timeout=0.01)
+                        continue
+                    off = self._place(need)
+                    if off is None:
                         self._lock.wait(timeout=0.01)  # wait for a running request to release memory
                         continue
                     self._used += need
                     self.peak_used = max(self.peak_used, self._used)
-                    self._resident[key] = _Resident(None, need)
+                    self._resident[key] = _Resident(None, need, off)
                 res = self._resident[key]
                 res.busy = True
                 self._resident.move_to_end(key)
@@ -177,8 +234,9 @@ class Server:
                     with self._lock:
                         res = self._resident[key]
                     if res.grid is None:
+                        arena = self._slab[res.offset:res.offset + res.nbytes]
                         res.grid = Grid(req.scenario, precision=self.precision, levels=self._levels(req.scenario),
-                                        device=self.device, stream=stream)
+                                        device=self.device, stream=stream, arena=arena)
                     g = res.grid
                     g._stream = stream
                     u0 = g.initial_state()
@@ -197,10 +255,8 @@ class Server:
                         r.busy = False
                         r.last_used = time.perf_counter()
                         if not self.keep_resident:
-                            if r.grid is not None:
-                                r.grid.close()
-                            self._used -= r.nbytes
-                            del self._resident[key]
+                            self._evict(key)
+                            self.evictions -= 1  # a release, not an eviction
                     self._free_slots.append(slot)
                     self._lock.notify_all()
 

@@ -57,6 +57,21 @@ def test_budget_eviction_and_rejection():
     srv.shutdown()
 
 
+def test_slab_extents_reused_give_identical_results():
+    """Under a budget for about two grids, arenas are carved again and again from the
+    server's slab (evicting idle grids); every result equals the one computed under an
+    ample budget, bit for bit."""
+    reqs = small_requests()
+    need = max(serve.grid_bytes(q.scenario, precision="mixed") for q in reqs)
+    tight, st = run(reqs, slots=2, budget=int(need * 2.2))
+    ample, st2 = run(reqs, slots=2, budget=50e9)
+    assert st["evictions"] > 0 and st2["evictions"] == 0
+    assert st["peak"] <= int(need * 2.2)
+    for a, b in zip(tight, ample):
+        assert a.stats["iters"] == b.stats["iters"]
+        np.testing.assert_array_equal(a.x, b.x)
+
+
 def test_resident_grid_reused():
     reqs = small_requests()[:2]
     srv = serve.Server(budget_bytes=50e9, slots=2)
