@@ -305,10 +305,10 @@ def test_neumann_patch_total():
     assert f2.Q[:, 1].sum() == pytest.approx(0.075 * 0.2, rel=1e-13)
 
 
-@pytest.mark.parametrize("dim", [2, 3, "case5"])
+@pytest.mark.parametrize("dim", [2, 3, "case5", "case4"])
 def test_jacobian_complex_step_vs_central_differences(dim):
-    if dim == "case5":  # polynomial laws, residual saturations, layered p_d(K), point source
-        scn = W.case5(5)
+    if dim in ("case5", "case4"):  # polynomial laws, residual saturations, layered p_d(K), point source
+        scn = W.case5(5) if dim == "case5" else W.case4(16)
         u = W.perturbed_state(scn, 3, dp=2e4, sn_lo=0.12, sn_hi=0.6)
     else:
         scn = W.lens_2d(9, 5) if dim == 2 else W.small_cube(4, sigma=1.0, seed=5)
