@@ -121,7 +121,7 @@ def run(args):
         prof = prec == "mixed"
         breakdown, dom = None, None
         if prof:
-            # untimed breakdown step: every class timed (an event pair per launch)
+            # untimed breakdown step: every launch of every class timed with HIP events
             g.profile_begin(200000)
             g.assemble_stage(u0, h, f0_out=f)
             x, stats = g.solve_stage(f, rtol=rtol, maxit=500, out=x)

@@ -268,14 +268,17 @@ enum {
 typedef struct tpf_kernel_time {
   int32_t count;        /* timed launches                                        */
   int32_t reserved;
-  double total_ms;      /* summed event-to-event durations                       */
+  double total_ms;      /* summed start-to-end event durations                   */
 } tpf_kernel_time;
 
-/* Starts recording a pair of HIP events around each launch of the classes whose
- * bit (1u << class) is set in class_mask (0: every class), up to max_launches
- * launches; later launches are not timed.  Each recorded event is a marker in the
- * stream, so timing only the classes of interest keeps the others unperturbed.
- * Creates the events; no device memory is allocated. */
+/* Starts timing each launch of the classes whose bit (1u << class) is set in
+ * class_mask (0: every class), up to max_launches launches; later launches are not
+ * timed.  A class of single kernel launches gets its pair of HIP events attached to
+ * each dispatch (hipExtLaunchKernel: the kernel's own start and end); the classes
+ * TPF_K_RAP and TPF_K_COARSE_LU, several launches each, are bracketed by event
+ * markers in the stream.  A timed dispatch still costs about 6 us more than an
+ * untimed one, so timing only the classes of interest keeps the others
+ * unperturbed.  Creates the events; no device memory is allocated. */
 tpf_status tpf_profile_begin(tpf_grid *g, int32_t max_launches, uint32_t class_mask);
 
 /* Synchronises the recorded events, writes per-class totals to out[TPF_K_COUNT]

@@ -561,21 +561,22 @@ tpf_status launch_assemble(tpf_grid *g, const double *u0, double h, double *f0, 
   double *mst = g->lv[0].mst;
   const double ih = 1.0 / h;
   const CellIn in = cell_in(g, u0);
-  const int ps = prof_begin(g, TPF_K_ASSEMBLE, s);
+  const uint8_t *dm = g->dmask;
+  const double *Q = g->Q;
   if (g->dim == 3) {
     const unsigned nb2 = blocks_for(g->P.N, SPLIT_V);
     if (A32)
-      k_assemble3_split<true><<<nb2, BS, 0, s>>>(g->P, in, g->dmask, g->Q, ih, A64, A32, f0, mst);
+      TPF_HIP(launch(g, TPF_K_ASSEMBLE, k_assemble3_split<true>, nb2, BS, s, g->P, in, dm, Q, ih, A64, A32, f0, mst));
     else
-      k_assemble3_split<false><<<nb2, BS, 0, s>>>(g->P, in, g->dmask, g->Q, ih, A64, nullptr, f0, mst);
+      TPF_HIP(launch(g, TPF_K_ASSEMBLE, k_assemble3_split<false>, nb2, BS, s, g->P, in, dm, Q, ih, A64,
+                     (float *)nullptr, f0, mst));
   } else {
     if (A32)
-      k_assemble<2, true, true><<<nb, BS, 0, s>>>(g->P, in, g->dmask, g->Q, ih, A64, A32, f0, mst);
+      TPF_HIP(launch(g, TPF_K_ASSEMBLE, k_assemble<2, true, true>, nb, BS, s, g->P, in, dm, Q, ih, A64, A32, f0, mst));
     else
-      k_assemble<2, true, false><<<nb, BS, 0, s>>>(g->P, in, g->dmask, g->Q, ih, A64, nullptr, f0, mst);
+      TPF_HIP(launch(g, TPF_K_ASSEMBLE, k_assemble<2, true, false>, nb, BS, s, g->P, in, dm, Q, ih, A64,
+                     (float *)nullptr, f0, mst));
   }
-  TPF_LAUNCH_CHECK();
-  prof_end(g, ps, s);
   return TPF_OK;
 }
 

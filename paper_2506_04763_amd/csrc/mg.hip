@@ -401,10 +401,10 @@ __global__ void k_expand16(const uint16_t *__restrict__ A16, const float *__rest
 // residual enters in the volume-balance form of the Galerkin product: at vertices
 // without Dirichlet components the wetting entry becomes r_w + vr r_n.
 template <int DIM, typename T>
-__host__ __device__ __forceinline__ void restrict_vertex(long long I, const Geo &F, const Geo &C,
-                                                        const T *__restrict__ rf,
-                                                        const uint8_t *__restrict__ fmask, const T vr,
-                                                        T *__restrict__ bc) {
+__host__ __device__ __forceinline__ typename Vec2<T>::type restrict_vertex(long long I, const Geo &F, const Geo &C,
+                                                                          const T *__restrict__ rf,
+                                                                          const uint8_t *__restrict__ fmask,
+                                                                          const T vr, T *__restrict__ bc) {
   // branch-free: all 3^d neighbours are loaded (out-of-grid ones at a clamped, valid
   // position, with weight 0) before any is used; summation order dz, dy, dx
   constexpr int NP = DIM == 3 ? 27 : 9;
@@ -446,6 +446,7 @@ __host__ __device__ __forceinline__ void restrict_vertex(long long I, const Geo 
   o.x = s0;
   o.y = s1;
   *reinterpret_cast<typename Vec2<T>::type *>(bc + 2 * I) = o;
+  return o;
 }
 
 template <int DIM, typename T>
@@ -455,6 +456,30 @@ __global__ void __launch_bounds__(BS) k_restrict(const Geo F, const Geo C, const
   const long long I = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (I >= C.N) return;
   restrict_vertex<DIM, T>(I, F, C, rf, fmask, vr, bc);
+}
+
+// Restriction followed by the coarse level's first sweep from a zero guess,
+// xc = 0 + omega D_c^{-1} bc, which needs only the vertex's own restricted value and
+// centre block: one launch instead of two on every level that is smoothed.  The
+// arithmetic is that of the separate first sweep, so the results are identical.
+template <int DIM, typename T>
+__global__ void __launch_bounds__(BS) k_restrict_first(const Geo F, const Geo C, const T *__restrict__ rf,
+                                                       const uint8_t *__restrict__ fmask, const T vr,
+                                                       T *__restrict__ bc, const T *__restrict__ Ac,
+                                                       T *__restrict__ xc, const T omega) {
+  const long long I = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= C.N) return;
+  constexpr int CEN = DIM == 3 ? 13 : 4;
+  T d[4];
+  Blk<T>::load(Ac + ((long long)CEN * C.N + I) * 4, d);
+  const auto o = restrict_vertex<DIM, T>(I, F, C, rf, fmask, vr, bc);
+  T z0, z1;
+  solve2<T>(d, o.x, o.y, z0, z1);
+  const T x0 = 0, x1 = 0;
+  typename Vec2<T>::type out;
+  out.x = x0 + omega * z0;
+  out.y = x1 + omega * z1;
+  *reinterpret_cast<typename Vec2<T>::type *>(xc + 2 * I) = out;
 }
 
 // Prolongation and correction xf += P ec: linear interpolation of the pressure
@@ -823,9 +848,11 @@ bool sweep16(tpf_grid *g, int l, bool first, const T *b, const T *xi, T *xo, T o
     const Level &lv = g->lv[l];
     const unsigned nb = blocks_for(lv.N);
     if (first)
-      k_jacobi16<DIM, true><<<nb, BS, 0, s>>>(geo(lv), lv.A16, lv.s16, b, nullptr, xo, om);
+      (void)launch(g, TPF_K_COARSE_LEVELS, k_jacobi16<DIM, true>, nb, BS, s, geo(lv), (const uint16_t *)lv.A16,
+                   (const float *)lv.s16, b, (const T *)nullptr, xo, om);
     else
-      k_jacobi16<DIM, false><<<nb, BS, 0, s>>>(geo(lv), lv.A16, lv.s16, b, xi, xo, om);
+      (void)launch(g, TPF_K_COARSE_LEVELS, k_jacobi16<DIM, false>, nb, BS, s, geo(lv), (const uint16_t *)lv.A16,
+                   (const float *)lv.s16, b, xi, xo, om);
     return true;
   }
 }
@@ -837,7 +864,8 @@ bool resid16(tpf_grid *g, int l, const T *b, const T *x, T *r, hipStream_t s) {
   } else {
     if (g->prec != TPF_MIXED16 || l == 0) return false;
     const Level &lv = g->lv[l];
-    k_resid16<DIM><<<blocks_for(lv.N), BS, 0, s>>>(geo(lv), lv.A16, lv.s16, b, x, r);
+    (void)launch(g, TPF_K_COARSE_LEVELS, k_resid16<DIM>, blocks_for(lv.N), BS, s, geo(lv),
+                 (const uint16_t *)lv.A16, (const float *)lv.s16, b, x, r);
     return true;
   }
 }
@@ -863,13 +891,13 @@ tpf_status vcycle_t(tpf_grid *g, const double *bin, double *xout, hipStream_t s)
     return reinterpret_cast<const T *>(g->lv[l].A32);
   };
   constexpr bool NT0 = sizeof(T) == sizeof(float);  // finest FP32 matrix: streamed, non-temporal
+  const T *const noT = nullptr;
+  const uint8_t *const nomask = nullptr;
   if (L == 1) {  // single level: the dense solve is the whole cycle
     Level &lc = g->lv[0];
     T *X = sizeof(T) == sizeof(double) ? reinterpret_cast<T *>(xout) : reinterpret_cast<T *>(lc.x);
-    const int ps = prof_begin(g, TPF_K_COARSE_LEVELS, s);
-    k_coarse_solve<T><<<(g->nc + 3) / 4, 256, 0, s>>>(g->ainv, g->nc, b0, X);
-    TPF_LAUNCH_CHECK();
-    prof_end(g, ps, s);
+    TPF_HIP(launch(g, TPF_K_COARSE_LEVELS, k_coarse_solve<T>, (unsigned)((g->nc + 3) / 4), 256u, s,
+                   (const double *)g->ainv, g->nc, b0, X));
     if (sizeof(T) != sizeof(double)) {
       k_cast<T, double><<<1024, BS, 0, s>>>(X, xout, 2 * lc.N);
       TPF_LAUNCH_CHECK();
@@ -879,61 +907,68 @@ tpf_status vcycle_t(tpf_grid *g, const double *bin, double *xout, hipStream_t s)
   const T *bl[MAXL];
   T *cur[MAXL];
   bl[0] = b0;
+  // levels whose first sweep runs inside the restriction (not the FP16 levels)
+  auto fused_first = [&](int l) { return l >= 1 && l < L - 1 && g->prec != TPF_MIXED16; };
   for (int l = 0; l < L - 1; ++l) {
     Level &lv = g->lv[l];
     const Geo G = geo(lv);
     const unsigned nb = blocks_for(lv.N);
     T *X = reinterpret_cast<T *>(lv.x), *Y = reinterpret_cast<T *>(lv.y);
-    int ps = prof_begin(g, l == 0 ? TPF_K_SMOOTH0_FIRST : TPF_K_COARSE_LEVELS, s);
-    if (sweep16<DIM, T>(g, l, true, bl[l], nullptr, X, om, s)) {
-    } else if (l == 0 && NT0)
-      k_jacobi<DIM, T, T, true, false, true><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], nullptr, X, om);
-    else
-      k_jacobi<DIM, T, T, true><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], nullptr, X, om);
-    TPF_LAUNCH_CHECK();
-    prof_end(g, ps, s);
-    for (int k = 1; k < g->nu_pre; ++k) {
-      ps = prof_begin(g, l == 0 ? TPF_K_SMOOTH0 : TPF_K_COARSE_LEVELS, s);
-      if (sweep16<DIM, T>(g, l, false, bl[l], X, Y, om, s)) {
-      } else if (l == 0 && NT0)
-        k_jacobi_stream<DIM, T, T><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, Y, om);
-      else if (lv.N > LAT_NMAX)
-        k_jacobi<DIM, T, T, false><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, Y, om);
-      else
-        k_jacobi<DIM, T, T, false, false, false, true><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, Y, om);
+    const int c_sm = l == 0 ? TPF_K_SMOOTH0 : TPF_K_COARSE_LEVELS;
+    if (fused_first(l)) {
+      // X already holds the first sweep, written with the restriction into this level
+    } else if (sweep16<DIM, T>(g, l, true, bl[l], nullptr, X, om, s)) {
       TPF_LAUNCH_CHECK();
-      prof_end(g, ps, s);
+    } else if (l == 0 && NT0) {
+      TPF_HIP(launch(g, TPF_K_SMOOTH0_FIRST, k_jacobi<DIM, T, T, true, false, true>, nb, BS, s, G, A_of(l), bl[l],
+                     noT, X, om));
+    } else {
+      TPF_HIP(launch(g, l == 0 ? TPF_K_SMOOTH0_FIRST : TPF_K_COARSE_LEVELS, k_jacobi<DIM, T, T, true>, nb, BS, s,
+                     G, A_of(l), bl[l], noT, X, om));
+    }
+    for (int k = 1; k < g->nu_pre; ++k) {
+      if (sweep16<DIM, T>(g, l, false, bl[l], X, Y, om, s)) {
+        TPF_LAUNCH_CHECK();
+      } else if (l == 0 && NT0) {
+        TPF_HIP(launch(g, c_sm, k_jacobi_stream<DIM, T, T>, nb, BS, s, G, A_of(l), bl[l], (const T *)X, Y, om));
+      } else if (lv.N > LAT_NMAX) {
+        TPF_HIP(launch(g, c_sm, k_jacobi<DIM, T, T, false>, nb, BS, s, G, A_of(l), bl[l], (const T *)X, Y, om));
+      } else {
+        TPF_HIP(launch(g, c_sm, k_jacobi<DIM, T, T, false, false, false, true>, nb, BS, s, G, A_of(l), bl[l],
+                       (const T *)X, Y, om));
+      }
       T *t = X; X = Y; Y = t;
     }
     cur[l] = X;
     T *R = reinterpret_cast<T *>(lv.r);
-    ps = prof_begin(g, l == 0 ? TPF_K_RESID0 : TPF_K_COARSE_LEVELS, s);
+    const int c_re = l == 0 ? TPF_K_RESID0 : TPF_K_COARSE_LEVELS;
     if (resid16<DIM, T>(g, l, bl[l], X, R, s)) {
-    } else if (l == 0 && NT0)
-      k_resid_stream<DIM, T><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, R);
-    else if (lv.N > LAT_NMAX)
-      k_resid<DIM, T><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, R);
-    else
-      k_resid<DIM, T, false, true><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, R);
-    TPF_LAUNCH_CHECK();
-    prof_end(g, ps, s);
+      TPF_LAUNCH_CHECK();
+    } else if (l == 0 && NT0) {
+      TPF_HIP(launch(g, c_re, k_resid_stream<DIM, T>, nb, BS, s, G, A_of(l), bl[l], (const T *)X, R));
+    } else if (lv.N > LAT_NMAX) {
+      TPF_HIP(launch(g, c_re, k_resid<DIM, T>, nb, BS, s, G, A_of(l), bl[l], (const T *)X, R));
+    } else {
+      TPF_HIP(launch(g, c_re, k_resid<DIM, T, false, true>, nb, BS, s, G, A_of(l), bl[l], (const T *)X, R));
+    }
     Level &lc = g->lv[l + 1];
     T *bc = reinterpret_cast<T *>(lc.b);
-    ps = prof_begin(g, l == 0 ? TPF_K_TRANSFER0 : TPF_K_COARSE_LEVELS, s);
-    k_restrict<DIM, T><<<blocks_for(lc.N), BS, 0, s>>>(G, geo(lc), R, l == 0 ? g->dmask : nullptr,
-                                                       (T)(g->P.rho_w / g->P.rho_n), bc);
-    TPF_LAUNCH_CHECK();
-    prof_end(g, ps, s);
+    const int c_tr = l == 0 ? TPF_K_TRANSFER0 : TPF_K_COARSE_LEVELS;
+    const uint8_t *fm = l == 0 ? (const uint8_t *)g->dmask : nomask;
+    const T vr = (T)(g->P.rho_w / g->P.rho_n);
+    if (fused_first(l + 1))
+      TPF_HIP(launch(g, c_tr, k_restrict_first<DIM, T>, blocks_for(lc.N), BS, s, G, geo(lc), (const T *)R, fm, vr,
+                     bc, A_of(l + 1), reinterpret_cast<T *>(lc.x), om));
+    else
+      TPF_HIP(launch(g, c_tr, k_restrict<DIM, T>, blocks_for(lc.N), BS, s, G, geo(lc), (const T *)R, fm, vr, bc));
     bl[l + 1] = bc;
   }
   // coarsest level: x = A^{-1} b, one wavefront per row of the inverse
   {
     Level &lc = g->lv[L - 1];
     T *X = reinterpret_cast<T *>(lc.x);
-    const int ps = prof_begin(g, TPF_K_COARSE_LEVELS, s);
-    k_coarse_solve<T><<<(g->nc + 3) / 4, 256, 0, s>>>(g->ainv, g->nc, bl[L - 1], X);
-    TPF_LAUNCH_CHECK();
-    prof_end(g, ps, s);
+    TPF_HIP(launch(g, TPF_K_COARSE_LEVELS, k_coarse_solve<T>, (unsigned)((g->nc + 3) / 4), 256u, s,
+                   (const double *)g->ainv, g->nc, bl[L - 1], X));
     cur[L - 1] = X;
   }
   for (int l = L - 2; l >= 0; --l) {
@@ -942,32 +977,31 @@ tpf_status vcycle_t(tpf_grid *g, const double *bin, double *xout, hipStream_t s)
     const unsigned nb = blocks_for(lv.N);
     T *X = cur[l];
     T *Y = (X == reinterpret_cast<T *>(lv.x)) ? reinterpret_cast<T *>(lv.y) : reinterpret_cast<T *>(lv.x);
-    int ps = prof_begin(g, l == 0 ? TPF_K_TRANSFER0 : TPF_K_COARSE_LEVELS, s);
-    k_prolong<DIM, T><<<nb, BS, 0, s>>>(G, geo(g->lv[l + 1]), cur[l + 1], l == 0 ? g->dmask : nullptr, X);
-    TPF_LAUNCH_CHECK();
-    prof_end(g, ps, s);
+    const int c_sm = l == 0 ? TPF_K_SMOOTH0 : TPF_K_COARSE_LEVELS;
+    TPF_HIP(launch(g, l == 0 ? TPF_K_TRANSFER0 : TPF_K_COARSE_LEVELS, k_prolong<DIM, T>, nb, BS, s, G,
+                   geo(g->lv[l + 1]), (const T *)cur[l + 1], l == 0 ? (const uint8_t *)g->dmask : nomask, X));
     const int nu = g->nu_post;
     for (int k = 0; k < nu; ++k) {
-      ps = prof_begin(g, l == 0 ? TPF_K_SMOOTH0 : TPF_K_COARSE_LEVELS, s);
       if (l == 0 && k == nu - 1) {
         if (NT0)
-          k_jacobi_stream<DIM, T, double><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, xout, om);
+          TPF_HIP(launch(g, c_sm, k_jacobi_stream<DIM, T, double>, nb, BS, s, G, A_of(l), bl[l], (const T *)X,
+                         xout, om));
         else
-          k_jacobi<DIM, T, double, false><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, xout, om);
-        TPF_LAUNCH_CHECK();
-        prof_end(g, ps, s);
+          TPF_HIP(launch(g, c_sm, k_jacobi<DIM, T, double, false>, nb, BS, s, G, A_of(l), bl[l], (const T *)X,
+                         xout, om));
         X = nullptr;
         break;
       }
       if (sweep16<DIM, T>(g, l, false, bl[l], X, Y, om, s)) {
-      } else if (l == 0 && NT0)
-        k_jacobi_stream<DIM, T, T><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, Y, om);
-      else if (lv.N > LAT_NMAX)
-        k_jacobi<DIM, T, T, false><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, Y, om);
-      else
-        k_jacobi<DIM, T, T, false, false, false, true><<<nb, BS, 0, s>>>(G, A_of(l), bl[l], X, Y, om);
-      TPF_LAUNCH_CHECK();
-      prof_end(g, ps, s);
+        TPF_LAUNCH_CHECK();
+      } else if (l == 0 && NT0) {
+        TPF_HIP(launch(g, c_sm, k_jacobi_stream<DIM, T, T>, nb, BS, s, G, A_of(l), bl[l], (const T *)X, Y, om));
+      } else if (lv.N > LAT_NMAX) {
+        TPF_HIP(launch(g, c_sm, k_jacobi<DIM, T, T, false>, nb, BS, s, G, A_of(l), bl[l], (const T *)X, Y, om));
+      } else {
+        TPF_HIP(launch(g, c_sm, k_jacobi<DIM, T, T, false, false, false, true>, nb, BS, s, G, A_of(l), bl[l],
+                       (const T *)X, Y, om));
+      }
       T *t = X; X = Y; Y = t;
     }
     if (l == 0 && X != nullptr) {  // nu_post == 0
@@ -1030,10 +1064,8 @@ tpf_status hierarchy_t(tpf_grid *g, hipStream_t s) {
 template <int DIM>
 tpf_status spmv_t(tpf_grid *g, int level, const double *x, double *y, hipStream_t s) {
   const Level &lv = g->lv[level];
-  const int ps = prof_begin(g, level == 0 ? TPF_K_SPMV64 : TPF_K_COARSE_LEVELS, s);
-  k_spmv64<DIM, 0><<<blocks_for(lv.N), BS, 0, s>>>(geo(lv), lv.A64, x, y, nullptr, nullptr);
-  TPF_LAUNCH_CHECK();
-  prof_end(g, ps, s);
+  TPF_HIP(launch(g, level == 0 ? TPF_K_SPMV64 : TPF_K_COARSE_LEVELS, k_spmv64<DIM, 0>, blocks_for(lv.N), BS, s,
+                 geo(lv), (const double *)lv.A64, x, y, (const double *)nullptr, (double *)nullptr));
   return TPF_OK;
 }
 
@@ -1076,24 +1108,26 @@ tpf_status spmv64_mode(tpf_grid *g, int mode, const double *x, double *y, const 
   const unsigned nb = blocks_for(lv.N);
   *nblk_out = nb;
   const Geo G = geo(lv);
-  const int ps = prof_begin(g, TPF_K_SPMV64, s);
+  auto go = [&](auto kern) {
+    return launch(g, TPF_K_SPMV64, kern, nb, BS, s, G, (const double *)lv.A64, x, y, d0, part);
+  };
+  hipError_t e;
   if (g->dim == 3) {
     switch (mode) {
-      case 1: k_spmv64<3, 1><<<nb, BS, 0, s>>>(G, lv.A64, x, y, d0, part); break;
-      case 2: k_spmv64<3, 2><<<nb, BS, 0, s>>>(G, lv.A64, x, y, d0, part); break;
-      case 3: k_spmv64<3, 3><<<nb, BS, 0, s>>>(G, lv.A64, x, y, d0, part); break;
-      default: k_spmv64<3, 0><<<nb, BS, 0, s>>>(G, lv.A64, x, y, d0, part); break;
+      case 1: e = go(k_spmv64<3, 1>); break;
+      case 2: e = go(k_spmv64<3, 2>); break;
+      case 3: e = go(k_spmv64<3, 3>); break;
+      default: e = go(k_spmv64<3, 0>); break;
     }
   } else {
     switch (mode) {
-      case 1: k_spmv64<2, 1><<<nb, BS, 0, s>>>(G, lv.A64, x, y, d0, part); break;
-      case 2: k_spmv64<2, 2><<<nb, BS, 0, s>>>(G, lv.A64, x, y, d0, part); break;
-      case 3: k_spmv64<2, 3><<<nb, BS, 0, s>>>(G, lv.A64, x, y, d0, part); break;
-      default: k_spmv64<2, 0><<<nb, BS, 0, s>>>(G, lv.A64, x, y, d0, part); break;
+      case 1: e = go(k_spmv64<2, 1>); break;
+      case 2: e = go(k_spmv64<2, 2>); break;
+      case 3: e = go(k_spmv64<2, 3>); break;
+      default: e = go(k_spmv64<2, 0>); break;
     }
   }
-  TPF_LAUNCH_CHECK();
-  prof_end(g, ps, s);
+  TPF_HIP(e);
   return TPF_OK;
 }
 

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cstdint>
 #include <cstdio>
@@ -113,6 +114,23 @@ inline int prof_begin(tpf_grid *g, int c, hipStream_t s) {
 }
 inline void prof_end(tpf_grid *g, int slot, hipStream_t s) {
   if (slot >= 0) (void)hipEventRecord(g->prof.ev[2 * slot + 1], s);
+}
+// Launches kern<<<grid, block, 0, s>>>(args...).  While launches of class c are timed,
+// the class's event pair is attached to the dispatch itself (the extended launch), so
+// the events hold the kernel's own start and end and the stream gets no marker packets
+// between kernels; otherwise this is a plain launch.  Returns the launch status.
+template <typename... P, typename... A>
+inline hipError_t launch(tpf_grid *g, int c, void (*kern)(P...), unsigned grid, unsigned block, hipStream_t s,
+                         A... args) {
+  Prof &p = g->prof;
+  if (p.active && p.used < p.cap && ((p.mask >> c) & 1u)) {
+    const int i = p.used++;
+    p.cls[i] = c;
+    hipExtLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, s, p.ev[2 * i], p.ev[2 * i + 1], 0u, args...);
+  } else {
+    kern<<<grid, block, 0, s>>>(args...);
+  }
+  return hipGetLastError();
 }
 }  // namespace tpf
 
