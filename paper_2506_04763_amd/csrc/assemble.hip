@@ -227,7 +227,68 @@ __host__ __device__ __forceinline__ constexpr int bit(int l, int a) { return (l 
 
 struct CellIn {
   const double *u, *Kc, *phic, *pdc, *lamc, *pdmin, *pv;
+  const double *cp;  // per (cell, corner) laws from corner_pass (CP doubles each), or null
 };
+
+// The quantities of one (cell, corner) pair that depend only on the corner vertex
+// and the cell, in this order: the hat saturation of the corner in the cell and its
+// S_n-derivative, the element-local capillary pressure and its derivative, the
+// non-wetting mobility at the hat saturation and its derivative, the wetting mobility
+// at the plain saturation and its derivative (both derivatives w.r.t. S_n).
+constexpr int CP = 8;
+
+// Interface condition (Eq. hSw) and the laws at corner saturation sn of a cell with
+// entry pressure pde and 1/lambda il; pdm = p_dmin of the corner, pvl = (P, dP/dS_n)
+// of the corner.
+__host__ __device__ __forceinline__ void corner_laws(const double sn, const double pdm, const double2 pvl,
+                                                    const double pde, const double lame, const double il,
+                                                    const Phys &P, double &sh, double &dsh, double &pc,
+                                                    double &dpc, double &khn, double &dkhn) {
+  // equal entry pressure / barrier / continuity
+  if (pde == pdm) {
+    sh = sn; dsh = 1.0;
+  } else if (pde >= pvl.x) {
+    sh = P.snr; dsh = 0.0;
+  } else {
+    const double ses = exp_fin(-lame * log_pos(pvl.x / pde));
+    sh = 1.0 - (P.swr + ses * P.D);
+    dsh = -P.D * (-lame * ses / pvl.x * pvl.y);
+  }
+  double se, dse;
+  eff_sat(sh, P, se, dse);
+  const double t = root_lam(se, il);
+  pc = pde / t;
+  dpc = pc * (-il) / se * dse * dsh;
+  // non-wetting mobility of the corner at its hat saturation (for upwinding)
+  double dk_dse;
+  krn_se(se, t, il, P, khn, dk_dse);
+  dkhn = dk_dse * dse;
+}
+
+// All corners of cell c: the CP quantities of corner l at cp[(c * 2^d + l) * CP].
+template <int DIM>
+__host__ __device__ __forceinline__ void corner_pass(const long long c, const Phys &P, const CellIn &in,
+                                                    double *__restrict__ cp) {
+  constexpr int NC = 1 << DIM;
+  int ox, oy, oz;
+  grid_coords(c, P.ncx, P.ncy, ox, oy, oz);
+  const long long sy = P.nx, sz = (long long)P.nx * P.ny;
+  const long long v0 = ox + sy * oy + sz * oz;
+  const double pde = in.pdc[c], lame = in.lamc[c];
+  const double il = 1.0 / lame;
+#pragma unroll
+  for (int l = 0; l < NC; ++l) {
+    const long long vl = v0 + bit(l, 0) + sy * bit(l, 1) + sz * ((DIM == 3) ? bit(l, 2) : 0);
+    const double sn = in.u[2 * vl + 1];
+    const double2 pvl = *reinterpret_cast<const double2 *>(in.pv + 2 * vl);
+    double q[CP];
+    corner_laws(sn, in.pdmin[vl], pvl, pde, lame, il, P, q[0], q[1], q[2], q[3], q[4], q[5]);
+    krw(sn, il, P, q[6], q[7]);
+    double2 *dst = reinterpret_cast<double2 *>(cp + (c * NC + l) * CP);
+#pragma unroll
+    for (int k = 0; k < CP / 2; ++k) dst[k] = make_double2(q[2 * k], q[2 * k + 1]);
+  }
+}
 
 // ---------------------------------------------------------------------------------
 // Cell contributions to the residual row of vertex v and (WANT_A) to its row of
@@ -235,7 +296,7 @@ struct CellIn {
 // HALF >= 0; stencil slot o goes to acc[o - BASE].  Storage derivatives are returned
 // in mwS, mnS (dm_w/dS_n and dm_n/dS_n of the vertex).
 // ---------------------------------------------------------------------------------
-template <int DIM, bool WANT_A, int HALF, int BASE, int NSLOT>
+template <int DIM, bool WANT_A, int HALF, int BASE, int NSLOT, bool PAIRS = false>
 __host__ __device__ __forceinline__ void accumulate_cells(const long long v, const Phys &P, const CellIn &in,
                                                          double (&acc)[NSLOT][4], double &Fw, double &Fn,
                                                          double &mwS, double &mnS) {
@@ -257,7 +318,7 @@ __host__ __device__ __forceinline__ void accumulate_cells(const long long v, con
       const long long c = ox + (long long)P.ncx * (oy + (long long)P.ncy * oz);
       const double Ke = in.Kc[c], phie = in.phic[c], pde = in.pdc[c], lame = in.lamc[c];
       const double il = 1.0 / lame;
-      double p[NC], sn[NC], sh[NC], dsh[NC], pc[NC], dpc[NC], khn[NC], dkhn[NC];
+      double p[NC], sn[NC], sh[NC], dsh[NC], pc[NC], dpc[NC], khn[NC], dkhn[NC], kwl[NC], dkwl[NC];
 #pragma unroll
       for (int l = 0; l < NC; ++l) {
         const int dx = bit(l, 0) - bit(cc, 0), dy = bit(l, 1) - bit(cc, 1);
@@ -266,27 +327,16 @@ __host__ __device__ __forceinline__ void accumulate_cells(const long long v, con
         const double2 ul = *reinterpret_cast<const double2 *>(in.u + 2 * vl);
         p[l] = ul.x;
         sn[l] = ul.y;
-        const double pdm = in.pdmin[vl];
-        const double2 pvl = *reinterpret_cast<const double2 *>(in.pv + 2 * vl);
-        // interface condition (Eq. hSw): equal entry pressure / barrier / continuity
-        if (pde == pdm) {
-          sh[l] = sn[l]; dsh[l] = 1.0;
-        } else if (pde >= pvl.x) {
-          sh[l] = P.snr; dsh[l] = 0.0;
+        if constexpr (PAIRS) {  // the pair's laws from the corner pass
+          const double2 *q = reinterpret_cast<const double2 *>(in.cp + (c * NC + l) * CP);
+          const double2 q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3];
+          sh[l] = q0.x; dsh[l] = q0.y; pc[l] = q1.x; dpc[l] = q1.y;
+          khn[l] = q2.x; dkhn[l] = q2.y; kwl[l] = q3.x; dkwl[l] = q3.y;
         } else {
-          const double ses = exp_fin(-lame * log_pos(pvl.x / pde));
-          sh[l] = 1.0 - (P.swr + ses * P.D);
-          dsh[l] = -P.D * (-lame * ses / pvl.x * pvl.y);
+          const double2 pvl = *reinterpret_cast<const double2 *>(in.pv + 2 * vl);
+          corner_laws(sn[l], in.pdmin[vl], pvl, pde, lame, il, P, sh[l], dsh[l], pc[l], dpc[l], khn[l], dkhn[l]);
+          kwl[l] = dkwl[l] = 0.0;  // unused: the wetting mobility is evaluated per face
         }
-        double se, dse;
-        eff_sat(sh[l], P, se, dse);
-        const double t = root_lam(se, il);
-        pc[l] = pde / t;
-        dpc[l] = pc[l] * (-il) / se * dse * dsh[l];
-        // non-wetting mobility of the corner at its hat saturation (for upwinding)
-        double dk_dse;
-        krn_se(se, t, il, P, khn[l], dk_dse);
-        dkhn[l] = dk_dse * dse;
       }
       // storage of the sub-control volume (vertex, cell): only dM/dS_n is non-zero
       mwS -= phie * rw * P.scv * dsh[cc];
@@ -326,7 +376,12 @@ __host__ __device__ __forceinline__ void accumulate_cells(const long long v, con
         const double phw = cw * (dp - rw * ga);
         const bool upw0 = phw >= 0.0;
         double kw, dkw;
-        krw(upw0 ? sn[l0] : sn[l1], il, P, kw, dkw);
+        if constexpr (PAIRS) {
+          kw = upw0 ? kwl[l0] : kwl[l1];
+          dkw = upw0 ? dkwl[l0] : dkwl[l1];
+        } else {
+          krw(upw0 ? sn[l0] : sn[l1], il, P, kw, dkw);
+        }
         const double fw = rw * kw * phw;
         // non-wetting phase, upwinded hat saturation
         const double cn = -(Ke / P.mu_n) * area;
@@ -426,7 +481,7 @@ __host__ __device__ __forceinline__ void finish_vertex(const long long v, const 
 
 // Residual F(u) and (WANT_A) the stage matrix A = M(u)/h - dF/du for one vertex,
 // all cells in one thread.
-template <int DIM, bool WANT_A, bool W32>
+template <int DIM, bool WANT_A, bool W32, bool PAIRS = false>
 __host__ __device__ __forceinline__ void assemble_vertex(const long long v, const Phys &P, const CellIn &in,
                                                         const uint8_t *__restrict__ dmask,
                                                         const double *__restrict__ Q, const double inv_h,
@@ -440,18 +495,29 @@ __host__ __device__ __forceinline__ void assemble_vertex(const long long v, cons
 #pragma unroll
     for (int e = 0; e < 4; ++e) acc[o][e] = 0.0;
   double Fw = 0.0, Fn = 0.0, mwS = 0.0, mnS = 0.0;
-  accumulate_cells<DIM, WANT_A, -1, 0, NS>(v, P, in, acc, Fw, Fn, mwS, mnS);
+  accumulate_cells<DIM, WANT_A, -1, 0, NS, PAIRS>(v, P, in, acc, Fw, Fn, mwS, mnS);
   finish_vertex<DIM, WANT_A, W32, true, 0, NS>(v, P, dmask, Q, inv_h, acc, Fw, Fn, mwS, mnS, A64, A32, F, mst);
 }
 
-template <int DIM, bool WANT_A, bool W32>
+template <int DIM, bool WANT_A, bool W32, bool PAIRS = false>
 __global__ void __launch_bounds__(BS)
 k_assemble(const Phys P, const CellIn in, const uint8_t *__restrict__ dmask, const double *__restrict__ Q,
            const double inv_h, double *__restrict__ A64, float *__restrict__ A32, double *__restrict__ F,
            double *__restrict__ mst) {
   const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= P.N) return;
-  assemble_vertex<DIM, WANT_A, W32>(v, P, in, dmask, Q, inv_h, A64, A32, F, mst);
+  assemble_vertex<DIM, WANT_A, W32, PAIRS>(v, P, in, dmask, Q, inv_h, A64, A32, F, mst);
+}
+
+// The per-(cell, corner) laws of every cell, one thread per cell.  A vertex's row
+// needs them at all corners of its 2^d cells, so evaluating them once per pair
+// instead of once per (row, pair) removes most of the assembly's logarithms and
+// exponentials (64 + 24 -> 8 + 8 per 3D vertex besides the 24 face mobilities).
+template <int DIM>
+__global__ void __launch_bounds__(BS) k_corners(const Phys P, const CellIn in, double *__restrict__ cp) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= (long long)P.ncx * P.ncy * P.ncz) return;
+  corner_pass<DIM>(c, P, in, cp);
 }
 
 // 3D matrix assembly with two threads per vertex.  Thread half 1 takes the four
@@ -459,7 +525,7 @@ k_assemble(const Phys P, const CellIn in, const uint8_t *__restrict__ dmask, con
 // above (dz = 0, +1: slots 9..26).  Half 1 hands its dz = 0 plane and its partial
 // sums to half 0 through LDS; half 0 owns the centre, the residual and the storage.
 constexpr int SPLIT_V = BS / 2;  // vertices per block
-template <bool W32>
+template <bool W32, bool PAIRS>
 __global__ void __launch_bounds__(BS)
 k_assemble3_split(const Phys P, const CellIn in, const uint8_t *__restrict__ dmask, const double *__restrict__ Q,
                   const double inv_h, double *__restrict__ A64, float *__restrict__ A32, double *__restrict__ F,
@@ -477,9 +543,9 @@ k_assemble3_split(const Phys P, const CellIn in, const uint8_t *__restrict__ dma
   double Fw = 0.0, Fn = 0.0, mwS = 0.0, mnS = 0.0;
   if (valid) {
     if (half == 1)
-      accumulate_cells<3, true, 1, 0, 18>(v, P, in, acc, Fw, Fn, mwS, mnS);
+      accumulate_cells<3, true, 1, 0, 18, PAIRS>(v, P, in, acc, Fw, Fn, mwS, mnS);
     else
-      accumulate_cells<3, true, 0, 9, 18>(v, P, in, acc, Fw, Fn, mwS, mnS);
+      accumulate_cells<3, true, 0, 9, 18, PAIRS>(v, P, in, acc, Fw, Fn, mwS, mnS);
   }
   if (half == 1) {
 #pragma unroll
@@ -524,7 +590,7 @@ __global__ void k_apply_dirichlet(long long N, const uint8_t *__restrict__ m,
 }
 
 inline CellIn cell_in(const tpf_grid *g, const double *u) {
-  return CellIn{u, g->K, g->phi, g->pd, g->lam, g->pdmin, g->pv};
+  return CellIn{u, g->K, g->phi, g->pd, g->lam, g->pdmin, g->pv, nullptr};
 }
 
 }  // namespace
@@ -543,11 +609,25 @@ tpf_status launch_residual(tpf_grid *g, const double *u, double *f, hipStream_t 
   const unsigned nb = blocks_for(g->P.N);
   k_vertex_pc<<<nb, BS, 0, s>>>(g->P, u, g->pdmin, g->lamref, g->pv);
   TPF_LAUNCH_CHECK();
-  const CellIn in = cell_in(g, u);
-  if (g->dim == 3)
-    k_assemble<3, false, false><<<nb, BS, 0, s>>>(g->P, in, g->dmask, g->Q, 0.0, nullptr, nullptr, f, nullptr);
-  else
-    k_assemble<2, false, false><<<nb, BS, 0, s>>>(g->P, in, g->dmask, g->Q, 0.0, nullptr, nullptr, f, nullptr);
+  CellIn in = cell_in(g, u);
+  if (g->L > 1) {  // the per-(cell, corner) laws first, as in the assembly
+    in.cp = g->rapb;
+    const long long ncell = (long long)g->P.ncx * g->P.ncy * g->P.ncz;
+    if (g->dim == 3)
+      k_corners<3><<<blocks_for(ncell), BS, 0, s>>>(g->P, in, g->rapb);
+    else
+      k_corners<2><<<blocks_for(ncell), BS, 0, s>>>(g->P, in, g->rapb);
+    TPF_LAUNCH_CHECK();
+    if (g->dim == 3)
+      k_assemble<3, false, false, true><<<nb, BS, 0, s>>>(g->P, in, g->dmask, g->Q, 0.0, nullptr, nullptr, f, nullptr);
+    else
+      k_assemble<2, false, false, true><<<nb, BS, 0, s>>>(g->P, in, g->dmask, g->Q, 0.0, nullptr, nullptr, f, nullptr);
+  } else {
+    if (g->dim == 3)
+      k_assemble<3, false, false><<<nb, BS, 0, s>>>(g->P, in, g->dmask, g->Q, 0.0, nullptr, nullptr, f, nullptr);
+    else
+      k_assemble<2, false, false><<<nb, BS, 0, s>>>(g->P, in, g->dmask, g->Q, 0.0, nullptr, nullptr, f, nullptr);
+  }
   TPF_LAUNCH_CHECK();
   return TPF_OK;
 }
@@ -560,23 +640,44 @@ tpf_status launch_assemble(tpf_grid *g, const double *u0, double h, double *f0, 
   float *A32 = g->prec != TPF_FP64 ? g->lv[0].A32 : nullptr;
   double *mst = g->lv[0].mst;
   const double ih = 1.0 / h;
-  const CellIn in = cell_in(g, u0);
-  const uint8_t *dm = g->dmask;
-  const double *Q = g->Q;
+  CellIn in = cell_in(g, u0);
+  // The per-(cell, corner) laws go to the Galerkin-product scratch, which is idle
+  // until the hierarchy is built and holds NST * 4 doubles per vertex, more than the
+  // 2^d * CP per cell needed (grids of one level have none: the rows then evaluate
+  // the laws themselves).
+  const bool pairs = g->L > 1;
+  const int ps = prof_begin(g, TPF_K_ASSEMBLE, s);
+  if (pairs) {
+    in.cp = g->rapb;
+    const long long ncell = (long long)g->P.ncx * g->P.ncy * g->P.ncz;
+    if (g->dim == 3)
+      k_corners<3><<<blocks_for(ncell), BS, 0, s>>>(g->P, in, g->rapb);
+    else
+      k_corners<2><<<blocks_for(ncell), BS, 0, s>>>(g->P, in, g->rapb);
+    TPF_LAUNCH_CHECK();
+  }
   if (g->dim == 3) {
     const unsigned nb2 = blocks_for(g->P.N, SPLIT_V);
-    if (A32)
-      TPF_HIP(launch(g, TPF_K_ASSEMBLE, k_assemble3_split<true>, nb2, BS, s, g->P, in, dm, Q, ih, A64, A32, f0, mst));
+    if (A32 && pairs)
+      k_assemble3_split<true, true><<<nb2, BS, 0, s>>>(g->P, in, g->dmask, g->Q, ih, A64, A32, f0, mst);
+    else if (A32)
+      k_assemble3_split<true, false><<<nb2, BS, 0, s>>>(g->P, in, g->dmask, g->Q, ih, A64, A32, f0, mst);
+    else if (pairs)
+      k_assemble3_split<false, true><<<nb2, BS, 0, s>>>(g->P, in, g->dmask, g->Q, ih, A64, nullptr, f0, mst);
     else
-      TPF_HIP(launch(g, TPF_K_ASSEMBLE, k_assemble3_split<false>, nb2, BS, s, g->P, in, dm, Q, ih, A64,
-                     (float *)nullptr, f0, mst));
+      k_assemble3_split<false, false><<<nb2, BS, 0, s>>>(g->P, in, g->dmask, g->Q, ih, A64, nullptr, f0, mst);
   } else {
-    if (A32)
-      TPF_HIP(launch(g, TPF_K_ASSEMBLE, k_assemble<2, true, true>, nb, BS, s, g->P, in, dm, Q, ih, A64, A32, f0, mst));
+    if (A32 && pairs)
+      k_assemble<2, true, true, true><<<nb, BS, 0, s>>>(g->P, in, g->dmask, g->Q, ih, A64, A32, f0, mst);
+    else if (A32)
+      k_assemble<2, true, true, false><<<nb, BS, 0, s>>>(g->P, in, g->dmask, g->Q, ih, A64, A32, f0, mst);
+    else if (pairs)
+      k_assemble<2, true, false, true><<<nb, BS, 0, s>>>(g->P, in, g->dmask, g->Q, ih, A64, nullptr, f0, mst);
     else
-      TPF_HIP(launch(g, TPF_K_ASSEMBLE, k_assemble<2, true, false>, nb, BS, s, g->P, in, dm, Q, ih, A64,
-                     (float *)nullptr, f0, mst));
+      k_assemble<2, true, false, false><<<nb, BS, 0, s>>>(g->P, in, g->dmask, g->Q, ih, A64, nullptr, f0, mst);
   }
+  TPF_LAUNCH_CHECK();
+  prof_end(g, ps, s);
   return TPF_OK;
 }
 
