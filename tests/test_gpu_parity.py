@@ -216,3 +216,27 @@ def test_repeat_runs_bitwise_equal(case):
     assert outs[0][1] == outs[1][1]
     np.testing.assert_array_equal(outs[0][0], outs[1][0])
     g.close()
+
+
+def test_corner_pass_rows_equal_inline_rows(case):
+    """Grids of several levels evaluate the per-(cell, corner) laws once per pair in a
+    corner pass; a one-level grid has no scratch for it, and its rows evaluate the laws
+    themselves.  The same state must give the same finest matrix, F(u0) and residual
+    on both, bit for bit (FP64 and the FP32 copy)."""
+    import copy
+    scn = case["scn"]
+    if 2 * scn.nverts > 4096:
+        pytest.skip("one level only up to 4096 unknowns (the dense coarsest solve)")
+    one = copy.copy(scn)
+    one.levels = 1
+    ut = torch.as_tensor(case["u"].ravel(), device="cuda")
+    out = []
+    for s_ in (scn, one):
+        g = tpf.Grid(s_, precision="mixed")
+        f0 = g.empty()
+        g.assemble_stage(ut, case["h"], f0_out=f0)
+        out.append((g.matrix(0).cpu().numpy(), g.matrix(0, precision="mixed").cpu().numpy(), f0.cpu().numpy(),
+                    g.residual(ut).cpu().numpy()))
+        g.close()
+    for a, b in zip(out[0], out[1]):
+        np.testing.assert_array_equal(a, b)
