@@ -769,8 +769,112 @@ __global__ void __launch_bounds__(256) k_lu_gemm(double *__restrict__ a, int n, 
   }
 }
 
-// Column j of A^{-1} from the LU factors (one 64-lane block per column).
+// Lane l's copy of register v of lane `src` (a wavefront-uniform index), for doubles.
+__device__ __forceinline__ double readlane_d(double v, int src) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)bits, src);
+  const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Column j of A^{-1} from the factors P A = L U, one 64-lane workgroup per column.
+// Lane l holds rows l + 64 q of the column in registers (q < NB = ceil(n / 64) <=
+// NBMAX).  Forward (L, unit lower) and back (U) substitution go in blocks of 64 rows:
+// the block's 64 x 64 diagonal part of the factor is staged in LDS by one burst of
+// independent loads, its 64 sequential steps broadcast the solved entry with a
+// readlane, and each 64 x 64 block of the factor below (above) it is staged the same
+// way for the update of the rows outside the block.  The updates of every entry come in the
+// same order as in plain column-by-column substitution.  No load or update is
+// conditional (a conditional load is issued and waited for on its own): rows and
+// columns past n are read at clamped, valid positions, and the lanes of rows past n
+// compute values that are never read or stored.  The result is stored in row-major
+// order for the coarse solve.
+template <int NBMAX>
 __global__ void __launch_bounds__(64) k_lu_inverse(const double *__restrict__ lu, const int *__restrict__ piv,
+                                                   int n, double *__restrict__ inv) {
+  __shared__ double D[64 * 64];  // D[c * 64 + l] = factor entry (64 kb + l, 64 kb + c)
+  __shared__ double E[64 * 64];  // the same for the block (64 q + l, 64 kb + c), q != kb
+  const int j = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int NB = (n + 63) >> 6;
+  // P e_j: the unit entry moves with every interchange that touches it
+  int pv[NBMAX];
+#pragma unroll
+  for (int q = 0; q < NBMAX; ++q) pv[q] = piv[min(64 * q + lane, n - 1)];
+  int pos = j;
+#pragma unroll
+  for (int q = 0; q < NBMAX; ++q) {
+    if (q >= NB) break;
+    const int rmax = min(64, n - 64 * q);
+    for (int r = 0; r < rmax; ++r) {
+      const int k = 64 * q + r;
+      const int pk = __builtin_amdgcn_readlane(pv[q], r);
+      pos = pos == k ? pk : (pos == pk ? k : pos);
+    }
+  }
+  double y[NBMAX];
+#pragma unroll
+  for (int q = 0; q < NBMAX; ++q) y[q] = (64 * q + lane == pos) ? 1.0 : 0.0;
+  // L y = P e_j
+#pragma unroll
+  for (int kb = 0; kb < NBMAX; ++kb) {
+    if (kb >= NB) break;
+    const int rc = min(64 * kb + lane, n - 1);
+    const int cmax = min(64, n - 64 * kb);  // columns of this block inside the matrix
+#pragma unroll 16
+    for (int c = 0; c < 64; ++c) D[c * 64 + lane] = lu[(long long)min(64 * kb + c, n - 1) * n + rc];
+    __syncthreads();
+    for (int c = 0; c < cmax; ++c) {
+      const double yk = readlane_d(y[kb], c);
+      if (lane > c) y[kb] -= D[c * 64 + lane] * yk;
+    }
+    // the blocks below, each staged in LDS by one burst of loads
+#pragma unroll
+    for (int q = kb + 1; q < NBMAX; ++q) {
+      if (q >= NB) break;
+      const int rq = min(64 * q + lane, n - 1);
+#pragma unroll 16
+      for (int c = 0; c < 64; ++c) E[c * 64 + lane] = lu[(long long)min(64 * kb + c, n - 1) * n + rq];
+      __syncthreads();
+      for (int c = 0; c < cmax; ++c) y[q] -= E[c * 64 + lane] * readlane_d(y[kb], c);
+      __syncthreads();
+    }
+    __syncthreads();  // D is restaged for the next block
+  }
+  // U x = y
+#pragma unroll
+  for (int kb = NBMAX - 1; kb >= 0; --kb) {
+    if (kb >= NB) continue;
+    const int rc = min(64 * kb + lane, n - 1);
+    const int cmax = min(64, n - 64 * kb);
+#pragma unroll 16
+    for (int c = 0; c < 64; ++c) D[c * 64 + lane] = lu[(long long)min(64 * kb + c, n - 1) * n + rc];
+    __syncthreads();
+    for (int c = cmax - 1; c >= 0; --c) {
+      const double xk = readlane_d(y[kb], c) / D[c * 64 + c];
+      if (lane == c) y[kb] = xk;
+      if (lane < c) y[kb] -= D[c * 64 + lane] * xk;
+    }
+#pragma unroll
+    for (int q = 0; q < kb; ++q) {  // the blocks above
+#pragma unroll 16
+      for (int c = 0; c < 64; ++c) E[c * 64 + lane] = lu[(long long)min(64 * kb + c, n - 1) * n + 64 * q + lane];
+      __syncthreads();
+      for (int c = cmax - 1; c >= 0; --c) y[q] -= E[c * 64 + lane] * readlane_d(y[kb], c);
+      __syncthreads();
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < NBMAX; ++q) {
+    const int i = 64 * q + lane;
+    if (q < NB && i < n) inv[(long long)i * n + j] = y[q];
+  }
+}
+
+// Column j of A^{-1} from the LU factors (one 64-lane block per column), column by
+// column with the vector in LDS: the inverse of coarsest levels above 1024 unknowns.
+__global__ void __launch_bounds__(64) k_lu_inverse_cols(const double *__restrict__ lu, const int *__restrict__ piv,
                                                    int n, double *__restrict__ inv) {
   extern __shared__ double y[];
   const int j = blockIdx.x;
@@ -1055,8 +1159,16 @@ tpf_status hierarchy_t(tpf_grid *g, hipStream_t s) {
       TPF_LAUNCH_CHECK();
     }
   }
-  k_lu_inverse<<<n, 64, (size_t)n * sizeof(double), s>>>(g->lu, g->piv, n, g->ainv);
-  TPF_LAUNCH_CHECK();
+  {
+    const int nb = (n + 63) / 64;
+    if (nb <= 4)
+      k_lu_inverse<4><<<n, 64, 0, s>>>(g->lu, g->piv, n, g->ainv);
+    else if (nb <= 16)
+      k_lu_inverse<16><<<n, 64, 0, s>>>(g->lu, g->piv, n, g->ainv);
+    else  // more row blocks than registers comfortably hold
+      k_lu_inverse_cols<<<n, 64, (size_t)n * sizeof(double), s>>>(g->lu, g->piv, n, g->ainv);
+    TPF_LAUNCH_CHECK();
+  }
   prof_end(g, pl, s);
   return TPF_OK;
 }
