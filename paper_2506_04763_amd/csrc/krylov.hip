@@ -62,21 +62,28 @@ __global__ void __launch_bounds__(BS) k_init(long long n, const double *__restri
 }
 
 // p = r (first) or p = r + beta (p - omega v)
+// (b32: the FP32 copy of the result for a mixed-precision V-cycle, or null)
 __global__ void __launch_bounds__(BS) k_update_p(long long n, const double *__restrict__ r,
                                                  const double *__restrict__ v, double *__restrict__ p,
-                                                 const double *__restrict__ sc, int first) {
+                                                 const double *__restrict__ sc, int first, float *__restrict__ b32) {
   const double beta = sc[S_BETA], omega = sc[S_OMEGA];
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-    p[i] = first ? r[i] : r[i] + beta * (p[i] - omega * v[i]);
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const double pi = first ? r[i] : r[i] + beta * (p[i] - omega * v[i]);
+    p[i] = pi;
+    if (b32) b32[i] = (float)pi;
+  }
 }
 
 // s = r - alpha v
 __global__ void __launch_bounds__(BS) k_update_s(long long n, const double *__restrict__ r,
                                                  const double *__restrict__ v, double *__restrict__ s,
-                                                 const double *__restrict__ sc) {
+                                                 const double *__restrict__ sc, float *__restrict__ b32) {
   const double alpha = sc[S_ALPHA];
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-    s[i] = r[i] - alpha * v[i];
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const double si = r[i] - alpha * v[i];
+    s[i] = si;
+    if (b32) b32[i] = (float)si;
+  }
 }
 
 // x += alpha ph + omega sh; r = s - omega t; partials (r, r), (rh, r)
@@ -201,6 +208,9 @@ tpf_status bicgstab(tpf_grid *g, const double *f, double *x, double rtol, int ma
   const long long n = 2 * g->P.N;
   double *part = g->part;
   unsigned nb = 0;
+  // mixed precision: the p and s updates also write the FP32 right-hand side of the
+  // V-cycle that follows them, which then needs no cast pass of its own
+  float *b32 = g->prec != TPF_FP64 ? static_cast<float *>(g->lv[0].b) : nullptr;
   k_init<<<RED_BLOCKS, BS, 0, s>>>(n, f, g->r, g->rh, x, part);
   TPF_LAUNCH_CHECK();
   k_finalize<1><<<1, 1024, 0, s>>>(part, RED_BLOCKS, g->scal, F_INIT);
@@ -224,16 +234,16 @@ tpf_status bicgstab(tpf_grid *g, const double *f, double *x, double rtol, int ma
   tpf_status result = TPF_NOT_CONVERGED;
   while (it < maxit) {
     ++it;
-    k_update_p<<<RED_BLOCKS, BS, 0, s>>>(n, g->r, g->v, g->p, g->scal, first);
+    k_update_p<<<RED_BLOCKS, BS, 0, s>>>(n, g->r, g->v, g->p, g->scal, first, b32);
     TPF_LAUNCH_CHECK();
     first = 0;
-    TPF_TRY(vcycle(g, g->p, g->ph, s));
+    TPF_TRY(vcycle(g, g->p, g->ph, s, b32 != nullptr));
     TPF_TRY(spmv64_mode(g, 1, g->ph, g->v, g->rh, part, &nb, s));
     k_finalize<1><<<1, 1024, 0, s>>>(part, nb, g->scal, F_ALPHA);
     TPF_LAUNCH_CHECK();
-    k_update_s<<<RED_BLOCKS, BS, 0, s>>>(n, g->r, g->v, g->s, g->scal);
+    k_update_s<<<RED_BLOCKS, BS, 0, s>>>(n, g->r, g->v, g->s, g->scal, b32);
     TPF_LAUNCH_CHECK();
-    TPF_TRY(vcycle(g, g->s, g->sh, s));
+    TPF_TRY(vcycle(g, g->s, g->sh, s, b32 != nullptr));
     TPF_TRY(spmv64_mode(g, 2, g->sh, g->t, g->s, part, &nb, s));
     k_finalize<2><<<1, 1024, 0, s>>>(part, nb, g->scal, F_OMEGA);
     TPF_LAUNCH_CHECK();

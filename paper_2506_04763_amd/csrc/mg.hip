@@ -979,15 +979,17 @@ bool resid16(tpf_grid *g, int l, const T *b, const T *x, T *r, hipStream_t s) {
 constexpr long long LAT_NMAX = 65536;
 
 template <int DIM, typename T>
-tpf_status vcycle_t(tpf_grid *g, const double *bin, double *xout, hipStream_t s) {
+tpf_status vcycle_t(tpf_grid *g, const double *bin, double *xout, hipStream_t s, bool staged) {
   const int L = g->L;
   const T om = (T)g->omega;
   const T *b0;
   if (sizeof(T) == sizeof(double)) {
     b0 = reinterpret_cast<const T *>(bin);
   } else {
-    k_cast<double, T><<<1024, BS, 0, s>>>(bin, reinterpret_cast<T *>(g->lv[0].b), 2 * g->lv[0].N);
-    TPF_LAUNCH_CHECK();
+    if (!staged) {  // else the caller has written (T)bin to the level-0 right-hand side
+      k_cast<double, T><<<1024, BS, 0, s>>>(bin, reinterpret_cast<T *>(g->lv[0].b), 2 * g->lv[0].N);
+      TPF_LAUNCH_CHECK();
+    }
     b0 = reinterpret_cast<const T *>(g->lv[0].b);
   }
   auto A_of = [&](int l) -> const T * {
@@ -1203,10 +1205,10 @@ tpf_status build_hierarchy(tpf_grid *g, hipStream_t s) {
   return g->dim == 3 ? hierarchy_t<3>(g, s) : hierarchy_t<2>(g, s);
 }
 
-tpf_status vcycle(tpf_grid *g, const double *b, double *x, hipStream_t s) {
+tpf_status vcycle(tpf_grid *g, const double *b, double *x, hipStream_t s, bool staged) {
   if (g->prec != TPF_FP64)
-    return g->dim == 3 ? vcycle_t<3, float>(g, b, x, s) : vcycle_t<2, float>(g, b, x, s);
-  return g->dim == 3 ? vcycle_t<3, double>(g, b, x, s) : vcycle_t<2, double>(g, b, x, s);
+    return g->dim == 3 ? vcycle_t<3, float>(g, b, x, s, staged) : vcycle_t<2, float>(g, b, x, s, staged);
+  return g->dim == 3 ? vcycle_t<3, double>(g, b, x, s, staged) : vcycle_t<2, double>(g, b, x, s, staged);
 }
 
 tpf_status spmv64(tpf_grid *g, int level, const double *x, double *y, hipStream_t s) {

@@ -195,7 +195,8 @@ tpf_status build_hierarchy(tpf_grid *g, hipStream_t s);
 tpf_status untile_matrix32(tpf_grid *g, float *dst, hipStream_t s);
 // A coarse level's FP16 matrix as floats (entries times row scales), [offset][vertex][4].
 tpf_status expand_matrix16(tpf_grid *g, int level, float *dst, hipStream_t s);
-tpf_status vcycle(tpf_grid *g, const double *b, double *x, hipStream_t s);
+// staged: (mixed precision) the FP32 copy of b is already in the level-0 right-hand side
+tpf_status vcycle(tpf_grid *g, const double *b, double *x, hipStream_t s, bool staged = false);
 // y = A x (FP64, level l); if dot_with != null also block partials of (dot_with, y)
 // and, if second != null, (second, y) and (y, y) as selected by mode.
 tpf_status spmv64(tpf_grid *g, int level, const double *x, double *y, hipStream_t s);
