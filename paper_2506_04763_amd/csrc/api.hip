@@ -304,7 +304,15 @@ tpf_status tpf_create_grid(const tpf_grid_desc *d, void *arena, size_t arena_byt
     delete g;
     return TPF_EDEVICE;
   }
+  he = hipEventCreateWithFlags(&g->scal_ev, hipEventDisableTiming);
+  if (he != hipSuccess) {
+    set_error("hipEventCreate failed: %s", hipGetErrorString(he));
+    (void)hipHostFree(g->hscal);
+    delete g;
+    return TPF_EDEVICE;
+  }
   auto fail = [&](tpf_status e) {
+    (void)hipEventDestroy(g->scal_ev);
     (void)hipHostFree(g->hscal);
     delete g;
     return e;
@@ -358,6 +366,7 @@ static void prof_release(tpf_grid *g);
 void tpf_destroy_grid(tpf_grid *g) {
   if (!g) return;
   prof_release(g);
+  if (g->scal_ev) (void)hipEventDestroy(g->scal_ev);
   if (g->hscal) (void)hipHostFree(g->hscal);
   delete g;
 }

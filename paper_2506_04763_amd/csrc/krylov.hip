@@ -230,12 +230,16 @@ tpf_status bicgstab(tpf_grid *g, const double *f, double *x, double rtol, int ma
   const double thr2 = rtol * rtol * ff;
   int first = 1, it = 0, restarts = 0;
   bool breakdown_restart_used = false;
+  bool p_ready = false;  // this iteration's p update was enqueued during the last readback
   double rr = ff;
   tpf_status result = TPF_NOT_CONVERGED;
   while (it < maxit) {
     ++it;
-    k_update_p<<<RED_BLOCKS, BS, 0, s>>>(n, g->r, g->v, g->p, g->scal, first, b32);
-    TPF_LAUNCH_CHECK();
+    if (!p_ready) {
+      k_update_p<<<RED_BLOCKS, BS, 0, s>>>(n, g->r, g->v, g->p, g->scal, first, b32);
+      TPF_LAUNCH_CHECK();
+    }
+    p_ready = false;
     first = 0;
     TPF_TRY(vcycle(g, g->p, g->ph, s, b32 != nullptr));
     TPF_TRY(spmv64_mode(g, 1, g->ph, g->v, g->rh, part, &nb, s));
@@ -251,7 +255,17 @@ tpf_status bicgstab(tpf_grid *g, const double *f, double *x, double rtol, int ma
     TPF_LAUNCH_CHECK();
     k_finalize<2><<<1, 1024, 0, s>>>(part, RED_BLOCKS, g->scal, F_RHO);
     TPF_LAUNCH_CHECK();
-    TPF_TRY(read_scalars(g, s));
+    // Read the scalars back.  The next iteration's p update needs only the device-side
+    // beta and omega, so it is enqueued behind the copy and runs while the host waits
+    // for the copy alone; the restart paths below (first = 1) enqueue it again.
+    TPF_HIP(hipMemcpyAsync(g->hscal, g->scal, NSCAL * sizeof(double), hipMemcpyDeviceToHost, s));
+    TPF_HIP(hipEventRecord(g->scal_ev, s));
+    if (it < maxit) {
+      k_update_p<<<RED_BLOCKS, BS, 0, s>>>(n, g->r, g->v, g->p, g->scal, 0, b32);
+      TPF_LAUNCH_CHECK();
+      p_ready = true;
+    }
+    TPF_HIP(hipEventSynchronize(g->scal_ev));
     rr = g->hscal[S_RR];
     const double rho = g->hscal[S_RHO];
     if (!(rr == rr) || !(rho == rho)) {
@@ -278,6 +292,7 @@ tpf_status bicgstab(tpf_grid *g, const double *f, double *x, double rtol, int ma
       TPF_LAUNCH_CHECK();
       ++restarts;
       first = 1;
+      p_ready = false;
       continue;
     }
     if (rho == 0.0) {
@@ -293,6 +308,7 @@ tpf_status bicgstab(tpf_grid *g, const double *f, double *x, double rtol, int ma
       breakdown_restart_used = true;
       ++restarts;
       first = 1;
+      p_ready = false;
     }
   }
   // final true residual (recomputed unless the exit path just did)

@@ -95,6 +95,7 @@ struct tpf_grid {
   double *u0, *f0, *fv, *T[tpf::MAXK], *Tp;
   // host side
   double *hscal;  // pinned, NSCAL doubles
+  hipEvent_t scal_ev;  // recorded after each per-iteration copy of the scalars to hscal
   bool assembled;
   bool has_f0;
   size_t bytes;
