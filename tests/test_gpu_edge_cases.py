@@ -2,7 +2,9 @@
 
   * grids of one or a few cells, and a one-level hierarchy (the preconditioner is
     then the dense LU solve of the whole system, so BiCGSTAB converges at once);
-  * the largest coarsest level the dense solve takes (4096 unknowns, a 64 x 32 grid);
+  * one-level grids of 578 and 686 unknowns (the dense inverse's register kernel with
+    up to 16 row blocks) and the largest coarsest level the dense solve takes (4096
+    unknowns, a 64 x 32 grid);
   * a grid whose every vertex is Dirichlet (A = I, F = 0) and a zero right-hand side;
   * a stage step so long (1e12 s) that the storage part all but vanishes.
 """
@@ -127,3 +129,19 @@ def test_very_long_stage_step():
         Ar = ref.H.A[l]
         assert abs(Ag - Ar).max() <= 1e-11 * abs(Ar).max(), l
     g.close()
+
+
+@pytest.mark.parametrize("name,make", [
+    ("2d_17x17", lambda: W.lens_2d(17, 17)),  # 578 unknowns
+    ("3d_7", lambda: W.small_cube(7, seed=43)),  # 686 unknowns
+])
+def test_dense_inverse_of_hundreds_of_unknowns(name, make):
+    """One level of 257-1024 unknowns: the dense inverse is formed with the column in
+    registers, 64-row blocks (up to 16 of them); the solve is then exact."""
+    scn = make()
+    scn.levels = 1
+    assert 256 < 2 * scn.nverts <= 1024
+    print(f"[edge] {name} n={2 * scn.nverts}", flush=True)
+    u = W.perturbed_state(scn, 9, sn_lo=0.05, sn_hi=0.5)
+    st = parity(scn, u, 32.0)
+    assert st["status"] == "TPF_OK" and st["iters"] <= 2
