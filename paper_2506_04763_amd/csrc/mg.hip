@@ -461,17 +461,31 @@ __global__ void __launch_bounds__(BS) k_restrict(const Geo F, const Geo C, const
 // Restriction followed by the coarse level's first sweep from a zero guess,
 // xc = 0 + omega D_c^{-1} bc, which needs only the vertex's own restricted value and
 // centre block: one launch instead of two on every level that is smoothed.  The
-// arithmetic is that of the separate first sweep, so the results are identical.
+// arithmetic is that of the separate first sweep, so the results are identical.  On
+// the small levels the finest level's streams have evicted the level's matrix from
+// L2 since the last cycle; the kernel loads each vertex's whole row alongside its
+// centre block (one cold round trip for both), with the sweeps' vertex-to-XCD mapping,
+// so that the next, full sweep finds it in the same L2.
 template <int DIM, typename T>
 __global__ void __launch_bounds__(BS) k_restrict_first(const Geo F, const Geo C, const T *__restrict__ rf,
                                                        const uint8_t *__restrict__ fmask, const T vr,
                                                        T *__restrict__ bc, const T *__restrict__ Ac,
                                                        T *__restrict__ xc, const T omega) {
-  const long long I = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const unsigned blk = xcd_block(blockIdx.x, gridDim.x);  // the sweeps' vertex-to-XCD mapping
+  const long long I = (long long)blk * blockDim.x + threadIdx.x;
   if (I >= C.N) return;
   constexpr int CEN = DIM == 3 ? 13 : 4;
+  constexpr int NST = DIM == 3 ? 27 : 9;
   T d[4];
   Blk<T>::load(Ac + ((long long)CEN * C.N + I) * 4, d);
+  T touch = 0;
+  if (C.N <= 65536) {  // small level: bring the whole row into this XCD's L2 for the next sweep
+    T q[NST][4];
+#pragma unroll
+    for (int o = 0; o < NST; ++o) Blk<T>::load(Ac + ((long long)o * C.N + I) * 4, q[o]);
+#pragma unroll
+    for (int o = 0; o < NST; ++o) touch += q[o][0];
+  }
   const auto o = restrict_vertex<DIM, T>(I, F, C, rf, fmask, vr, bc);
   T z0, z1;
   solve2<T>(d, o.x, o.y, z0, z1);
@@ -479,6 +493,7 @@ __global__ void __launch_bounds__(BS) k_restrict_first(const Geo F, const Geo C,
   typename Vec2<T>::type out;
   out.x = x0 + omega * z0;
   out.y = x1 + omega * z1;
+  if (omega < (T)0) out.x += touch;  // never true: keeps the row loads
   *reinterpret_cast<typename Vec2<T>::type *>(xc + 2 * I) = out;
 }
 
