@@ -200,6 +200,13 @@ class FV:
         self.mref = mref
         self.lam_ref = self.lam[mref]
 
+    def vertex_pc(self, u):
+        """Vertex capillary pressure P_i = p_dmin,i J_m(i)(S_i) in the reference medium
+        m(i) (the p_c that the interface condition of Eq. hSw compares with), so that
+        p_n,i = p_w,i + P_i at every vertex.  u: (N, 2)."""
+        se = eff_sat(u[:, 1], self.swr, self.snr)
+        return self.pdmin * se ** (-1.0 / self.lam_ref)
+
     # -- Neumann sources: exact overlap of the dual-box face with each patch -------
     def neumann_sources(self):
         scn = self.scn

@@ -6,13 +6,16 @@ Paper passages followed:
     (M(u_old) - tau J(u_old)) (u_new - u_old) = tau F(u_old), J = F_u exact;
   * step-size rule tau_new = (rho TOL / [[eps]])^(1/(q+1)) tau_old with q = 2;
   * error estimate [[eps]] = relative error in the scaled norm
-    |||u|||^2 = alpha ||grad p||^2 + beta ||S_w||^2 (Eq. norm_u).
+    |||u|||^2 = alpha ||grad p_n||^2 + beta ||S_w||^2 (Eq. norm_u), the H1-seminorm of
+    the non-wetting pressure and the L2 norm of the wetting saturation.
 Readings: harmonic stage sequence n_j = j, stage j takes j
 substeps of H/j with M and J frozen at the step's initial state and F re-evaluated at
 every substep; Aitken-Neville extrapolation
   T_{j,l+1} = T_{j,l} + (T_{j,l} - T_{j-1,l}) / (n_j / n_{j-l} - 1);
-eps = |||T_kk - T_{k,k-1}||| / |||T_kk||| with alpha = 1/(2 ||grad p_w(T_kk)||^2),
-beta = 1/(2 ||S_w(T_kk)||^2), so eps^2 = (e_p^2 + e_S^2)/2; accept iff eps <= TOL;
+eps = |||T_kk - T_{k,k-1}||| / |||T_kk||| with alpha = 1/(2 ||grad p_n(T_kk)||^2),
+beta = 1/(2 ||S_w(T_kk)||^2), so eps^2 = (e_p^2 + e_S^2)/2; p_n at a vertex is
+p_w + P_i, P_i the capillary pressure of the vertex's reference medium (the one the
+interface condition compares with); accept iff eps <= TOL;
 tau_new = min(tau_max, H (rho TOL / eps)^(1/3)).
 """
 from __future__ import annotations
@@ -107,12 +110,19 @@ class Norms:
     def sat_sq(self, sw):
         return float(np.sum(self.dual * sw * sw))
 
+    def pn(self, u):
+        """Non-wetting pressure p_n = p_w + P_i at every vertex of the state u (N, 2)."""
+        return u[:, 0] + self.fv.vertex_pc(u)
+
     def err_ratio(self, kk, km):
+        """[[eps]] of Eq. norm_u between T_kk and T_{k,k-1} (flat or (N, 2) states):
+        sqrt((||grad dp_n||^2 / ||grad p_n(kk)||^2 + ||dS_w||^2 / ||S_w(kk)||^2) / 2)."""
         kk = kk.reshape(-1, 2)
         km = km.reshape(-1, 2)
-        dp = kk[:, 0] - km[:, 0]
+        pn_kk = self.pn(kk)
+        dp = pn_kk - self.pn(km)
         ds = -(kk[:, 1] - km[:, 1])
-        gp = max(self.grad_sq(kk[:, 0]), 1e-300)
+        gp = max(self.grad_sq(pn_kk), 1e-300)
         gs = max(self.sat_sq(1.0 - kk[:, 1]), 1e-300)
         e2 = 0.5 * (self.grad_sq(dp) / gp + self.sat_sq(ds) / gs)
         return float(np.sqrt(e2))

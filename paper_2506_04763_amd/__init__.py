@@ -234,6 +234,15 @@ class Grid:
         L.check(self.lib.tpf_precondition(self.handle, _ptr(b), _ptr(x), self._sptr()), "tpf_precondition")
         return x
 
+    def pdmin(self):
+        """p_dmin per vertex (Eq. pdmin): a float64 view of the arena at the address
+        tpf_pdmin_ptr reports."""
+        ptr = self.lib.tpf_pdmin_ptr(self.handle)
+        off = int(ptr) - self.arena.data_ptr()
+        if ptr is None or off < 0 or off % 8 or off + 8 * self.N > self.nbytes:
+            raise RuntimeError("tpf_pdmin_ptr is outside the grid's arena")
+        return self.arena[off:off + 8 * self.N].view(self.torch.float64)
+
     def coarse_inverse(self):
         n = self.level_dims(self.levels - 1)
         nc = 2 * n[0] * n[1] * n[2]

@@ -232,6 +232,7 @@ tpf_status bicgstab(tpf_grid *g, const double *f, double *x, double rtol, int ma
   bool breakdown_restart_used = false;
   bool p_ready = false;  // this iteration's p update was enqueued during the last readback
   double rr = ff;
+  bool true_fresh = false;  // S_WW holds the true residual of the final x
   tpf_status result = TPF_NOT_CONVERGED;
   while (it < maxit) {
     ++it;
@@ -282,6 +283,7 @@ tpf_status bicgstab(tpf_grid *g, const double *f, double *x, double rtol, int ma
       const double ww = g->hscal[S_WW];
       if (ww <= thr2 || restarts >= 2) {
         result = ww <= thr2 ? TPF_OK : TPF_NOT_CONVERGED;
+        true_fresh = true;
         break;
       }
       // the recursive residual drifted: restart from the true residual
@@ -311,11 +313,13 @@ tpf_status bicgstab(tpf_grid *g, const double *f, double *x, double rtol, int ma
       p_ready = false;
     }
   }
-  // final true residual (recomputed unless the exit path just did)
-  TPF_TRY(spmv64_mode(g, 3, x, g->w, f, part, &nb, s));
-  k_finalize<1><<<1, 1024, 0, s>>>(part, nb, g->scal, F_TRUE);
-  TPF_LAUNCH_CHECK();
-  TPF_TRY(read_scalars(g, s));
+  // final true residual, unless the convergence check has just computed it for this x
+  if (!true_fresh) {
+    TPF_TRY(spmv64_mode(g, 3, x, g->w, f, part, &nb, s));
+    k_finalize<1><<<1, 1024, 0, s>>>(part, nb, g->scal, F_TRUE);
+    TPF_LAUNCH_CHECK();
+    TPF_TRY(read_scalars(g, s));
+  }
   local.iters = it;
   local.restarts = restarts;
   local.rel_res = sqrt(rr / ff);

@@ -189,6 +189,8 @@ tpf_status setup_vertices(tpf_grid *g, const Patches &pt, hipStream_t s);
 tpf_status launch_residual(tpf_grid *g, const double *u, double *f, hipStream_t s);
 tpf_status launch_assemble(tpf_grid *g, const double *u0, double h, double *f0, hipStream_t s);
 tpf_status launch_apply_dirichlet(tpf_grid *g, double *u, hipStream_t s);
+// p_n = p_w + P_i of the states a and b: out[0, N) from a, out[N, 2N) from b
+tpf_status launch_pn2(tpf_grid *g, const double *a, const double *b, double *out, hipStream_t s);
 
 // ---- launchers (mg.hip) ----
 tpf_status build_hierarchy(tpf_grid *g, hipStream_t s);

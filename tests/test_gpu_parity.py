@@ -240,3 +240,48 @@ def test_corner_pass_rows_equal_inline_rows(case):
         g.close()
     for a, b in zip(out[0], out[1]):
         np.testing.assert_array_equal(a, b)
+
+
+def test_pdmin_parity(case):
+    """p_dmin per vertex (Eq. pdmin) as the library stores it, against the oracle: a
+    minimum of stored entry pressures, so bit for bit."""
+    g = tpf.Grid(case["scn"], precision="fp64")
+    pdm = g.pdmin().cpu().numpy()
+    g.close()
+    np.testing.assert_array_equal(pdm, case["ref"].fv.pdmin)
+
+
+def _two_media(dim):
+    """The hand-worked two-medium grids of the oracle pins (equal entry pressures of
+    cells with different lambda meet at some vertices)."""
+    if dim == 2:
+        n, ext = (4, 3, 1), (3.0, 2.0, 1.0)
+        pd = [800.0, 800.0, 1500.0, 1500.0, 2000.0, 1200.0]
+        lam = [2.5, 2.0, 2.0, 2.0, 3.0, 1.5]
+    else:
+        n, ext = (3, 3, 3), (1.0, 1.0, 1.0)
+        pd = [900.0, 700.0, 700.0, 1000.0, 1100.0, 650.0, 600.0, 1300.0]
+        lam = [2.0, 2.0, 3.0, 2.0, 2.0, 4.0, 1.5, 2.0]
+    scn = W._empty(f"two_media_{dim}d", dim, n, ext, (0.0, -9.81, 0.0) if dim == 2 else (0.0, 0.0, -9.81))
+    nc = scn.ncells
+    scn.perm = np.full(nc, 1e-11)
+    scn.poro = np.full(nc, 0.3)
+    scn.entry_p = np.array(pd)
+    scn.bc_lambda = np.array(lam)
+    scn.levels = 1
+    return scn
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_reference_medium_tie_parity(dim):
+    """On the two-medium grids the residual at a perturbed state depends on which
+    cell is the reference medium at the tie vertices (lambda enters P_i): the GPU's
+    p_dmin and residual against the oracle's."""
+    scn = _two_media(dim)
+    u = W.perturbed_state(scn, 9, dp=30.0, sn_lo=0.05, sn_hi=0.5)
+    ref = ST.Stage(scn)
+    g = tpf.Grid(scn, precision="fp64")
+    np.testing.assert_array_equal(g.pdmin().cpu().numpy(), ref.fv.pdmin)
+    f = g.residual(torch.as_tensor(u.ravel(), device="cuda")).cpu().numpy()
+    g.close()
+    assert per_field(f, ref.residual(u.ravel())) < 1e-12

@@ -41,7 +41,7 @@ def test_launch_counts_follow_the_solver(cube):
         "assemble": 1,
         "rap": scn.levels - 1,
         "coarse_lu": 1,
-        "spmv64": 2 * it + 2,  # two per iteration, the confirmation and the final true residual
+        "spmv64": 2 * it + 1,  # two per iteration and the true residual that confirms convergence
         "smooth0": 3 * cyc,  # second pre-sweep and both post-sweeps of V(2,2)
         "smooth0_first": cyc,
         "resid0": cyc,

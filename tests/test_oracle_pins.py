@@ -589,3 +589,112 @@ def test_vcycle_is_a_contraction_on_a_heterogeneous_cube():
         res.append(np.linalg.norm(b - A @ x) / np.linalg.norm(b))
     assert all(res[i + 1] < res[i] for i in range(5))
     assert res[-1] < 1e-7
+
+
+# ---------------------------------------------------------------------------------
+# p_dmin and the reference medium (Section 3.3, Eq. pdmin), worked out by hand.
+# ---------------------------------------------------------------------------------
+def test_pdmin_and_reference_medium_by_hand_2d():
+    """A 4 x 3-vertex grid of 3 x 2 cells (cell c = cx + 3 cy) with two media meeting
+    at an equal entry pressure.  Expected p_dmin,i and m(i) for every vertex are written
+    out from the cells around it (lowest cell index on a tie, reading R4): corner,
+    edge and interior vertices, the lens-like high-p_d cells and the tie between
+    cells 0 (lambda 2.5) and 1 (lambda 2.0)."""
+    pd = [800.0, 800.0, 1500.0, 1500.0, 2000.0, 1200.0]
+    lam = [2.5, 2.0, 2.0, 2.0, 3.0, 1.5]
+    scn = make_scn(2, (4, 3, 1), (3.0, 2.0, 1.0), pd=pd, lam=lam)
+    f = FV.FV(scn)
+    # vertex v = ix + 4 iy: its cells, their minimum and the lowest minimiser
+    want_pdmin = [800, 800, 800, 1500,    # iy = 0: {c0} {c0,c1} {c1,c2} {c2}
+                  800, 800, 800, 1200,    # iy = 1: {c0,c3} {c0,c1,c3,c4} {c1,c2,c4,c5} {c2,c5}
+                  1500, 1500, 1200, 1200]  # iy = 2: {c3} {c3,c4} {c4,c5} {c5}
+    want_mref = [0, 0, 1, 2,
+                 0, 0, 1, 5,
+                 3, 3, 5, 5]
+    np.testing.assert_array_equal(f.pdmin, np.array(want_pdmin, float))
+    np.testing.assert_array_equal(f.mref, np.array(want_mref))
+    np.testing.assert_array_equal(f.lam_ref, np.array(lam)[want_mref])
+    # the tie at vertex 1 and 5 resolves to lambda 2.5 (cell 0), not 2.0 (cell 1)
+    assert f.lam_ref[1] == 2.5 and f.lam_ref[5] == 2.5
+
+
+def test_pdmin_and_reference_medium_by_hand_3d():
+    """A 3^3-vertex grid of 2^3 cells (c = cx + 2 cy + 4 cz).  Vertices on each face
+    centre, edge and the centre touch different cell sets, so a slip in the
+    vertex-to-cell mapping of any axis moves one of these minima."""
+    pd = [900.0, 700.0, 700.0, 1000.0, 1100.0, 650.0, 600.0, 1300.0]
+    lam = [2.0, 2.0, 3.0, 2.0, 2.0, 4.0, 1.5, 2.0]
+    scn = make_scn(3, (3, 3, 3), (1.0, 1.0, 1.0), pd=pd, lam=lam)
+    f = FV.FV(scn)
+
+    def v(ix, iy, iz):
+        return ix + 3 * (iy + 3 * iz)
+    cases = {  # vertex: (p_dmin, m) from the cells touching it
+        (0, 0, 0): (900, 0),     # {c0}
+        (2, 2, 2): (1300, 7),    # {c7}
+        (1, 0, 0): (700, 1),     # {c0, c1}
+        (1, 1, 0): (700, 1),     # {c0..c3}: tie c1 (lambda 2) / c2 (lambda 3) -> c1
+        (1, 1, 1): (600, 6),     # all eight
+        (0, 1, 1): (600, 6),     # x face: {c0, c2, c4, c6}
+        (2, 1, 1): (650, 5),     # x face: {c1, c3, c5, c7}
+        (1, 0, 1): (650, 5),     # y face: {c0, c1, c4, c5}
+        (1, 2, 1): (600, 6),     # y face: {c2, c3, c6, c7}
+        (1, 1, 2): (600, 6),     # z face: {c4..c7}
+        (0, 0, 1): (900, 0),     # z edge: {c0, c4}
+        (0, 1, 0): (700, 2),     # y edge: {c0, c2}
+        (2, 0, 1): (650, 5),     # z edge: {c1, c5}
+    }
+    for (ix, iy, iz), (pdm, m) in cases.items():
+        i = v(ix, iy, iz)
+        assert f.pdmin[i] == pdm and f.mref[i] == m and f.lam_ref[i] == lam[m], ((ix, iy, iz), f.pdmin[i], f.mref[i])
+
+
+# ---------------------------------------------------------------------------------
+# The LIMEX error estimate (Section 4, Eq. norm_u), on states with closed forms.
+# ---------------------------------------------------------------------------------
+def test_error_estimate_closed_form_constant_saturation():
+    """Linear pressures and spatially constant saturations: the Q1 interpolant of a
+    linear function is exact, so ||grad p||^2 = |grad p|^2 |Omega| and the lumped
+    ||S||^2 = S^2 |Omega| (the dual boxes tile Omega).  With p_c = 0 (p_d = 0) p_n = p_w,
+    so eps = sqrt((|grad dp|^2 / |grad p|^2 + dS_w^2 / S_w^2) / 2) exactly.  A missing
+    1/2, S_n in place of S_w (0.3 against 0.7) or a swapped normalisation fails."""
+    scn = make_scn(3, (5, 4, 6), (1.0, 0.5, 2.0), pd=0.0)
+    vol = 1.0 * 0.5 * 2.0
+    x, y, z = scn.vertex_coords()
+    nm = LX.Norms(FV.FV(scn))
+    a = np.array([3.0e3, -1.0e3, 2.0e2])      # grad p_w of T_kk
+    b = np.array([3.1e3, -0.9e3, 2.0e2])      # grad p_w of T_k,k-1
+    kk = np.stack([a[0] * x + a[1] * y + a[2] * z + 1e5, np.full_like(x, 0.3)], axis=1)
+    km = np.stack([b[0] * x + b[1] * y + b[2] * z + 1e5, np.full_like(x, 0.32)], axis=1)
+    e_p2 = np.sum((a - b) ** 2) * vol / (np.sum(a ** 2) * vol)
+    e_s2 = (0.02 ** 2 * vol) / (0.7 ** 2 * vol)
+    assert nm.err_ratio(kk, km) == pytest.approx(np.sqrt(0.5 * (e_p2 + e_s2)), rel=1e-12)
+    # the two halves separately: equal saturations, then equal pressures
+    km_p = km.copy(); km_p[:, 1] = 0.3
+    assert nm.err_ratio(kk, km_p) == pytest.approx(np.sqrt(0.5 * e_p2), rel=1e-12)
+    km_s = km.copy(); km_s[:, 0] = kk[:, 0]
+    assert nm.err_ratio(kk, km_s) == pytest.approx(np.sqrt(0.5 * e_s2), rel=1e-12)
+
+
+def test_error_estimate_uses_the_non_wetting_pressure():
+    """Eq. norm_u measures grad p_n.  A homogeneous medium (p_d 1000 Pa, lambda 2) whose
+    saturation is chosen per vertex so that p_c = p_d S_e^(-1/lambda) = 1500 + 750 x is
+    linear: p_n = p_w + p_c is then linear too and its Q1 interpolant exact.  With the
+    same saturation in both states only the pressure term is left:
+    eps = sqrt(1/2) |grad dp_w| / |grad p_w + grad p_c|, whereas a p_w norm would give
+    sqrt(1/2) |grad dp_w| / |grad p_w|."""
+    scn = make_scn(2, (9, 5, 1), (2.0, 1.0, 1.0), pd=1000.0, lam=2.0, s_res=(0.1, 0.05))
+    x, y, _ = scn.vertex_coords()
+    pc = 1500.0 + 750.0 * x                        # 1500 ... 3000 Pa
+    se = (pc / 1000.0) ** (-2.0)                   # S_e in (0.11, 0.44): no clamp
+    sn = 1.0 - (0.1 + se * (1.0 - 0.1 - 0.05))
+    nm = LX.Norms(FV.FV(scn))
+    np.testing.assert_allclose(nm.fv.vertex_pc(np.stack([0 * x, sn], axis=1)), pc, rtol=1e-13)
+    gw = np.array([-100.0, 50.0])
+    dg = np.array([5.0, -2.0])
+    kk = np.stack([2e5 + gw[0] * x + gw[1] * y, sn], axis=1)
+    km = np.stack([2e5 + (gw[0] - dg[0]) * x + (gw[1] - dg[1]) * y, sn], axis=1)
+    gn = gw + np.array([750.0, 0.0])
+    want = np.sqrt(0.5 * np.sum(dg ** 2) / np.sum(gn ** 2))
+    assert nm.err_ratio(kk, km) == pytest.approx(want, rel=1e-12)
+    assert abs(nm.err_ratio(kk, km) / (np.sqrt(0.5 * np.sum(dg ** 2) / np.sum(gw ** 2))) - 1) > 0.5
