@@ -21,7 +21,9 @@
  *                     (the linear solver named in Section 1 and Section 5);
  *   - limex_step:     one adaptive LIMEX step (Section 4: linearly implicit
  *                     extrapolation, error estimate in the scaled norm Eq. norm_u,
- *                     step-size rule with q = 2).
+ *                     step-size rule with q = 2);
+ *   - ie_step:        one fixed implicit Euler step with Newton's method, the
+ *                     scheme Section 5 compares LIMEX with.
  *
  * Conventions
  *   - Device pointers are HIP device addresses owned by the caller (e.g. from a
@@ -157,6 +159,27 @@ typedef struct tpf_limex_stats {
   double dt_next;        /* proposed next step                                   */
 } tpf_limex_stats;
 
+typedef struct tpf_newton_opts {
+  int32_t max_newton;    /* Newton iterations per step (>= 1)                     */
+  int32_t max_halvings;  /* consecutive halvings of a Newton step (>= 0)          */
+  int32_t maxit;         /* BiCGSTAB iteration cap per linear solve (>= 1)        */
+  int32_t reserved;      /* 0                                                     */
+  double atol;           /* absolute defect tolerance, kg (>= 0)                  */
+  double rtol;           /* defect tolerance relative to the step's first (>= 0)  */
+  double lin_rtol;       /* relative residual of every linear solve (> 0)         */
+} tpf_newton_opts;
+
+typedef struct tpf_newton_stats {
+  int32_t converged;     /* 1: the defect met atol or rtol                        */
+  int32_t newton;        /* Newton iterations (accepted steps of the iteration)   */
+  int32_t halvings;      /* step halvings of the backtracking                     */
+  int32_t linear_solves; /* BiCGSTAB solves                                       */
+  int32_t linear_iters;  /* BiCGSTAB iterations summed over the solves            */
+  int32_t reserved;
+  double defect0;        /* ||G(u_old)|| = tau ||F(u_old)|| (kg)                   */
+  double defect;         /* ||G|| at exit                                         */
+} tpf_newton_stats;
+
 /* Message of the calling thread's last hard error ("" if none).  The pointer stays
  * valid until the next library call on the same thread. */
 const char *tpf_last_error(void);
@@ -199,6 +222,16 @@ tpf_status tpf_residual(tpf_grid *g, const double *u, double *f, tpf_stream stre
  * substep of a stage). */
 tpf_status tpf_assemble_stage(tpf_grid *g, const double *u0, double h, double *f0_out, tpf_stream stream);
 
+/* Moves the assembled stage operator to another step h > 0 without re-assembling:
+ * A = M(u0)/h - J(u0) with M and J still those of the last tpf_assemble_stage (the
+ * linearly implicit stages of Section 4 freeze both at the step's initial state and
+ * differ only in their step H/j).  The flux part of every multigrid level is
+ * independent of h and its storage part proportional to 1/h, so each level's storage
+ * diagonal is rescaled (the FP32/FP16 copies follow) and the coarsest level is
+ * refactored; F(u0) is unchanged.  Equal to a fresh tpf_assemble_stage(u0, h) up to
+ * rounding.  Returns TPF_OK, TPF_EINVAL or TPF_ESTATE (nothing assembled). */
+tpf_status tpf_rescale_stage(tpf_grid *g, double h, tpf_stream stream);
+
 /* Solves A x = f (A from the last assemble_stage) with right-preconditioned
  * BiCGSTAB, x0 = 0, one V(nu_pre, nu_post) cycle as preconditioner, until
  * ||r|| <= rtol ||f||.  f, x: device double[2N], may not alias.  Synchronises the
@@ -223,6 +256,31 @@ tpf_status tpf_solve_stage(tpf_grid *g, const double *f, double *x, double rtol,
  * Returns TPF_OK, TPF_STEP_REJECTED or an error. */
 tpf_status tpf_limex_step(tpf_grid *g, double *u, double *t, double *dt, const tpf_limex_opts *opts,
                           tpf_limex_stats *stats, tpf_stream stream);
+
+/* m = m(u): the storage of both phases in each control volume (kg), the sum over
+ * the vertex's sub-control volumes of porosity x density x saturation x volume with
+ * the saturation of the interface condition (Section 3.1, Eqs. dsW/dpN; M(u) of
+ * Section 4 is dm/du).  u, m: device double[2N] (m interleaved (w, n)); may not
+ * alias.  Dirichlet components are not cleared. */
+tpf_status tpf_storage(tpf_grid *g, const double *u, double *m, tpf_stream stream);
+
+/* One fixed implicit Euler step of size tau from the state u (device double[2N],
+ * in/out), the scheme Section 5 compares LIMEX with: Newton's method on
+ * G(u) = m(u) - m(u_old) - tau F(u) = 0 (conservative backward Euler of
+ * M(u) u' = F(u)), whose Jacobian is tau times the stage matrix A(u; h = tau) of
+ * tpf_assemble_stage.  Every Newton iteration assembles A and F at the iterate, builds
+ * the hierarchy and solves A delta = F(u) - (m(u) - m(u_old))/tau (Dirichlet rows 0)
+ * with BiCGSTAB + GMG to opts->lin_rtol.  The defect ||G|| (2-norm over the rows
+ * without a Dirichlet component, kg) starts at tau ||F(u_old)||; the step converges when
+ * it is <= opts->atol or <= opts->rtol times its initial value (the solver settings of
+ * Section 5 use 1e-8 and 1e-6).  A trial whose defect does not fall below its base's is
+ * halved, at most opts->max_halvings times in a row.  u must satisfy the Dirichlet
+ * values.  Leaves the last stage matrix assembled (at the final iterate).
+ * Returns TPF_OK (u advanced), TPF_NOT_CONVERGED (no convergence within
+ * opts->max_newton iterations, or a linear breakdown: u unchanged), or an error (u
+ * unchanged).  Synchronises the stream once per Newton iteration. */
+tpf_status tpf_ie_step(tpf_grid *g, double *u, double tau, const tpf_newton_opts *opts, tpf_newton_stats *stats,
+                       tpf_stream stream);
 
 /* ---- inspection hooks (used by the parity tests and the benchmark) ---------- */
 

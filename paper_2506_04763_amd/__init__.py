@@ -180,6 +180,10 @@ class Grid:
                 "tpf_assemble_stage")
         return f0_out
 
+    def rescale_stage(self, h):
+        """Moves the assembled stage operator (M, J frozen) and its hierarchy to the step h."""
+        L.check(self.lib.tpf_rescale_stage(self.handle, float(h), self._sptr()), "tpf_rescale_stage")
+
     def solve_stage(self, f, rtol=1e-10, maxit=500, out=None, raise_on_soft=False):
         f = self._vec(f)
         x = self.empty() if out is None else out
@@ -203,6 +207,25 @@ class Grid:
                                          self._sptr())
         L.check(status, "tpf_limex_step", soft_ok=True)
         return status == TPF_OK, tt.value, dd.value, st.as_dict()
+
+    def storage(self, u, out=None):
+        """m(u): the storage of both phases per control volume (kg), interleaved (w, n)."""
+        u = self._vec(u)
+        m = self.empty() if out is None else out
+        L.check(self.lib.tpf_storage(self.handle, _ptr(u), _ptr(m), self._sptr()), "tpf_storage")
+        return m
+
+    def ie_step(self, u, tau, atol=1e-8, rtol=1e-6, lin_rtol=1e-6, max_newton=30, max_halvings=8, maxit=500):
+        """One implicit Euler step with Newton in place on the device tensor u; returns
+        (converged, stats).  On failure u is unchanged."""
+        if not (isinstance(u, self.torch.Tensor) and u.device == self.device and u.dtype == self.torch.float64):
+            raise TypeError("u must be a float64 tensor on the grid's device")
+        o = L.NewtonOpts(int(max_newton), int(max_halvings), int(maxit), 0, float(atol), float(rtol),
+                         float(lin_rtol))
+        st = L.NewtonStats()
+        status = self.lib.tpf_ie_step(self.handle, _ptr(u), float(tau), C.byref(o), C.byref(st), self._sptr())
+        L.check(status, "tpf_ie_step", soft_ok=True)
+        return status == TPF_OK, st.as_dict()
 
     # -- inspection ------------------------------------------------------------------
     def level_dims(self, level):

@@ -65,6 +65,20 @@ class LimexStats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class NewtonOpts(C.Structure):
+    _fields_ = [("max_newton", C.c_int32), ("max_halvings", C.c_int32), ("maxit", C.c_int32),
+                ("reserved", C.c_int32), ("atol", C.c_double), ("rtol", C.c_double), ("lin_rtol", C.c_double)]
+
+
+class NewtonStats(C.Structure):
+    _fields_ = [("converged", C.c_int32), ("newton", C.c_int32), ("halvings", C.c_int32),
+                ("linear_solves", C.c_int32), ("linear_iters", C.c_int32), ("reserved", C.c_int32),
+                ("defect0", C.c_double), ("defect", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
 class KernelTime(C.Structure):
     _fields_ = [("count", C.c_int32), ("reserved", C.c_int32), ("total_ms", C.c_double)]
 
@@ -84,9 +98,12 @@ _SIGS = {
     "tpf_apply_dirichlet": (C.c_int32, [VP, DP, VP]),
     "tpf_residual": (C.c_int32, [VP, DP, DP, VP]),
     "tpf_assemble_stage": (C.c_int32, [VP, DP, C.c_double, DP, VP]),
+    "tpf_rescale_stage": (C.c_int32, [VP, C.c_double, VP]),
     "tpf_solve_stage": (C.c_int32, [VP, DP, DP, C.c_double, C.c_int32, C.POINTER(SolveStats), VP]),
     "tpf_limex_step": (C.c_int32, [VP, DP, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(LimexOpts),
                                    C.POINTER(LimexStats), VP]),
+    "tpf_storage": (C.c_int32, [VP, DP, DP, VP]),
+    "tpf_ie_step": (C.c_int32, [VP, DP, C.c_double, C.POINTER(NewtonOpts), C.POINTER(NewtonStats), VP]),
     "tpf_levels": (C.c_int32, [VP]),
     "tpf_level_dims": (C.c_int32, [VP, C.c_int32, C.POINTER(C.c_int32)]),
     "tpf_copy_matrix": (C.c_int32, [VP, C.c_int32, C.c_int32, DP, VP]),

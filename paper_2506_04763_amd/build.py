@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libtpf.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["rap.hip", "assemble.hip", "mg.hip", "krylov.hip", "limex.hip", "api.hip"]
+SOURCES = ["rap.hip", "assemble.hip", "mg.hip", "krylov.hip", "limex.hip", "ie.hip", "api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++20", "-fPIC", "--offload-arch=gfx950", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-I", INCLUDE, "-I", CSRC]

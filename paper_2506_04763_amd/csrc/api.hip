@@ -159,7 +159,7 @@ void layout(const tpf_grid_desc *d, Layout &L) {
   L.off_scal = o;
   o += align_up(NSCAL * sizeof(double));
   L.off_lx = o;
-  o += align_up(2 * L.N * sizeof(double)) * (3 + (d->limex_stages > 0 ? 1 + d->limex_stages : 0));
+  o += align_up(2 * L.N * sizeof(double)) * (4 + (d->limex_stages > 0 ? 1 + d->limex_stages : 0));
   L.total = o;
 }
 
@@ -291,6 +291,7 @@ tpf_status tpf_create_grid(const tpf_grid_desc *d, void *arena, size_t arena_byt
   g->u0 = reinterpret_cast<double *>(base + o); o += align_up(2 * L.N * sizeof(double));
   g->f0 = reinterpret_cast<double *>(base + o); o += align_up(2 * L.N * sizeof(double));
   g->fv = reinterpret_cast<double *>(base + o); o += align_up(2 * L.N * sizeof(double));
+  g->ua = reinterpret_cast<double *>(base + o); o += align_up(2 * L.N * sizeof(double));
   if (d->limex_stages > 0) {
     g->Tp = reinterpret_cast<double *>(base + o); o += align_up(2 * L.N * sizeof(double));
     for (int k = 0; k < d->limex_stages; ++k) {
@@ -399,6 +400,16 @@ tpf_status tpf_assemble_stage(tpf_grid *g, const double *u0, double h, double *f
   return TPF_OK;
 }
 
+tpf_status tpf_rescale_stage(tpf_grid *g, double h, tpf_stream stream) {
+  g_err[0] = 0;
+  if (!g) { set_error("NULL argument"); return TPF_EINVAL; }
+  if (!(h > 0.0) || !std::isfinite(h)) { set_error("h must be positive and finite"); return TPF_EINVAL; }
+  if (!g->assembled) { set_error("rescale_stage before assemble_stage"); return TPF_ESTATE; }
+  const tpf_status st = rescale_stage(g, g->h_stage / h, reinterpret_cast<hipStream_t>(stream));
+  if (st == TPF_OK) g->h_stage = h;
+  return st;
+}
+
 tpf_status tpf_solve_stage(tpf_grid *g, const double *f, double *x, double rtol, int32_t maxit,
                            tpf_solve_stats *stats, tpf_stream stream) {
   g_err[0] = 0;
@@ -423,6 +434,26 @@ tpf_status tpf_limex_step(tpf_grid *g, double *u, double *t, double *dt, const t
     return TPF_EINVAL;
   }
   return limex_step(g, u, t, dt, opts, stats, reinterpret_cast<hipStream_t>(stream));
+}
+
+tpf_status tpf_storage(tpf_grid *g, const double *u, double *m, tpf_stream stream) {
+  g_err[0] = 0;
+  if (!g || !u || !m) { set_error("NULL argument"); return TPF_EINVAL; }
+  if (u == m) { set_error("u and m may not alias"); return TPF_EINVAL; }
+  return launch_storage(g, u, m, reinterpret_cast<hipStream_t>(stream));
+}
+
+tpf_status tpf_ie_step(tpf_grid *g, double *u, double tau, const tpf_newton_opts *opts, tpf_newton_stats *stats,
+                       tpf_stream stream) {
+  g_err[0] = 0;
+  if (!g || !u || !opts) { set_error("NULL argument"); return TPF_EINVAL; }
+  if (!(tau > 0.0) || !std::isfinite(tau)) { set_error("tau must be positive and finite"); return TPF_EINVAL; }
+  if (opts->max_newton < 1 || opts->max_halvings < 0 || opts->maxit < 1 || !(opts->atol >= 0.0) ||
+      !(opts->rtol >= 0.0) || !(opts->lin_rtol > 0.0)) {
+    set_error("invalid Newton options");
+    return TPF_EINVAL;
+  }
+  return ie_step(g, u, tau, opts, stats, reinterpret_cast<hipStream_t>(stream));
 }
 
 int32_t tpf_levels(const tpf_grid *g) { return g ? g->L : 0; }

@@ -255,11 +255,12 @@ constexpr int CP = 8;
 // Interface condition (Eq. hSw) and the laws at corner saturation sn of a cell with
 // entry pressure pde and 1/lambda il; pdm = p_dmin of the corner, pvl = (P, dP/dS_n)
 // of the corner.
-__host__ __device__ __forceinline__ void corner_laws(const double sn, const double pdm, const double2 pvl,
-                                                    const double pde, const double lame, const double il,
-                                                    const Phys &P, double &sh, double &dsh, double &pc,
-                                                    double &dpc, double &khn, double &dkhn) {
-  // equal entry pressure / barrier / continuity
+// The saturation of the sub-control volume (vertex, cell) under the interface
+// condition (Eq. hSw): equal entry pressure / barrier / continuity, as a non-wetting
+// saturation, and its derivative w.r.t. the vertex S_n.
+__host__ __device__ __forceinline__ void hat_sat(const double sn, const double pdm, const double2 pvl,
+                                                const double pde, const double lame, const Phys &P, double &sh,
+                                                double &dsh) {
   if (pde == pdm) {
     sh = sn; dsh = 1.0;
   } else if (pde >= pvl.x) {
@@ -269,6 +270,13 @@ __host__ __device__ __forceinline__ void corner_laws(const double sn, const doub
     sh = 1.0 - (P.swr + ses * P.D);
     dsh = -P.D * (-lame * ses / pvl.x * pvl.y);
   }
+}
+
+__host__ __device__ __forceinline__ void corner_laws(const double sn, const double pdm, const double2 pvl,
+                                                    const double pde, const double lame, const double il,
+                                                    const Phys &P, double &sh, double &dsh, double &pc,
+                                                    double &dpc, double &khn, double &dkhn) {
+  hat_sat(sn, pdm, pvl, pde, lame, P, sh, dsh);
   double se, dse;
   eff_sat(sh, P, se, dse);
   const double t = root_lam(se, il);
@@ -595,6 +603,74 @@ k_assemble3_split(const Phys P, const CellIn in, const uint8_t *__restrict__ dma
   }
 }
 
+// Storage of vertex v, m_i = sum over its sub-control volumes of Phi_e rho_a S^_a |SCV|
+// with the saturation of the interface condition (Section 3.1, Eqs. dsW/dpN; the
+// quantity whose derivative is M(u) in M(u) u' = F(u)).  in.pv must hold the vertex
+// capillary pressures of in.u.
+template <int DIM>
+__host__ __device__ __forceinline__ void storage_vertex(const long long v, const Phys &P, const CellIn &in,
+                                                       double &mw, double &mn) {
+  constexpr int NC = 1 << DIM;
+  int ix, iy, iz;
+  grid_coords(v, P.nx, P.ny, ix, iy, iz);
+  const double sn = in.u[2 * v + 1], pdm = in.pdmin[v];
+  const double2 pvl = *reinterpret_cast<const double2 *>(in.pv + 2 * v);
+  mw = 0.0;
+  mn = 0.0;
+#pragma unroll
+  for (int cc = 0; cc < NC; ++cc) {
+    const int ox = ix - bit(cc, 0), oy = iy - bit(cc, 1), oz = (DIM == 3) ? iz - bit(cc, 2) : 0;
+    if (ox < 0 || oy < 0 || oz < 0 || ox >= P.ncx || oy >= P.ncy || oz >= P.ncz) continue;
+    const long long c = ox + (long long)P.ncx * (oy + (long long)P.ncy * oz);
+    double sh, dsh;
+    hat_sat(sn, pdm, pvl, in.pdc[c], in.lamc[c], P, sh, dsh);
+    const double w = in.phic[c] * P.scv;
+    mw += w * P.rho_w * (1.0 - sh);
+    mn += w * P.rho_n * sh;
+  }
+}
+
+template <int DIM>
+__global__ void __launch_bounds__(BS) k_storage(const Phys P, const CellIn in, double *__restrict__ m) {
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= P.N) return;
+  double mw, mn;
+  storage_vertex<DIM>(v, P, in, mw, mn);
+  *reinterpret_cast<double2 *>(m + 2 * v) = make_double2(mw, mn);
+}
+
+// Newton right-hand side of the implicit Euler step m(u) - m(u_old) - tau F(u) = 0:
+// r = F(u) - (m(u) - m_old) / tau in place of F (Dirichlet components 0), and the
+// block partial sums of r.r (grid-stride over the vertices, fixed order).
+template <int DIM>
+__global__ void __launch_bounds__(BS) k_ie_rhs(const Phys P, const CellIn in, const uint8_t *__restrict__ dmask,
+                                               const double *__restrict__ mold, const double inv_tau,
+                                               double *__restrict__ r, double *__restrict__ part) {
+  __shared__ double sm[BS / 64];
+  double acc = 0.0;
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < P.N; v += (long long)gridDim.x * blockDim.x) {
+    double mw, mn;
+    storage_vertex<DIM>(v, P, in, mw, mn);
+    const double2 f = *reinterpret_cast<const double2 *>(r + 2 * v);
+    const double2 mo = *reinterpret_cast<const double2 *>(mold + 2 * v);
+    const uint8_t m = dmask[v];
+    const double rw = (m & 1) ? 0.0 : f.x - (mw - mo.x) * inv_tau;
+    const double rn = (m & 2) ? 0.0 : f.y - (mn - mo.y) * inv_tau;
+    *reinterpret_cast<double2 *>(r + 2 * v) = make_double2(rw, rn);
+    acc += rw * rw + rn * rn;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < BS / 64; ++w) t += sm[w];
+    part[blockIdx.x] = t;
+  }
+}
+
 __global__ void k_apply_dirichlet(long long N, const uint8_t *__restrict__ m,
                                   const double *__restrict__ val, double *__restrict__ u) {
   const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -649,6 +725,7 @@ tpf_status launch_residual(tpf_grid *g, const double *u, double *f, hipStream_t 
 
 tpf_status launch_assemble(tpf_grid *g, const double *u0, double h, double *f0, hipStream_t s) {
   const unsigned nb = blocks_for(g->P.N);
+  g->h_stage = h;
   k_vertex_pc<<<nb, BS, 0, s>>>(g->P, u0, g->pdmin, g->lamref, g->pv);
   TPF_LAUNCH_CHECK();
   double *A64 = g->lv[0].A64;
@@ -693,6 +770,32 @@ tpf_status launch_assemble(tpf_grid *g, const double *u0, double h, double *f0, 
   }
   TPF_LAUNCH_CHECK();
   prof_end(g, ps, s);
+  return TPF_OK;
+}
+
+tpf_status launch_storage(tpf_grid *g, const double *u, double *m, hipStream_t s) {
+  const unsigned nb = blocks_for(g->P.N);
+  k_vertex_pc<<<nb, BS, 0, s>>>(g->P, u, g->pdmin, g->lamref, g->pv);
+  TPF_LAUNCH_CHECK();
+  const CellIn in = cell_in(g, u);
+  if (g->dim == 3)
+    k_storage<3><<<nb, BS, 0, s>>>(g->P, in, m);
+  else
+    k_storage<2><<<nb, BS, 0, s>>>(g->P, in, m);
+  TPF_LAUNCH_CHECK();
+  return TPF_OK;
+}
+
+tpf_status launch_ie_rhs(tpf_grid *g, const double *u, double *r, const double *mold, double inv_tau, double *part,
+                         unsigned nblk, hipStream_t s) {
+  k_vertex_pc<<<blocks_for(g->P.N), BS, 0, s>>>(g->P, u, g->pdmin, g->lamref, g->pv);
+  TPF_LAUNCH_CHECK();
+  const CellIn in = cell_in(g, u);
+  if (g->dim == 3)
+    k_ie_rhs<3><<<nblk, BS, 0, s>>>(g->P, in, g->dmask, mold, inv_tau, r, part);
+  else
+    k_ie_rhs<2><<<nblk, BS, 0, s>>>(g->P, in, g->dmask, mold, inv_tau, r, part);
+  TPF_LAUNCH_CHECK();
   return TPF_OK;
 }
 

@@ -138,6 +138,7 @@ tpf_status launch_assemble(tpf_grid *g, const double *u0, double h, double *f0, 
 tpf_status launch_residual(tpf_grid *g, const double *u, double *f, hipStream_t s);
 tpf_status build_hierarchy(tpf_grid *g, hipStream_t s);
 tpf_status copy_vec(double *dst, const double *src, long long n, hipStream_t s);
+tpf_status rescale_stage(tpf_grid *g, double ratio, hipStream_t s);
 
 #define TPF_TRY(x)                   \
   do {                               \
@@ -155,8 +156,14 @@ tpf_status limex_step(tpf_grid *g, double *u, double *t, double *dt, const tpf_l
   TPF_TRY(copy_vec(g->u0, u, n, s));
   bool failed = false;  // a stage solve missed rtol within maxit or broke down
   for (int j = 1; j <= k && !failed; ++j) {
-    TPF_TRY(launch_assemble(g, g->u0, H / j, g->f0, s));
-    TPF_TRY(build_hierarchy(g, s));
+    if (j == 1) {  // A(H) = M(u0)/H - J(u0), F(u0) and the hierarchy
+      TPF_TRY(launch_assemble(g, g->u0, H, g->f0, s));
+      TPF_TRY(build_hierarchy(g, s));
+    } else {  // M and J stay frozen at u0: only the storage parts follow the step H/j
+      const double h = H / j;
+      TPF_TRY(rescale_stage(g, g->h_stage / h, s));
+      g->h_stage = h;
+    }
     g->assembled = true;
     g->has_f0 = true;
     double *Tj = g->T[j - 1];

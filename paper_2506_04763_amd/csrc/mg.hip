@@ -957,6 +957,34 @@ __global__ void k_untile(const float *__restrict__ src, float *__restrict__ dst,
   *reinterpret_cast<float4 *>(dst + t * 4) = *reinterpret_cast<const float4 *>(src + tiled_block(o, v, nst) * 4);
 }
 
+// Storage part of one level's operator moved to a new step: the centre block's S-column
+// entries are (flux part) + mst, where mst is the level's storage M/h (fine level: the
+// box-method storage, zero on Dirichlet rows; coarse levels: its lumped Galerkin image,
+// linear in the fine storage).  The flux part of every level does not depend on h, so
+// A(h') = A(h) - mst + ratio mst with ratio = h / h'.  The FP32 copy's centre block is
+// rewritten from the new FP64 block (tiled on the finest level).
+template <int DIM>
+__global__ void __launch_bounds__(BS) k_rescale(const Geo G, double *__restrict__ A, float *__restrict__ A32,
+                                                int tiled, double *__restrict__ mst, double ratio) {
+  constexpr int NST = DIM == 3 ? 27 : 9;
+  constexpr int CEN = DIM == 3 ? 13 : 4;
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= G.N) return;
+  const double2 m = *reinterpret_cast<const double2 *>(mst + 2 * v);
+  const double n0 = m.x * ratio, n1 = m.y * ratio;
+  double2 *blk = reinterpret_cast<double2 *>(A + ((long long)CEN * G.N + v) * 4);
+  double2 b01 = blk[0], b23 = blk[1];
+  b01.y = (b01.y - m.x) + n0;
+  b23.y = (b23.y - m.y) + n1;
+  blk[0] = b01;
+  blk[1] = b23;
+  *reinterpret_cast<double2 *>(mst + 2 * v) = make_double2(n0, n1);
+  if (A32) {
+    const long long k = tiled ? tiled_block(CEN, v, NST) : (long long)CEN * G.N + v;
+    *reinterpret_cast<float4 *>(A32 + k * 4) = make_float4((float)b01.x, (float)b01.y, (float)b23.x, (float)b23.y);
+  }
+}
+
 // ---- V-cycle driver ----------------------------------------------------------
 // TPF_MIXED16 coarse levels: sweep (first: zero initial guess) and residual with the
 // FP16 matrix; return false where the level is not stored in FP16.
@@ -1137,6 +1165,9 @@ tpf_status vcycle_t(tpf_grid *g, const double *bin, double *xout, hipStream_t s,
 }
 
 template <int DIM>
+tpf_status coarse_factor_t(tpf_grid *g, hipStream_t s);
+
+template <int DIM>
 tpf_status hierarchy_t(tpf_grid *g, hipStream_t s) {
   for (int l = 0; l + 1 < g->L; ++l) {
     const Level &f = g->lv[l];
@@ -1152,6 +1183,12 @@ tpf_status hierarchy_t(tpf_grid *g, hipStream_t s) {
     }
     prof_end(g, ps, s);
   }
+  return coarse_factor_t<DIM>(g, s);
+}
+
+// Dense LU with partial pivoting of the coarsest level and its inverse.
+template <int DIM>
+tpf_status coarse_factor_t(tpf_grid *g, hipStream_t s) {
   Level &lc = g->lv[g->L - 1];
   const int n = g->nc;
   const int pl = prof_begin(g, TPF_K_COARSE_LU, s);
@@ -1200,7 +1237,30 @@ tpf_status spmv_t(tpf_grid *g, int level, const double *x, double *y, hipStream_
   return TPF_OK;
 }
 
+// Every level's operator moved from the step h to h / ratio (storage parts scaled by
+// ratio), the FP32 / FP16 copies refreshed, the coarsest level refactored.
+template <int DIM>
+tpf_status rescale_t(tpf_grid *g, double ratio, hipStream_t s) {
+  const int ps = prof_begin(g, TPF_K_ASSEMBLE, s);
+  for (int l = 0; l < g->L; ++l) {
+    Level &lv = g->lv[l];
+    float *a32 = lv.A32;  // FP32 copy where one exists (finest tiled)
+    k_rescale<DIM><<<blocks_for(lv.N), BS, 0, s>>>(geo(lv), lv.A64, a32, l == 0 ? 1 : 0, lv.mst, ratio);
+    TPF_LAUNCH_CHECK();
+    if (g->prec == TPF_MIXED16 && l > 0) {  // the row scales depend on the centre block
+      k_to16<DIM><<<blocks_for(lv.N), BS, 0, s>>>(geo(lv), lv.A64, lv.A16, lv.s16);
+      TPF_LAUNCH_CHECK();
+    }
+  }
+  prof_end(g, ps, s);
+  return coarse_factor_t<DIM>(g, s);
+}
+
 }  // namespace
+
+tpf_status rescale_stage(tpf_grid *g, double ratio, hipStream_t s) {
+  return g->dim == 3 ? rescale_t<3>(g, ratio, s) : rescale_t<2>(g, ratio, s);
+}
 
 tpf_status untile_matrix32(tpf_grid *g, float *dst, hipStream_t s) {
   const Level &lv = g->lv[0];

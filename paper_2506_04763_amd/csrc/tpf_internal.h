@@ -22,7 +22,7 @@ constexpr int NSCAL = 32;         // device scalars of the Krylov solver
 // Scalars of the Krylov recurrence kept on the device (indices into g->scal).
 enum Scal {
   S_RHO = 0, S_RHO_OLD, S_ALPHA, S_OMEGA, S_BETA, S_RV, S_TS, S_TT, S_RR, S_FF, S_WW,
-  S_NORM_A, S_NORM_B, S_NORM_C, S_NORM_D, S_COUNT
+  S_NORM_A, S_NORM_B, S_NORM_C, S_NORM_D, S_IE_RR, S_COUNT
 };
 
 // Physical and geometric constants passed by value to every kernel.
@@ -92,12 +92,13 @@ struct tpf_grid {
   long long npart;
   double *scal;
   // LIMEX
-  double *u0, *f0, *fv, *T[tpf::MAXK], *Tp;
+  double *u0, *f0, *fv, *ua, *T[tpf::MAXK], *Tp;
   // host side
   double *hscal;  // pinned, NSCAL doubles
   hipEvent_t scal_ev;  // recorded after each per-iteration copy of the scalars to hscal
   bool assembled;
   bool has_f0;
+  double h_stage;  // step of the assembled stage operator
   size_t bytes;
   int device;
   tpf::Prof prof;
@@ -189,11 +190,21 @@ tpf_status setup_vertices(tpf_grid *g, const Patches &pt, hipStream_t s);
 tpf_status launch_residual(tpf_grid *g, const double *u, double *f, hipStream_t s);
 tpf_status launch_assemble(tpf_grid *g, const double *u0, double h, double *f0, hipStream_t s);
 tpf_status launch_apply_dirichlet(tpf_grid *g, double *u, hipStream_t s);
+// m(u): the storage of both phases per vertex (double[2N], kg)
+tpf_status launch_storage(tpf_grid *g, const double *u, double *m, hipStream_t s);
+// r <- r - (m(u) - mold) / tau with Dirichlet components 0 (r holds F(u) on entry),
+// and nblk block partial sums of r.r in part (grid-stride launch of nblk blocks)
+tpf_status launch_ie_rhs(tpf_grid *g, const double *u, double *r, const double *mold, double inv_tau, double *part,
+                         unsigned nblk, hipStream_t s);
 // p_n = p_w + P_i of the states a and b: out[0, N) from a, out[N, 2N) from b
 tpf_status launch_pn2(tpf_grid *g, const double *a, const double *b, double *out, hipStream_t s);
 
 // ---- launchers (mg.hip) ----
 tpf_status build_hierarchy(tpf_grid *g, hipStream_t s);
+// Moves the assembled stage operator and the whole hierarchy from the step h to
+// h / ratio (M(u0) and J(u0) frozen): storage parts times ratio, copies refreshed,
+// coarsest level refactored.
+tpf_status rescale_stage(tpf_grid *g, double ratio, hipStream_t s);
 // The finest FP32 matrix in the [offset][vertex] layout of the ABI (dst: nst*4*N floats).
 tpf_status untile_matrix32(tpf_grid *g, float *dst, hipStream_t s);
 // A coarse level's FP16 matrix as floats (entries times row scales), [offset][vertex][4].
@@ -207,6 +218,10 @@ tpf_status spmv64(tpf_grid *g, int level, const double *x, double *y, hipStream_
 // ---- krylov.hip ----
 tpf_status bicgstab(tpf_grid *g, const double *f, double *x, double rtol, int maxit,
                     tpf_solve_stats *st, hipStream_t s);
+
+// ---- ie.hip ----
+tpf_status ie_step(tpf_grid *g, double *u, double tau, const tpf_newton_opts *o, tpf_newton_stats *st,
+                   hipStream_t s);
 
 // ---- shared small kernels (krylov.hip) ----
 tpf_status fill_zero(double *p, long long n, hipStream_t s);

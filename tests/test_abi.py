@@ -68,7 +68,8 @@ def _bytes_expected(scn, prec, limex=0):
     tot += al(nst * 4 * N * 8) if scn.levels > 1 else 0   # Galerkin-product scratch
     tot += 10 * al(2 * N * 8)
     tot += al(4 * max(1024, (N + 255) // 256) * 8) + al(32 * 8)
-    tot += al(2 * N * 8) * (3 + (1 + limex if limex else 0))
+    # step vectors: u0, F0, F(v) and the Newton base point, then the LIMEX tableau
+    tot += al(2 * N * 8) * (4 + (1 + limex if limex else 0))
     return tot
 
 

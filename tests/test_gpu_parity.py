@@ -285,3 +285,39 @@ def test_reference_medium_tie_parity(dim):
     f = g.residual(torch.as_tensor(u.ravel(), device="cuda")).cpu().numpy()
     g.close()
     assert per_field(f, ref.residual(u.ravel())) < 1e-12
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "mixed16"])
+def test_rescaled_stage_parity(case, prec):
+    """The LIMEX stages j >= 2 move the assembled operator to the step H/j by rescaling
+    the storage part of every level (M and J frozen at u0): after assembling at h and
+    rescaling to h/2 and then h/3, every level, the FP32 copies, the FP16 coarse
+    matrices and the coarsest inverse match the oracle assembled at h/3 directly."""
+    scn = case["scn"]
+    h3 = case["h"] / 3.0
+    ref = ST.Stage(scn)
+    ref.assemble(case["u"].ravel(), h3)
+    g = tpf.Grid(scn, precision=prec)
+    g.assemble_stage(torch.as_tensor(case["u"].ravel(), device="cuda"), case["h"])
+    g.rescale_stage(case["h"] / 2.0)
+    g.rescale_stage(h3)
+    for l in range(scn.levels):
+        a64 = g.matrix(l).cpu().numpy()
+        Ag = stencil_to_csr(a64, g.level_dims(l), scn.dim)
+        Ar = ref.H.A[l]
+        D = abs(Ag - Ar).tocsr()
+        for r in (0, 1):
+            assert D[r::2].max() <= 1e-11 * abs(Ar[r::2]).max(), (l, r, D[r::2].max() / abs(Ar[r::2]).max())
+        if prec == "mixed" or (prec == "mixed16" and l == 0):
+            np.testing.assert_array_equal(g.matrix(l, "mixed").cpu().numpy(), a64.astype(np.float32))
+        if prec == "mixed16" and l > 0:  # FP16 entries within their rounding of the rescaled rows
+            a16 = g.matrix(l, "mixed16").cpu().numpy().astype(np.float64)
+            for r in (0, 1):
+                rows64 = a64[:, :, 2 * r:2 * r + 2]
+                scale = np.abs(rows64).max(axis=(0, 2))
+                scale = np.where(scale > 0, scale, 1.0)
+                err = np.abs(a16[:, :, 2 * r:2 * r + 2] - rows64).max(axis=(0, 2))
+                assert np.all(err <= (2.0 ** -11 + 2.0 ** -21) * scale), (l, r)
+    inv = g.coarse_inverse().cpu().numpy()
+    assert rel(inv, np.linalg.inv(ref.H.A[-1].toarray())) < 1e-9
+    g.close()
