@@ -241,6 +241,21 @@ tpf_status tpf_rescale_stage(tpf_grid *g, double h, tpf_stream stream);
 tpf_status tpf_solve_stage(tpf_grid *g, const double *f, double *x, double rtol, int32_t maxit,
                            tpf_solve_stats *stats, tpf_stream stream);
 
+/* tpf_solve_stage for callers that cannot allocate device memory or bring
+ * workspace of their own (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation): the same solve, same kernels and the same result, but the
+ * BiCGSTAB work vectors, block partials and device scalars live in a fixed device
+ * array inside the library (64 MiB per GPU, held until the process ends) instead of
+ * the grid's arena.  The assembled hierarchy and the V-cycle's level vectors stay in
+ * the arena.  Grids needing more than the array holds (above about 460,000 vertices,
+ * e.g. 65^3 fits, 97^3 does not) get TPF_EINVAL with a message.  Calls nothing that
+ * allocates.  Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (different streams or threads) race and must be serialised by the caller.  The
+ * array keeps the last call's contents; the solve initialises everything it reads.
+ * The grid's device must be current.  Returns as tpf_solve_stage. */
+tpf_status tpf_solve_stage_static(tpf_grid *g, const double *f, double *x, double rtol, int32_t maxit,
+                                  tpf_solve_stats *stats, tpf_stream stream);
+
 /* One LIMEX step of size *dt from state u at time *t (Section 4): stages
  * j = 1..k take j linearly implicit Euler substeps of *dt/j with M and J frozen
  * at u and F re-evaluated each substep; Aitken-Neville extrapolation; error

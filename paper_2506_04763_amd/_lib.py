@@ -99,6 +99,7 @@ _SIGS = {
     "tpf_residual": (C.c_int32, [VP, DP, DP, VP]),
     "tpf_assemble_stage": (C.c_int32, [VP, DP, C.c_double, DP, VP]),
     "tpf_rescale_stage": (C.c_int32, [VP, C.c_double, VP]),
+    "tpf_solve_stage_static": (C.c_int32, [VP, DP, DP, C.c_double, C.c_int32, C.POINTER(SolveStats), VP]),
     "tpf_solve_stage": (C.c_int32, [VP, DP, DP, C.c_double, C.c_int32, C.POINTER(SolveStats), VP]),
     "tpf_limex_step": (C.c_int32, [VP, DP, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(LimexOpts),
                                    C.POINTER(LimexStats), VP]),

@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "tpf_internal.h"
@@ -164,6 +165,56 @@ void layout(const tpf_grid_desc *d, Layout &L) {
 }
 
 }  // namespace
+}  // namespace tpf
+
+namespace tpf {
+
+// ---- the solve without caller-provided Krylov workspace -----------------------
+// Workspace of tpf_solve_stage_static: the BiCGSTAB vectors, block partials and device
+// scalars of one solve, in a device array of fixed size (each GPU the library runs on
+// holds its own copy until the process ends).  Host code never uses the array's name
+// as an address: it takes the device address once per device from the runtime.
+constexpr size_t STATIC_SCRATCH_BYTES = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {nullptr};
+
+// The device address of this device's scratch array (looked up on first use, with the
+// device current).
+tpf_status scratch_for_current_device(void **out) {
+  int dev = -1;
+  TPF_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) {
+    set_error("device %d out of range", dev);
+    return TPF_EDEVICE;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      set_error("hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+      return TPF_EDEVICE;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return TPF_OK;
+}
+
+// Bytes of the static workspace a solve on g needs: nine Krylov vectors (the tenth of
+// the arena's set, the LIMEX update, is not used by a solve), the block partials and
+// the device scalars.
+size_t static_solve_bytes(const tpf_grid *g) {
+  return 9 * align_up(2 * (size_t)g->P.N * sizeof(double)) + align_up(4 * (size_t)g->npart * sizeof(double)) +
+         align_up(NSCAL * sizeof(double));
+}
+}  // namespace
+
 }  // namespace tpf
 
 using namespace tpf;
@@ -398,6 +449,49 @@ tpf_status tpf_assemble_stage(tpf_grid *g, const double *u0, double h, double *f
   g->assembled = true;
   g->has_f0 = true;
   return TPF_OK;
+}
+
+tpf_status tpf_solve_stage_static(tpf_grid *g, const double *f, double *x, double rtol, int32_t maxit,
+                                  tpf_solve_stats *stats, tpf_stream stream) {
+  g_err[0] = 0;
+  if (!g || !f || !x) { set_error("NULL argument"); return TPF_EINVAL; }
+  if (f == x) { set_error("f and x may not alias"); return TPF_EINVAL; }
+  if (!(rtol > 0.0) || maxit < 1) { set_error("need rtol > 0 and maxit >= 1"); return TPF_EINVAL; }
+  if (!g->assembled) { set_error("solve_stage before assemble_stage"); return TPF_ESTATE; }
+  const size_t need = static_solve_bytes(g);
+  if (need > STATIC_SCRATCH_BYTES) {
+    set_error("tpf_solve_stage_static: the grid needs %zu bytes of workspace, the static array holds %zu "
+              "(at most about %lld vertices); use tpf_solve_stage", need, STATIC_SCRATCH_BYTES,
+              (long long)(STATIC_SCRATCH_BYTES / (9 * 16 + 1)));
+    return TPF_EINVAL;
+  }
+  int dev = -1;
+  TPF_HIP(hipGetDevice(&dev));
+  if (dev != g->device) {
+    set_error("the grid lives on device %d but device %d is current", g->device, dev);
+    return TPF_EINVAL;
+  }
+  void *base = nullptr;
+  tpf_status st = scratch_for_current_device(&base);
+  if (st != TPF_OK) return st;
+  // point the grid's solve workspace into the static array for this call
+  double **kv[9] = {&g->r, &g->rh, &g->p, &g->v, &g->s, &g->t, &g->ph, &g->sh, &g->w};
+  double *saved[9];
+  double *saved_part = g->part, *saved_scal = g->scal;
+  char *c = static_cast<char *>(base);
+  for (int k = 0; k < 9; ++k) {
+    saved[k] = *kv[k];
+    *kv[k] = reinterpret_cast<double *>(c);
+    c += align_up(2 * (size_t)g->P.N * sizeof(double));
+  }
+  g->part = reinterpret_cast<double *>(c);
+  c += align_up(4 * (size_t)g->npart * sizeof(double));
+  g->scal = reinterpret_cast<double *>(c);
+  st = bicgstab(g, f, x, rtol, maxit, stats, reinterpret_cast<hipStream_t>(stream));
+  for (int k = 0; k < 9; ++k) *kv[k] = saved[k];
+  g->part = saved_part;
+  g->scal = saved_scal;
+  return st;
 }
 
 tpf_status tpf_rescale_stage(tpf_grid *g, double h, tpf_stream stream) {
