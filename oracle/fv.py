@@ -382,12 +382,17 @@ class FV:
         keep[self.dirichlet_dofs()] = 0.0
         return sp.csr_matrix(sp.diags(keep) @ self.mass_matrix(u0) / h)
 
-    def stage_matrix(self, u0, h, cells=None):
+    def stage_matrix(self, u0, h, cells=None, frozen=None):
         """A = M(u0)/h - J(u0) (Section 4: the linearly implicit Euler matrix divided
-        by the step), with unit rows at the Dirichlet components."""
-        J = self.jacobian(u0, cells)
-        M = self.mass_matrix(u0)
+        by the step), with unit rows at the Dirichlet components.  frozen = (M, J) of
+        u0 from an earlier call (the stages of one linearly implicit step share them)."""
+        M, J = frozen if frozen is not None else self.frozen_matrices(u0, cells)
         keep = np.ones(2 * self.N)
         keep[self.dirichlet_dofs()] = 0.0
         A = sp.diags(keep) @ (M / h - J) + sp.diags(1.0 - keep)
         return sp.csr_matrix(A)
+
+    def frozen_matrices(self, u0, cells=None):
+        """(M(u0), J(u0)): the storage and flux Jacobians a linearly implicit step
+        freezes at its initial state."""
+        return self.mass_matrix(u0), self.jacobian(u0, cells)

@@ -6,16 +6,16 @@ Paper passages followed:
     (M(u_old) - tau J(u_old)) (u_new - u_old) = tau F(u_old), J = F_u exact;
   * step-size rule tau_new = (rho TOL / [[eps]])^(1/(q+1)) tau_old with q = 2;
   * error estimate [[eps]] = relative error in the scaled norm
-    |||u|||^2 = alpha ||grad p_n||^2 + beta ||S_w||^2 (Eq. norm_u), the H1-seminorm of
-    the non-wetting pressure and the L2 norm of the wetting saturation.
+    |||u|||^2 = alpha ||grad p||^2 + beta ||S_w||^2 (Eq. norm_u).  Eqs. norm_uw and norm_un
+    derive it from the convective parts of both mass balances, which the pressure
+    whose gradient drives them controls: p_n in the paper's (p_n, S_w) form, p_w in the
+    (p_w, S_n) form used here (v_w and the convective v_n' both move with grad p_w).
 Readings: harmonic stage sequence n_j = j, stage j takes j
 substeps of H/j with M and J frozen at the step's initial state and F re-evaluated at
 every substep; Aitken-Neville extrapolation
   T_{j,l+1} = T_{j,l} + (T_{j,l} - T_{j-1,l}) / (n_j / n_{j-l} - 1);
-eps = |||T_kk - T_{k,k-1}||| / |||T_kk||| with alpha = 1/(2 ||grad p_n(T_kk)||^2),
-beta = 1/(2 ||S_w(T_kk)||^2), so eps^2 = (e_p^2 + e_S^2)/2; p_n at a vertex is
-p_w + P_i, P_i the capillary pressure of the vertex's reference medium (the one the
-interface condition compares with); accept iff eps <= TOL;
+eps = |||T_kk - T_{k,k-1}||| / |||T_kk||| with alpha = 1/(2 ||grad p_w(T_kk)||^2),
+beta = 1/(2 ||S_w(T_kk)||^2), so eps^2 = (e_p^2 + e_S^2)/2; accept iff eps <= TOL;
 tau_new = min(tau_max, H (rho TOL / eps)^(1/3)).
 """
 from __future__ import annotations
@@ -110,19 +110,14 @@ class Norms:
     def sat_sq(self, sw):
         return float(np.sum(self.dual * sw * sw))
 
-    def pn(self, u):
-        """Non-wetting pressure p_n = p_w + P_i at every vertex of the state u (N, 2)."""
-        return u[:, 0] + self.fv.vertex_pc(u)
-
     def err_ratio(self, kk, km):
         """[[eps]] of Eq. norm_u between T_kk and T_{k,k-1} (flat or (N, 2) states):
-        sqrt((||grad dp_n||^2 / ||grad p_n(kk)||^2 + ||dS_w||^2 / ||S_w(kk)||^2) / 2)."""
+        sqrt((||grad dp_w||^2 / ||grad p_w(kk)||^2 + ||dS_w||^2 / ||S_w(kk)||^2) / 2)."""
         kk = kk.reshape(-1, 2)
         km = km.reshape(-1, 2)
-        pn_kk = self.pn(kk)
-        dp = pn_kk - self.pn(km)
+        dp = kk[:, 0] - km[:, 0]
         ds = -(kk[:, 1] - km[:, 1])
-        gp = max(self.grad_sq(pn_kk), 1e-300)
+        gp = max(self.grad_sq(kk[:, 0]), 1e-300)
         gs = max(self.sat_sq(1.0 - kk[:, 1]), 1e-300)
         e2 = 0.5 * (self.grad_sq(dp) / gp + self.sat_sq(ds) / gs)
         return float(np.sqrt(e2))

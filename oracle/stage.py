@@ -23,8 +23,10 @@ class Stage:
     def residual(self, u):
         return self.fv.residual(u.reshape(-1, 2)).ravel()
 
-    def assemble(self, u0, h):
-        self.A = self.fv.stage_matrix(u0.reshape(-1, 2), h)
+    def assemble(self, u0, h, frozen=None):
+        """Stage matrix and hierarchy at u0 for the step h; frozen = (M(u0), J(u0))
+        reuses the matrices of an earlier stage of the same step."""
+        self.A = self.fv.stage_matrix(u0.reshape(-1, 2), h, frozen=frozen)
         S0 = self.fv.storage_part(u0.reshape(-1, 2), h)
         T0 = _gmg.volume_balance(self.fv.dir_mask, self.scn.rho)
         self.H = _gmg.Hierarchy(self.A, self.scn.n, self.scn.dim, self.levels, self.fv.dir_mask,
@@ -39,8 +41,12 @@ class Stage:
         norms = _lx.Norms(self.fv)
         info = dict(iters=[], solves=0)
 
+        frozen = []  # M(u) and J(u), shared by the stages of this step
+
         def stage_solve(h):
-            self.assemble(u, h)
+            if not frozen:
+                frozen.append(self.fv.frozen_matrices(u.reshape(-1, 2)))
+            self.assemble(u, h, frozen=frozen[0])
 
             def solve(f):
                 x, st = self.solve(f, rtol, maxit)

@@ -218,21 +218,6 @@ __global__ void __launch_bounds__(BS) k_vertex_pc(const Phys P, const double *__
   vertex_pc(v, P, u, pdmin, lamref, pv);
 }
 
-// Non-wetting pressure p_n = p_w + P_i of two states a and b (the pressure of the
-// error norm, Eq. norm_u): out[v] from a, out[N + v] from b.
-__global__ void __launch_bounds__(BS) k_pn2(const Phys P, const double *__restrict__ a,
-                                            const double *__restrict__ b, const double *__restrict__ pdmin,
-                                            const double *__restrict__ lamref, double *__restrict__ out) {
-  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= P.N) return;
-  const double il = 1.0 / lamref[v], pdm = pdmin[v];
-  double se, dse;
-  eff_sat(a[2 * v + 1], P, se, dse);
-  out[v] = a[2 * v] + pdm / root_lam(se, il);
-  eff_sat(b[2 * v + 1], P, se, dse);
-  out[P.N + v] = b[2 * v] + pdm / root_lam(se, il);
-}
-
 template <int DIM>
 __host__ __device__ __forceinline__ constexpr int stencil_index(int dx, int dy, int dz) {
   return DIM == 3 ? (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1) : (dx + 1) + 3 * (dy + 1);
@@ -795,12 +780,6 @@ tpf_status launch_ie_rhs(tpf_grid *g, const double *u, double *r, const double *
     k_ie_rhs<3><<<nblk, BS, 0, s>>>(g->P, in, g->dmask, mold, inv_tau, r, part);
   else
     k_ie_rhs<2><<<nblk, BS, 0, s>>>(g->P, in, g->dmask, mold, inv_tau, r, part);
-  TPF_LAUNCH_CHECK();
-  return TPF_OK;
-}
-
-tpf_status launch_pn2(tpf_grid *g, const double *a, const double *b, double *out, hipStream_t s) {
-  k_pn2<<<blocks_for(g->P.N), BS, 0, s>>>(g->P, a, b, g->pdmin, g->lamref, out);
   TPF_LAUNCH_CHECK();
   return TPF_OK;
 }

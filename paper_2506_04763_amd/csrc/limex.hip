@@ -3,12 +3,13 @@
 // harmonic stage sequence n_j = j, relative error in the scaled norm of Eq. norm_u
 // and the step-size rule with order q = 2.
 //
-// Error norm: |||u|||^2 = alpha ||grad p_n||^2 + beta ||S_w||^2 with
-// alpha = 1/(2 ||grad p_n(T_kk)||^2) and beta = 1/(2 ||S_w(T_kk)||^2), so that
-// eps^2 = (e_p^2 + e_S^2)/2 balances pressure and saturation errors; p_n = p_w + P_i
-// at each vertex, P_i the capillary pressure of its reference medium; ||grad p||^2 is
-// the exact integral of the Q1 interpolant (closed-form element stiffness of a
-// box), ||S_w||^2 the lumped (dual-box) L2 norm.
+// Error norm: |||u|||^2 = alpha ||grad p_w||^2 + beta ||S_w||^2 with
+// alpha = 1/(2 ||grad p_w(T_kk)||^2) and beta = 1/(2 ||S_w(T_kk)||^2), so that
+// eps^2 = (e_p^2 + e_S^2)/2 balances pressure and saturation errors.  The pressure is
+// the one whose gradient drives the convective parts of both balances (the argument of
+// Eqs. norm_uw/norm_un): p_n in the paper's (p_n, S_w) unknowns, p_w in the (p_w, S_n)
+// unknowns here.  ||grad p||^2 is the exact integral of the Q1 interpolant
+// (closed-form element stiffness of a box), ||S_w||^2 the lumped (dual-box) L2 norm.
 #include <cmath>
 
 #include "tpf_internal.h"
@@ -34,13 +35,11 @@ __global__ void __launch_bounds__(BS) k_extrap(long long n, double *__restrict__
   }
 }
 
-// Partial sums of ||grad (a_pn - b_pn)||^2, ||grad a_pn||^2, ||b_Sw - a_Sw||^2, ||a_Sw||^2
-// (a = T_kk, b = T_{k,k-1}; pn = [p_n(a) | p_n(b)]); each vertex owns the cell whose
-// origin it is.
+// Partial sums of ||grad (a_p - b_p)||^2, ||grad a_p||^2, ||b_Sw - a_Sw||^2, ||a_Sw||^2
+// (a = T_kk, b = T_{k,k-1}); each vertex owns the cell whose origin it is.
 template <int DIM>
 __global__ void __launch_bounds__(BS) k_norms(const Phys P, const double *__restrict__ a,
-                                              const double *__restrict__ b, const double *__restrict__ pn,
-                                              double *__restrict__ part) {
+                                              const double *__restrict__ b, double *__restrict__ part) {
   constexpr int NC = 1 << DIM;
   __shared__ double sm[4][BS / 64];
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -62,8 +61,8 @@ __global__ void __launch_bounds__(BS) k_norms(const Phys P, const double *__rest
 #pragma unroll
       for (int l = 0; l < NC; ++l) {
         const long long vl = v + (l & 1) + sy * ((l >> 1) & 1) + (DIM == 3 ? sz * ((l >> 2) & 1) : 0);
-        pa[l] = pn[vl];
-        pd[l] = pn[vl] - pn[P.N + vl];
+        pa[l] = a[2 * vl];
+        pd[l] = a[2 * vl] - b[2 * vl];
       }
 #pragma unroll
       for (int ax = 0; ax < DIM; ++ax) {
@@ -210,13 +209,10 @@ tpf_status limex_step(tpf_grid *g, double *u, double *t, double *dt, const tpf_l
   }
   double eps = 0.0;
   if (k > 1) {
-    // the non-wetting pressures of T_kk and T_{k,k-1} (into the substep residual,
-    // free at this point)
-    TPF_TRY(launch_pn2(g, g->T[k - 1], g->Tp, g->fv, s));
     if (g->dim == 3)
-      k_norms<3><<<RED_BLOCKS, BS, 0, s>>>(g->P, g->T[k - 1], g->Tp, g->fv, g->part);
+      k_norms<3><<<RED_BLOCKS, BS, 0, s>>>(g->P, g->T[k - 1], g->Tp, g->part);
     else
-      k_norms<2><<<RED_BLOCKS, BS, 0, s>>>(g->P, g->T[k - 1], g->Tp, g->fv, g->part);
+      k_norms<2><<<RED_BLOCKS, BS, 0, s>>>(g->P, g->T[k - 1], g->Tp, g->part);
     TPF_LAUNCH_CHECK();
     k_sum4<<<1, 1024, 0, s>>>(g->part, RED_BLOCKS, g->scal + S_NORM_A);
     TPF_LAUNCH_CHECK();

@@ -196,8 +196,6 @@ tpf_status launch_storage(tpf_grid *g, const double *u, double *m, hipStream_t s
 // and nblk block partial sums of r.r in part (grid-stride launch of nblk blocks)
 tpf_status launch_ie_rhs(tpf_grid *g, const double *u, double *r, const double *mold, double inv_tau, double *part,
                          unsigned nblk, hipStream_t s);
-// p_n = p_w + P_i of the states a and b: out[0, N) from a, out[N, 2N) from b
-tpf_status launch_pn2(tpf_grid *g, const double *a, const double *b, double *out, hipStream_t s);
 
 // ---- launchers (mg.hip) ----
 tpf_status build_hierarchy(tpf_grid *g, hipStream_t s);

@@ -283,7 +283,10 @@ def prepare_requests(count=256, rate_per_s=40.0, seed=5, workers=8):
 
 
 def run_benchmark(count=256, rate_per_s=40.0, seed=5, budget_bytes=200e9, slots=8, precision="mixed",
-                  quiet=False, prepared=None):
+                  quiet=False, prepared=None, time_scale=1.0):
+    """Replays the requests' Poisson arrivals in real time (arrival times multiplied by
+    time_scale: 0.5 replays the same requests at twice the rate) and reports latency
+    percentiles and throughput."""
     import workloads as W
     reqs, scns = prepared if prepared is not None else prepare_requests(count, rate_per_s, seed)
     srv = Server(budget_bytes=budget_bytes, slots=slots, precision=precision,
@@ -294,10 +297,11 @@ def run_benchmark(count=256, rate_per_s=40.0, seed=5, budget_bytes=200e9, slots=
     srv.t0 = time.perf_counter()
     futs = []
     for req, scn in zip(reqs, scns):
-        delay = req.arrival - srv.now()
+        arrival = req.arrival * time_scale
+        delay = arrival - srv.now()
         if delay > 0:
             time.sleep(delay)
-        futs.append(srv.submit(StageRequest(req.rid, scn, arrival=req.arrival)))
+        futs.append(srv.submit(StageRequest(req.rid, scn, arrival=arrival)))
     results = [f.result() for f in futs]
     makespan = max(r.t_done for r in results) - min(r.t_arrive for r in results)
     srv.shutdown()
@@ -307,7 +311,7 @@ def run_benchmark(count=256, rate_per_s=40.0, seed=5, budget_bytes=200e9, slots=
         by_n[req.n].append(r.latency)
     out = {
         "requests": len(results),
-        "arrival_rate_per_s": rate_per_s,
+        "arrival_rate_per_s": round(rate_per_s / time_scale, 3),
         "throughput_per_s": round(len(results) / makespan, 3),
         "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 2),
         "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 2),
@@ -324,3 +328,18 @@ def run_benchmark(count=256, rate_per_s=40.0, seed=5, budget_bytes=200e9, slots=
     if not quiet:
         print(out, flush=True)
     return out
+
+
+def capacity_sweep(rates=(40.0, 80.0, 160.0), count=256, base_rate=40.0, seed=5, prepared=None, **kw):
+    """The serving workload replayed at several arrival rates (the same requests, arrival
+    times compressed): throughput and latency percentiles per rate.  Throughput that
+    stops following the arrival rate marks the device's capacity for this mix."""
+    if prepared is None:
+        prepared = prepare_requests(count, base_rate, seed)
+    rows = []
+    for rate in rates:
+        out = run_benchmark(count=count, rate_per_s=base_rate, seed=seed, prepared=prepared, quiet=True,
+                            time_scale=base_rate / rate, **kw)
+        rows.append({k: out[k] for k in ("arrival_rate_per_s", "throughput_per_s", "p50_ms", "p99_ms", "max_ms",
+                                         "all_converged", "evictions")})
+    return {"rates": rows, "capacity_per_s": max(r["throughput_per_s"] for r in rows)}

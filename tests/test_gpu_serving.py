@@ -10,12 +10,19 @@ torch = pytest.importorskip("torch")
 serve = pytest.importorskip("paper_2506_04763_amd.serve")
 
 
+SIZES = [17, 33, 17, 65, 33, 17, 33, 65, 17, 33]
+
+
+def request_spec(r, n):
+    """(n, sigma, seed, correlation, rate, levels) of request r."""
+    return (n, 0.5 + 0.15 * r, 100 + r, 4.0, 0.02 + 0.008 * r, {17: 3, 33: 4, 65: 5}[n])
+
+
 def small_requests():
     reqs = []
-    sizes = [17, 33, 17, 65, 33, 17, 33, 65, 17, 33]
-    for r, n in enumerate(sizes):
-        lv = {17: 3, 33: 4, 65: 5}[n]
-        scn = W.cube_3d(n, 0.5 + 0.15 * r, 100 + r, corr_cells=4.0, rate=0.02 + 0.008 * r, levels=lv)
+    for r, n in enumerate(SIZES):
+        n, sigma, seed, corr, rate, lv = request_spec(r, n)
+        scn = W.cube_3d(n, sigma, seed, corr_cells=corr, rate=rate, levels=lv)
         reqs.append(serve.StageRequest(r, scn, arrival=0.0, rtol=1e-8))
     return reqs
 
@@ -81,3 +88,39 @@ def test_resident_grid_reused():
     srv.shutdown()
     assert not r1.cache_hit and r2.cache_hit
     np.testing.assert_array_equal(r1.x, r2.x)
+
+
+def test_served_results_match_the_oracle_under_eviction():
+    """Six slots under a budget for about two grids, so arenas are carved from the
+    slab again and again and idle grids are evicted: every served 17^3 and 33^3 result
+    and one 65^3 result against the oracle's FP64 solve of the same request (assembled
+    at the request's initial state, solved to 1e-12), per field, at the mixed-precision
+    bound of the parity suite (1e-5).  The oracle solves run in worker processes
+    while the GPU serves."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+
+    from tests import _serving_oracle as SO
+    check = [r for r, n in enumerate(SIZES) if n in (17, 33)] + [SIZES.index(65)]
+    specs = [request_spec(r, SIZES[r]) for r in check]
+    ex = cf.ProcessPoolExecutor(max_workers=min(8, len(specs)), mp_context=mp.get_context("spawn"))
+    futs = {ex.submit(SO.oracle_stage_solution, sp): r for sp, r in zip(specs, check)}
+    reqs = small_requests()
+    need = max(serve.grid_bytes(q.scenario, precision="mixed") for q in reqs)
+    res, st = run(reqs, slots=6, budget=int(need * 2.2))
+    print(f"[serving] served {len(res)} requests, evictions {st['evictions']}, peak {st['peak']}", flush=True)
+    assert st["evictions"] > 0 and all(r.stats["status"] == "TPF_OK" for r in res)
+    worst = 0.0
+    try:
+        for fut in cf.as_completed(futs, timeout=600):
+            r = futs[fut]
+            _, x_ref, info = fut.result()
+            x = res[r].x
+            err = max(np.linalg.norm(x[c::2] - x_ref[c::2]) / np.linalg.norm(x_ref[c::2]) for c in (0, 1))
+            worst = max(worst, err)
+            print(f"[serving] request {r} ({SIZES[r]}^3): iters {res[r].stats['iters']}, "
+                  f"rel_res_true {res[r].stats['rel_res_true']:.2e}, error vs oracle {err:.2e}", flush=True)
+            assert err < 1e-5, (r, err)
+    finally:
+        ex.shutdown(cancel_futures=True)
+    print(f"[serving] worst error against the oracle: {worst:.2e}", flush=True)

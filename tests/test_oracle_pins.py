@@ -676,13 +676,13 @@ def test_error_estimate_closed_form_constant_saturation():
     assert nm.err_ratio(kk, km_s) == pytest.approx(np.sqrt(0.5 * e_s2), rel=1e-12)
 
 
-def test_error_estimate_uses_the_non_wetting_pressure():
-    """Eq. norm_u measures grad p_n.  A homogeneous medium (p_d 1000 Pa, lambda 2) whose
-    saturation is chosen per vertex so that p_c = p_d S_e^(-1/lambda) = 1500 + 750 x is
-    linear: p_n = p_w + p_c is then linear too and its Q1 interpolant exact.  With the
-    same saturation in both states only the pressure term is left:
-    eps = sqrt(1/2) |grad dp_w| / |grad p_w + grad p_c|, whereas a p_w norm would give
-    sqrt(1/2) |grad dp_w| / |grad p_w|."""
+def test_error_estimate_uses_the_convective_pressure():
+    """Eqs. norm_uw/norm_un measure the pressure whose gradient drives the convective
+    fluxes; with the unknowns (p_w, S_n) that is p_w, not p_n = p_w + p_c.  A
+    homogeneous medium (p_d 1000 Pa, lambda 2) whose saturation is chosen per vertex so
+    that p_c = p_d S_e^(-1/lambda) = 1500 + 750 x is linear: with the same saturation in
+    both states only the pressure term is left, eps = sqrt(1/2) |grad dp_w| / |grad p_w|,
+    while a p_n norm would give sqrt(1/2) |grad dp_w| / |grad p_w + grad p_c|."""
     scn = make_scn(2, (9, 5, 1), (2.0, 1.0, 1.0), pd=1000.0, lam=2.0, s_res=(0.1, 0.05))
     x, y, _ = scn.vertex_coords()
     pc = 1500.0 + 750.0 * x                        # 1500 ... 3000 Pa
@@ -694,7 +694,7 @@ def test_error_estimate_uses_the_non_wetting_pressure():
     dg = np.array([5.0, -2.0])
     kk = np.stack([2e5 + gw[0] * x + gw[1] * y, sn], axis=1)
     km = np.stack([2e5 + (gw[0] - dg[0]) * x + (gw[1] - dg[1]) * y, sn], axis=1)
-    gn = gw + np.array([750.0, 0.0])
-    want = np.sqrt(0.5 * np.sum(dg ** 2) / np.sum(gn ** 2))
+    want = np.sqrt(0.5 * np.sum(dg ** 2) / np.sum(gw ** 2))
     assert nm.err_ratio(kk, km) == pytest.approx(want, rel=1e-12)
-    assert abs(nm.err_ratio(kk, km) / (np.sqrt(0.5 * np.sum(dg ** 2) / np.sum(gw ** 2))) - 1) > 0.5
+    gn = gw + np.array([750.0, 0.0])
+    assert abs(nm.err_ratio(kk, km) / np.sqrt(0.5 * np.sum(dg ** 2) / np.sum(gn ** 2)) - 1) > 0.5

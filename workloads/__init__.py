@@ -365,12 +365,12 @@ def default_levels(n: int) -> int:
 
 def cube_3d(n: int, sigma: float, seed: int, corr_cells: float = 8.0, sn0: float = 0.05,
             rate: float = 0.075, layers: bool = False, levels: Optional[int] = None,
-            h: float = 32.0, field_cache: Optional[np.ndarray] = None) -> Scenario:
+            h: float = 32.0, field_cache: Optional[np.ndarray] = None, layer_cells: float = 8.0) -> Scenario:
     """3D unit-cube workload with a log-normal permeability field.
 
     ln K = -25 + sigma * G, G a unit Gaussian field with exponential covariance and
     correlation length `corr_cells` cells; optional three low-permeability slabs
-    (8 cells thick, centred at z = 0.25, 0.5, 0.75, K x 1e-2).  Entry pressure scales
+    (`layer_cells` cells thick, 8 by default, centred at z = 0.25, 0.5, 0.75, K x 1e-2).  Entry pressure scales
     with sqrt(K_ref/K); lambda = 2.5; porosity 0.4.  Gravity along -z, hydrostatic
     p_w from 1e5 Pa at the top, uniform initial S_n.  Dirichlet p_w (hydrostatic) and
     S_n = sn0 on the x = 0 and x = 1 faces; non-wetting injection over [0.4,0.6]^2 on
@@ -385,7 +385,7 @@ def cube_3d(n: int, sigma: float, seed: int, corr_cells: float = 8.0, sn0: float
     if layers:
         zc = (np.arange(ncell) + 0.5) / ncell
         slab = np.zeros(ncell, dtype=bool)
-        thick = 8.0 / ncell
+        thick = float(layer_cells) / ncell
         for zc0 in (0.25, 0.5, 0.75):
             slab |= np.abs(zc - zc0) < 0.5 * thick
         lnk = lnk + np.where(slab, np.log(1e-2), 0.0)[:, None, None]
@@ -420,6 +420,13 @@ def cube_c3() -> Scenario:
 def cube_c4() -> Scenario:
     """257^3 LIMEX workload, sigma_lnK = 1.5 plus three low-K slabs, field seed 4, 6 levels."""
     return cube_3d(257, 1.5, 4, layers=True, levels=6)
+
+
+def cube_c4_scaled(n: int = 33, levels: Optional[int] = None) -> Scenario:
+    """The 257^3 LIMEX recipe (sigma_lnK 1.5, field seed 4, three low-K slabs at
+    z = 0.25, 0.5, 0.75, the same injection patch) on a smaller cube: slabs 2 cells
+    thick, the correlation length the same 1/32 of the domain."""
+    return cube_3d(n, 1.5, 4, corr_cells=(n - 1) / 32.0, layers=True, levels=levels, layer_cells=2.0)
 
 
 # ---------------------------------------------------------------------------------
