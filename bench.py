@@ -12,8 +12,10 @@ Prints one JSON line.  Options:
   --steps K     timed steps (default 10)      --warmup W  untimed steps (default 2)
   --no-cpu      skip the oracle CPU baseline  --no-fp64   skip the FP64 and FP16-coarse comparisons
   --no-serve    skip the continuous-batching serving workload (p50/p99 latency)
-  --no-cases    skip the summaries of the paper's case 1 (Buckley-Leverett errors) and
-                case 5 (257^3 layered run to 128 min) that the default line carries
+  --no-cases    skip the summaries the default line carries of the paper's case 1
+                (Buckley-Leverett errors), case 5 (257^3 layered run to 128 min), case 4
+                (4096 x 2048 cells to 128 min) and the 257^3 log-normal layered cube
+                (20 accepted LIMEX steps)
   --limex-run K run the 257^3 LIMEX workload to K accepted steps (summary line only)
   --case5       Section 5's case 5 at the paper's mesh (257^3 vertices, 33,949,186 DoF)
                 to 128 minutes of simulated time: total time, LIMEX steps and time per
@@ -21,6 +23,9 @@ Prints one JSON line.  Options:
                 case5_strong (summary line only)
   --case4       the same for Section 5's 2D case 4 at the mesh of Table case4_strong
                 (4096 x 2048 cells, 16,789,506 DoF)
+  --case4-compare  Table case4_2: case 4 on 256 x 128 cells for 10 years (injection for
+                the first 2) with fixed implicit Euler steps of one day (Newton) against
+                adaptive LIMEX: total time, steps, Newton and linear iterations
   --case1       the Buckley-Leverett validation (Section 5, Case 1) on 64 ... 512
                 elements: error norms against the Welge solution, convergence rates,
                 LIMEX step counts and run times beside the paper's Table error1
@@ -63,33 +68,50 @@ def algorithmic_bytes(cls: str, N: int, Nc_levels) -> float:
     return float("nan")
 
 
-def cpu_baseline(iters_full, n_sample=49):
-    """The FP64 oracle, as it stands, on a bounded sample: one full stage (residual,
-    assembly by complex-step Jacobian, Galerkin hierarchy, BiCGSTAB to 1e-8) of the same
-    recipe on a 33^3 grid, single-threaded.  Setup time and time per BiCGSTAB iteration
-    are scaled linearly in DoF to 129^3, with the iteration count the 129^3 solve needs."""
+def cpu_baseline(iters_full, n_small=25):
+    """The FP64 oracle, as it stands, on a bounded sample of the benchmark stage,
+    single-threaded.  The oracle's stage is assembly by complex-step differentiation
+    (54 complex residual passes at 129^3, one per colour and component) plus the
+    Galerkin hierarchy and BiCGSTAB; its cost grows faster than the grid (large arrays).
+    Measured on the 129^3 workload itself: one residual F(u0).  Measured on a
+    n_small^3 grid of the same recipe: the ratio of a complex pass to a real residual,
+    and the hierarchy and per-iteration times, which are scaled by the DoF ratio with
+    the iteration count of the 129^3 solve."""
     from threadpoolctl import threadpool_limits
 
     import workloads as W
     from oracle import stage as ST
-    scn = W.cube_3d(n_sample, 2.0, 3, levels=4)
+    big = W.cube_c3()
+    small = W.cube_3d(n_small, 2.0, 3, levels=3)
     with threadpool_limits(1):
+        st = ST.Stage(big)
         t0 = time.perf_counter()
-        st = ST.Stage(scn)
-        u = scn.u0.ravel()
-        f = st.residual(u)
-        st.assemble(u, 32.0)
+        st.residual(big.u0.ravel())
+        t_res = time.perf_counter() - t0
+        sm = ST.Stage(small)
+        u = small.u0.ravel()
+        t0 = time.perf_counter()
+        f = sm.residual(u)
         t1 = time.perf_counter()
-        x, info = st.solve(f, rtol=1e-8)
+        frozen = sm.fv.frozen_matrices(u.reshape(-1, 2))
         t2 = time.perf_counter()
-    scale = (129 ** 3) / (n_sample ** 3)
-    t_iter = (t2 - t1) / max(info["iters"], 1)
-    t_full = scale * ((t1 - t0) + t_iter * iters_full)
+        sm.assemble(u, 32.0, frozen=frozen)
+        t3 = time.perf_counter()
+        x, info = sm.solve(f, rtol=1e-8)
+        t4 = time.perf_counter()
+    passes = 2 * 27  # complex residual passes of the 3D Jacobian
+    ratio = (t2 - t1) / passes / max(t1 - t0, 1e-9)  # one complex pass in units of one real residual
+    scale = big.nverts / small.nverts
+    t_setup = t_res * (1.0 + passes * ratio) + scale * (t3 - t2)
+    t_iter = scale * (t4 - t3) / max(info["iters"], 1)
+    t_full = t_setup + t_iter * iters_full
     return {"value": 1.0 / t_full, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle stage on the {n_sample}^3 grid of the same recipe (sigma_lnK 2, seed 3): setup "
-                      f"(residual + complex-step assembly + hierarchy) {t1 - t0:.2f} s, BiCGSTAB {t2 - t1:.2f} s for "
-                      f"{info['iters']} iterations; scaled by the DoF ratio {scale:.1f} to 129^3 with the "
-                      f"{iters_full} iterations the 129^3 solve takes: {t_full:.0f} s per stage"}
+            "sample": f"oracle (FP64 NumPy/SciPy, one thread) on the 129^3 stage: one residual F(u0) measured on "
+                      f"the 129^3 workload ({t_res:.1f} s); the Jacobian as {passes} complex passes of "
+                      f"{ratio:.2f} residuals each (ratio measured on {n_small}^3 of the same recipe); hierarchy "
+                      f"{t3 - t2:.2f} s and BiCGSTAB {(t4 - t3) / max(info['iters'], 1):.3f} s per iteration at "
+                      f"{n_small}^3 scaled by the DoF ratio {scale:.0f}, {iters_full} iterations: "
+                      f"{t_full:.0f} s per stage"}
 
 
 def run(args):
@@ -227,14 +249,21 @@ def run(args):
                              "paper_L2": [r["paper_limex"]["L2"] for r in c1["rows"]]}
         except Exception as e:  # reported, never fatal to the benchmark line
             line["case1"] = {"error": repr(e)}
-        try:
-            c5 = layered_run("case5")
-            line["case5"] = {k: c5[k] for k in ("dof", "reached_t_end", "T_total_s", "N_limex", "t_limex_s",
-                                                 "N_linear_solves", "t_linear_solve_s", "bicgstab_iterations",
-                                                 "unconverged_solves")}
-            line["case5"]["paper_256pe"] = c5["paper_table_case5_strong"]["256"]
+        keys = ("dof", "reached_t_end", "t_end_s", "T_total_s", "N_limex", "t_limex_s", "N_linear_solves",
+                "t_linear_solve_s", "bicgstab_iterations", "unconverged_solves", "sn_max")
+        for case, pe in (("case5", "256"), ("case4", "64")):
+            try:
+                c = layered_run(case)
+                line[case] = {k: c[k] for k in keys}
+                line[case][f"paper_{pe}pe"] = c[f"paper_table_{case}_strong"][pe]
+            except Exception as e:
+                line[case] = {"error": repr(e)}
+        try:  # the 257^3 layered log-normal cube, 20 accepted k = 3 steps
+            c4 = limex_run(20)
+            line["cube257_limex"] = {k: c4[k] for k in c4 if k != "dt_sequence"}
+            line["cube257_limex"]["dt_min_s"] = min(c4["dt_sequence"])
         except Exception as e:
-            line["case5"] = {"error": repr(e)}
+            line["cube257_limex"] = {"error": repr(e)}
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(mixed["iters"][-1])
     return line
@@ -244,37 +273,32 @@ def limex_run(accepted_target=20, max_attempts=80):
     """The 257^3 layered-cube LIMEX run: adaptive steps with k = 3 extrapolation
     stages from tau0 = 32 s (TOL 5e-3, safety 0.75, tau_max 100 d), FP32 multigrid
     (6 levels) inside FP64 BiCGSTAB to 1e-8, until `accepted_target` steps are
-    accepted.  Prints one progress line per attempted step (stderr) and returns a
-    summary."""
+    accepted, with the consistency rule for the pressure (driver.limex_run).  Prints
+    one progress line per attempted step (stderr) and returns a summary."""
     import torch
 
     import paper_2506_04763_amd as tpf
     import workloads as W
+    from paper_2506_04763_amd import driver as DR
     scn = W.cube_c4()
     g = tpf.Grid(scn, precision="mixed", levels=6, limex_stages=3)
     u = g.initial_state()
-    t, dt = 0.0, 32.0
-    steps = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    while sum(1 for s in steps if s["accepted"]) < accepted_target and len(steps) < max_attempts:
-        ts = time.perf_counter()
-        acc, t, dt_next, st = g.limex_step(u, t, dt, stages=3, tol=5e-3, safety=0.75, dt_max=8.64e6, rtol=1e-8)
-        torch.cuda.synchronize()
-        rec = dict(accepted=bool(acc), dt=dt, eps=st["eps"], dt_next=dt_next, solves=st["solves"],
-                   iters=st["iters_total"], unconverged=st["unconverged"], seconds=time.perf_counter() - ts)
-        steps.append(rec)
-        print(json.dumps({"limex_step": len(steps), "t": t, **rec}), file=sys.stderr, flush=True)
-        dt = dt_next
+    def log(rec):
+        print(json.dumps({"limex_step": rec["attempt"], **rec}), file=sys.stderr, flush=True)
+
+    res = DR.limex_run(lambda t: (g, float("inf")), u, 0.0, float("inf"), 32.0, 3, 5e-3, 0.75, 8.64e6, 1e-8,
+                       maxit=500, max_attempts=max_attempts, on_step=log, max_accepted=accepted_target)
+    torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     g.close()
-    acc = [s for s in steps if s["accepted"]]
+    att = res["accepted"] + res["rejected"]
     return {"workload": "cube257_layered_sigma1.5_seed4_limex_k3", "vertices": list(scn.n), "dof": 2 * scn.nverts,
-            "accepted": len(acc), "rejected": len(steps) - len(acc), "t_end_s": t, "wall_s": round(wall, 2),
-            "s_per_attempted_step": round(wall / max(len(steps), 1), 3),
-            "solves": sum(s["solves"] for s in steps), "bicgstab_iterations": sum(s["iters"] for s in steps),
-            "unconverged_solves": sum(s["unconverged"] for s in steps),
-            "dt_sequence": [round(s["dt"], 3) for s in steps]}
+            "accepted": res["accepted"], "rejected": res["rejected"], "t_end_s": res["t"], "wall_s": round(wall, 2),
+            "s_per_attempted_step": round(wall / max(att, 1), 3), "solves": res["solves"],
+            "bicgstab_iterations": res["bicgstab_iterations"], "unconverged_solves": res["unconverged"],
+            "projections": res["projections"], "dt_sequence": [round(x, 6) for x in res["dt_sequence"]]}
 
 
 # Table case5_strong: PE -> (T_total s, LIMEX steps accepted + rejected, t_LIMEX s, N_linear, t_linear s)
@@ -306,40 +330,137 @@ def layered_run(case="case5", max_attempts=400, precision="mixed", rtol=1e-8, ma
     u = g.initial_state()
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t_setup
-    t, dt = 0.0, m["dt0"]
-    steps = []
+    from paper_2506_04763_amd import driver as DR
+
+    def log(rec):
+        print(json.dumps({f"{case}_step": rec["attempt"], **rec}), file=sys.stderr, flush=True)
+
     t0 = time.perf_counter()
-    while t < m["t_end"] * (1 - 1e-14) and len(steps) < max_attempts:
-        dt = min(dt, m["t_end"] - t)
-        ts = time.perf_counter()
-        acc, t, dt_next, st = g.limex_step(u, t, dt, stages=m["stages"], tol=m["tol"], safety=m["safety"],
-                                           dt_max=m["dt_max"], rtol=rtol, maxit=maxit)
-        torch.cuda.synchronize()
-        rec = dict(accepted=bool(acc), t=t, dt=dt, eps=st["eps"], solves=st["solves"], iters=st["iters_total"],
-                   unconverged=st["unconverged"], seconds=time.perf_counter() - ts)
-        steps.append(rec)
-        print(json.dumps({f"{case}_step": len(steps), **rec}), file=sys.stderr, flush=True)
-        dt = dt_next
+    res = DR.limex_run(lambda t: (g, float("inf")), u, 0.0, m["t_end"], m["dt0"], m["stages"], m["tol"], m["safety"],
+                       m["dt_max"], rtol, maxit=maxit, max_attempts=max_attempts, on_step=log)
+    torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     sn_max = float(u.reshape(-1, 2)[:, 1].max())
     g.close()
-    acc = sum(1 for s in steps if s["accepted"])
-    solves = sum(s["solves"] for s in steps)
-    iters = sum(s["iters"] for s in steps)
+    t, acc = res["t"], res["accepted"]
+    att = acc + res["rejected"]
+    solves, iters = res["solves"], res["bicgstab_iterations"]
     name = ("case5_257^3_layered_poly_kr_point_injection_128min" if case == "case5"
             else "case4_4097x2049_layered_poly_kr_point_injection_128min")
     return {"workload": name, "dof": 2 * scn.nverts,
             "levels": scn.levels, "precision": precision, "rtol": rtol, "maxit": maxit, "stages": m["stages"],
             "t_end_s": t, "reached_t_end": bool(t >= m["t_end"] * (1 - 1e-14)),
             "T_total_s": round(wall, 2), "setup_s": round(setup_s, 2),
-            "N_limex": f"{acc}+{len(steps) - acc}", "t_limex_s": round(wall / max(len(steps), 1), 3),
+            "N_limex": f"{acc}+{res['rejected']}", "t_limex_s": round(wall / max(att, 1), 3),
             "N_linear_solves": solves, "t_linear_solve_s": round(wall / max(solves, 1), 4),
-            "bicgstab_iterations": iters, "unconverged_solves": sum(s["unconverged"] for s in steps),
-            "sn_max": sn_max,
+            "bicgstab_iterations": iters, "unconverged_solves": res["unconverged"],
+            "projections": res["projections"], "sn_max": sn_max,
             f"paper_table_{case}_strong": {str(k): {"T_total_s": v[0], "N_limex": v[1],
                                                     "t_limex_s": round(v[2], 3), "N_linear": v[3],
                                                     "t_linear_s": v[4]} for k, v in paper.items()},
-            "dt_sequence": [round(s["dt"], 3) for s in steps]}
+            "dt_sequence": [round(x, 3) for x in res["dt_sequence"]]}
+
+
+# Table case4_2 (256 x 128 cells, T = 10 years): scheme -> (T_total s, time steps, N_nonlinear, N_linear)
+PAPER_CASE4_2 = {"implicit_euler": (3938.76, "3650", 176596, 375093), "limex": (275.28, "6206+75", None, 58093)}
+
+
+def case4_compare(cells_x=256, years=10.0, inj_years=2.0, ie_dt=86400.0, precision="mixed", lin_rtol=1e-6,
+                  max_limex_attempts=40000, schemes=("limex", "implicit_euler"), wall_limit_s=1000.0,
+                  max_newton=50):
+    """Table case4_2 of Section 5: case 4 on 256 x 128 cells for 10 years with the
+    injection running for the first 2, once with fixed implicit Euler steps of one day
+    (Newton, defect tolerances 1e-8 absolute / 1e-6 relative) and once with adaptive
+    LIMEX (k = 3, TOL 5e-3, safety 0.75, tau0 32 s, tau_max 100 d); both solve their
+    linear systems with BiCGSTAB + GMG to 1e-6 relative (the paper's relative linear
+    tolerance).  The source switches off by moving the state to a second grid without
+    it.  Reports total time, time steps, Newton iterations and linear iterations
+    beside the paper's table.  A scheme still running after wall_limit_s stops and
+    reports the time it reached.  Each scheme's record is also printed to stdout as
+    soon as it ends; progress lines go to stderr."""
+    import copy
+
+    import numpy as np
+    import torch
+
+    import paper_2506_04763_amd as tpf
+    import workloads as W
+    scn_on = W.case4(cells_x)
+    scn_off = copy.deepcopy(scn_on)
+    scn_off.vertex_source = np.zeros_like(scn_on.vertex_source)
+    t_inj, t_end = inj_years * 365 * 86400.0, years * 365 * 86400.0
+    m = scn_on.meta
+    out = {"workload": f"case4_{cells_x}x{cells_x // 2}_10y_injection_2y", "dof": 2 * scn_on.nverts,
+           "levels": scn_on.levels, "precision": precision, "linear_rtol": lin_rtol,
+           "paper_table_case4_2": {k: {"T_total_s": v[0], "N_time_step": v[1], "N_nonlinear": v[2], "N_linear": v[3]}
+                                   for k, v in PAPER_CASE4_2.items()}}
+    grids = [tpf.Grid(s_, precision=precision, limex_stages=m["stages"]) for s_ in (scn_on, scn_off)]
+    if "limex" in schemes:
+        from paper_2506_04763_amd import driver as DR
+        u = grids[0].initial_state()
+
+        def grid_at(t):  # the injecting grid up to t_inj, then the one without the source
+            return (grids[0], t_inj) if t < t_inj * (1 - 1e-14) else (grids[1], t_end)
+
+        def log(rec):
+            if rec["attempt"] % 500 == 0 or rec["projected"]:
+                print(json.dumps({"case4_compare_limex": rec["attempt"], "t_days": rec["t"] / 86400,
+                                  "dt": rec["dt"], "projected": rec["projected"]}), file=sys.stderr, flush=True)
+
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        t_wall = time.perf_counter() + wall_limit_s
+
+        res = DR.limex_run(grid_at, u, 0.0, t_end, m["dt0"], m["stages"], m["tol"], m["safety"],
+                           m["dt_max"], lin_rtol, maxit=200, max_attempts=max_limex_attempts, on_step=log,
+                           stop=lambda: time.perf_counter() >= t_wall)
+        torch.cuda.synchronize()
+        out["limex"] = {"T_total_s": round(time.perf_counter() - t0, 2),
+                        "N_time_step": f"{res['accepted']}+{res['rejected']}",
+                        "reached_t_end": bool(res["t"] >= t_end * (1 - 1e-14)), "t_end_days": res["t"] / 86400.0,
+                        "N_linear_solves": res["solves"], "N_linear": res["bicgstab_iterations"],
+                        "unconverged_solves": res["unconverged"], "projections": res["projections"],
+                        "projection_newton": res["projection_newton"],
+                        "projection_linear": res["projection_linear_iters"],
+                        "sn_max": float(u.reshape(-1, 2)[:, 1].max())}
+        print(json.dumps({"case4_compare_record": "limex", **out["limex"]}), flush=True)
+    if "implicit_euler" in schemes:
+        u = grids[0].initial_state()
+        t = 0.0
+        steps = newton = lin = solves = fails = 0
+        n_steps = int(round(t_end / ie_dt))
+        todo = [ie_dt] * n_steps
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        t_wall = time.perf_counter() + wall_limit_s
+        while todo and time.perf_counter() < t_wall:
+            tau = todo.pop(0)
+            g = grids[0] if t < t_inj * (1 - 1e-12) else grids[1]
+            ok, st = g.ie_step(u, tau, atol=1e-8, rtol=1e-6, lin_rtol=lin_rtol, maxit=200, max_newton=max_newton)
+            newton += st["newton"]
+            lin += st["linear_iters"]
+            solves += st["linear_solves"]
+            if not ok:  # repeated as two half steps
+                fails += 1
+                todo[:0] = [0.5 * tau, 0.5 * tau]
+                continue
+            t += tau
+            steps += 1
+            if steps % 250 == 0:
+                print(json.dumps({"case4_compare_ie": steps, "t_days": t / 86400, "newton": newton}),
+                      file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        out["implicit_euler"] = {"T_total_s": round(time.perf_counter() - t0, 2), "N_time_step": steps,
+                                 "reached_t_end": not todo, "step_failures": fails, "N_nonlinear": newton,
+                                 "N_linear": lin, "N_linear_solves": solves, "t_end_days": t / 86400.0,
+                                 "max_newton": max_newton, "sn_max": float(u.reshape(-1, 2)[:, 1].max())}
+        print(json.dumps({"case4_compare_record": "implicit_euler", **out["implicit_euler"]}), flush=True)
+    for g in grids:
+        g.close()
+    if "limex" in out and "implicit_euler" in out:
+        out["ie_over_limex_time"] = round(out["implicit_euler"]["T_total_s"] / max(out["limex"]["T_total_s"], 1e-9), 2)
+        out["ie_over_limex_linear"] = round(out["implicit_euler"]["N_linear"] / max(out["limex"]["N_linear"], 1), 2)
+    return out
 
 
 def case1_run(elements=(64, 128, 256, 512)):
@@ -447,12 +568,18 @@ def main():
                     help="run Section 5's case 5 at 257^3 to 128 minutes instead of the benchmark")
     ap.add_argument("--case4", action="store_true",
                     help="run Section 5's case 4 at 4096 x 2048 cells to 128 minutes instead of the benchmark")
+    ap.add_argument("--case4-compare", action="store_true",
+                    help="Table case4_2: implicit Euler + Newton against LIMEX on case 4 (256 x 128 cells, 10 years)")
+    ap.add_argument("--schemes", default="limex,implicit_euler", help="schemes of --case4-compare")
     args = ap.parse_args()
     if args.counters:
         counters_driver()
         return
     if args.case1:
         print(json.dumps(case1_run()), flush=True)
+        return
+    if args.case4_compare:
+        print(json.dumps(case4_compare(schemes=tuple(args.schemes.split(",")))), flush=True)
         return
     if args.case5 or args.case4:
         print(json.dumps(layered_run("case5" if args.case5 else "case4")), flush=True)

@@ -297,6 +297,23 @@ tpf_status tpf_storage(tpf_grid *g, const double *u, double *m, tpf_stream strea
 tpf_status tpf_ie_step(tpf_grid *g, double *u, double tau, const tpf_newton_opts *opts, tpf_newton_stats *stats,
                        tpf_stream stream);
 
+/* Makes the pressure of u (device double[2N], in/out) consistent with its saturation.
+ * With incompressible phases the pressure column of M(u) u' = F(u) (Section 4)
+ * carries no storage: p is an algebraic unknown, and an extrapolated LIMEX state can
+ * violate the discrete volume balance by more than one linearised correction with the
+ * Jacobian frozen at that state restores; the stages of the next step then differ by
+ * an amount that does not vanish with the step (the paper does not discuss this).
+ * Newton at fixed saturation on the stage system with a vanishing step h_p > 0:
+ * assemble A(u; h_p) and F(u), solve A delta = F(u) (BiCGSTAB + GMG to
+ * opts->lin_rtol), p += delta_p with S untouched.  As h_p -> 0 that is the Newton step
+ * of F_w/rho_w + F_n/rho_n = 0 (the storages cancel), which holds at the end up to
+ * O(h_p).  Stops when max|delta_p| <= max(opts->atol, opts->rtol max|p|) (Pa);
+ * opts->max_halvings is unused.  stats->defect0 / defect: the first and last
+ * max|delta_p|.  Leaves A(u; h_p) assembled.  Returns TPF_OK, TPF_NOT_CONVERGED (u
+ * unchanged) or an error (u unchanged). */
+tpf_status tpf_project_pressure(tpf_grid *g, double *u, double h_p, const tpf_newton_opts *opts,
+                                tpf_newton_stats *stats, tpf_stream stream);
+
 /* ---- inspection hooks (used by the parity tests and the benchmark) ---------- */
 
 /* Number of multigrid levels and vertices per axis of a level. */

@@ -227,6 +227,18 @@ class Grid:
         L.check(status, "tpf_ie_step", soft_ok=True)
         return status == TPF_OK, st.as_dict()
 
+    def project_pressure(self, u, h_p=1e-6, rtol=1e-10, atol=0.0, lin_rtol=1e-10, max_newton=20, maxit=500):
+        """Newton at fixed saturation onto the volume-balance constraint, in place on the
+        device tensor u (pressure components only); returns (converged, stats)."""
+        if not (isinstance(u, self.torch.Tensor) and u.device == self.device and u.dtype == self.torch.float64):
+            raise TypeError("u must be a float64 tensor on the grid's device")
+        o = L.NewtonOpts(int(max_newton), 0, int(maxit), 0, float(atol), float(rtol), float(lin_rtol))
+        st = L.NewtonStats()
+        status = self.lib.tpf_project_pressure(self.handle, _ptr(u), float(h_p), C.byref(o), C.byref(st),
+                                               self._sptr())
+        L.check(status, "tpf_project_pressure", soft_ok=True)
+        return status == TPF_OK, st.as_dict()
+
     # -- inspection ------------------------------------------------------------------
     def level_dims(self, level):
         n = (C.c_int32 * 3)()

@@ -550,6 +550,19 @@ tpf_status tpf_ie_step(tpf_grid *g, double *u, double tau, const tpf_newton_opts
   return ie_step(g, u, tau, opts, stats, reinterpret_cast<hipStream_t>(stream));
 }
 
+tpf_status tpf_project_pressure(tpf_grid *g, double *u, double h_p, const tpf_newton_opts *opts,
+                                tpf_newton_stats *stats, tpf_stream stream) {
+  g_err[0] = 0;
+  if (!g || !u || !opts) { set_error("NULL argument"); return TPF_EINVAL; }
+  if (!(h_p > 0.0) || !std::isfinite(h_p)) { set_error("h_p must be positive and finite"); return TPF_EINVAL; }
+  if (opts->max_newton < 1 || opts->maxit < 1 || !(opts->atol >= 0.0) || !(opts->rtol >= 0.0) ||
+      !(opts->lin_rtol > 0.0)) {
+    set_error("invalid Newton options");
+    return TPF_EINVAL;
+  }
+  return project_pressure(g, u, h_p, opts, stats, reinterpret_cast<hipStream_t>(stream));
+}
+
 int32_t tpf_levels(const tpf_grid *g) { return g ? g->L : 0; }
 
 tpf_status tpf_level_dims(const tpf_grid *g, int32_t level, int32_t n_out[3]) {

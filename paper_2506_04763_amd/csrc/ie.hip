@@ -41,6 +41,57 @@ __global__ void __launch_bounds__(1024) k_sum1(const double *__restrict__ part, 
   }
 }
 
+// p += dp on the pressure components only (S untouched); block maxima of |dp| and of
+// the updated |p| (grid-stride)
+__global__ void __launch_bounds__(BS) k_add_p(long long N, double *__restrict__ u, const double *__restrict__ d,
+                                              double *__restrict__ part) {
+  __shared__ double sm[2][BS / 64];
+  double md = 0.0, mp = 0.0;
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < N; v += (long long)gridDim.x * blockDim.x) {
+    const double dp = d[2 * v];
+    const double p = u[2 * v] + dp;
+    u[2 * v] = p;
+    md = fmax(md, fabs(dp));
+    mp = fmax(mp, fabs(p));
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    md = fmax(md, __shfl_down(md, off, 64));
+    mp = fmax(mp, __shfl_down(mp, off, 64));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    sm[0][threadIdx.x >> 6] = md;
+    sm[1][threadIdx.x >> 6] = mp;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    double m = 0.0;
+#pragma unroll
+    for (int w = 0; w < BS / 64; ++w) m = fmax(m, sm[threadIdx.x][w]);
+    part[(long long)threadIdx.x * gridDim.x + blockIdx.x] = m;
+  }
+}
+
+// out[0], out[1] = maxima of the two rows of nblk partials (one block)
+__global__ void __launch_bounds__(1024) k_max2(const double *__restrict__ part, unsigned nblk,
+                                               double *__restrict__ out) {
+  __shared__ double sm[2][16];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    double m = 0.0;
+    for (unsigned b = threadIdx.x; b < nblk; b += 1024) m = fmax(m, part[(long long)k * nblk + b]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_down(m, off, 64));
+    if ((threadIdx.x & 63) == 0) sm[k][threadIdx.x >> 6] = m;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    double m = 0.0;
+    for (int w = 0; w < 16; ++w) m = fmax(m, sm[threadIdx.x][w]);
+    out[threadIdx.x] = m;
+  }
+}
+
 #define TPF_TRY(x)                   \
   do {                               \
     tpf_status st_ = (x);            \
@@ -131,6 +182,59 @@ tpf_status ie_step(tpf_grid *g, double *u, double tau, const tpf_newton_opts *o,
   }
   ns.converged = ok ? 1 : 0;
   if (!ok) TPF_TRY(copy_vec(u, g->u0, n, s));  // a failed step leaves u unchanged
+  TPF_HIP(hipStreamSynchronize(s));
+  if (st) *st = ns;
+  if (hard != TPF_OK) return hard;
+  return ok ? TPF_OK : TPF_NOT_CONVERGED;
+}
+
+// Consistent pressure for the saturation of u: Newton at fixed S on the stage system
+// with a vanishing step h_p (A(u; h_p) delta = F(u), p += delta_p).  With incompressible
+// phases the pressure column carries no storage, so p is the algebraic unknown of
+// M(u) u' = F(u); as h_p -> 0 the pressure update is the Newton step of the volume
+// balance F_w/rho_w + F_n/rho_n = 0, in which the two storages cancel.
+tpf_status project_pressure(tpf_grid *g, double *u, double h_p, const tpf_newton_opts *o, tpf_newton_stats *st,
+                            hipStream_t s) {
+  const long long n = 2 * g->P.N;
+  tpf_newton_stats ns{};
+  TPF_TRY(copy_vec(g->u0, u, n, s));  // restored if Newton fails
+  bool ok = false;
+  tpf_status hard = TPF_OK;
+  while (ns.newton < o->max_newton) {
+    TPF_TRY(launch_assemble(g, u, h_p, g->f0, s));
+    TPF_TRY(build_hierarchy(g, s));
+    g->assembled = true;
+    g->has_f0 = true;
+    tpf_solve_stats ls{};
+    const tpf_status rs = bicgstab(g, g->f0, g->xb, o->lin_rtol, o->maxit, &ls, s);
+    ns.linear_iters += ls.iters;
+    ++ns.linear_solves;
+    if (rs < 0) {
+      if (rs != TPF_EBREAKDOWN || !std::isfinite(ls.fnorm)) hard = rs;
+      break;
+    }
+    k_add_p<<<RED_BLOCKS, BS, 0, s>>>(g->P.N, u, g->xb, g->part);
+    TPF_LAUNCH_CHECK();
+    k_max2<<<1, 1024, 0, s>>>(g->part, RED_BLOCKS, g->scal + S_PROJ_DP);
+    TPF_LAUNCH_CHECK();
+    TPF_HIP(hipMemcpyAsync(g->hscal, g->scal, NSCAL * sizeof(double), hipMemcpyDeviceToHost, s));
+    TPF_HIP(hipStreamSynchronize(s));
+    const double dp = g->hscal[S_PROJ_DP], pmax = g->hscal[S_PROJ_P];
+    ++ns.newton;
+    if (ns.newton == 1) ns.defect0 = dp;
+    ns.defect = dp;
+    if (!std::isfinite(dp)) {
+      set_error("pressure projection: non-finite update at Newton iteration %d", ns.newton);
+      hard = TPF_EBREAKDOWN;
+      break;
+    }
+    if (dp <= fmax(o->atol, o->rtol * pmax)) {
+      ok = true;
+      break;
+    }
+  }
+  ns.converged = ok ? 1 : 0;
+  if (!ok) TPF_TRY(copy_vec(u, g->u0, n, s));
   TPF_HIP(hipStreamSynchronize(s));
   if (st) *st = ns;
   if (hard != TPF_OK) return hard;

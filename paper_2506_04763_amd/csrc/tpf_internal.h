@@ -22,7 +22,7 @@ constexpr int NSCAL = 32;         // device scalars of the Krylov solver
 // Scalars of the Krylov recurrence kept on the device (indices into g->scal).
 enum Scal {
   S_RHO = 0, S_RHO_OLD, S_ALPHA, S_OMEGA, S_BETA, S_RV, S_TS, S_TT, S_RR, S_FF, S_WW,
-  S_NORM_A, S_NORM_B, S_NORM_C, S_NORM_D, S_IE_RR, S_COUNT
+  S_NORM_A, S_NORM_B, S_NORM_C, S_NORM_D, S_IE_RR, S_PROJ_DP, S_PROJ_P, S_COUNT
 };
 
 // Physical and geometric constants passed by value to every kernel.
@@ -220,6 +220,8 @@ tpf_status bicgstab(tpf_grid *g, const double *f, double *x, double rtol, int ma
 // ---- ie.hip ----
 tpf_status ie_step(tpf_grid *g, double *u, double tau, const tpf_newton_opts *o, tpf_newton_stats *st,
                    hipStream_t s);
+tpf_status project_pressure(tpf_grid *g, double *u, double h_p, const tpf_newton_opts *o, tpf_newton_stats *st,
+                            hipStream_t s);
 
 // ---- shared small kernels (krylov.hip) ----
 tpf_status fill_zero(double *p, long long n, hipStream_t s);

@@ -144,3 +144,73 @@ def test_limex_layered_cube_step_collapse_matches_oracle():
     assert not any(acc[first_rej:])  # rejected from then on
     tail_eps = [l[1] for l in log[first_rej + 1:]]
     assert min(tail_eps) > 5e-3 and max(tail_eps) / min(tail_eps) < 2.0  # eps does not fall with tau
+
+
+def test_pressure_projection_parity():
+    """tpf_project_pressure against the oracle's projection from the same perturbed
+    lens state: the same Newton count, S untouched, p within 1e-9 of the oracle's
+    (relative to the pressure change), and the volume balance of the result."""
+    scn = W.lens_2d(17, 9)
+    scn.levels = 3
+    u0 = W.perturbed_state(scn, 12, dp=80.0, sn_lo=0.05, sn_hi=0.5)
+    ref = ST.Stage(scn)
+    uo, info = ref.project_pressure(u0.ravel(), rtol=1e-10)
+    g = tpf.Grid(scn, precision="fp64")
+    u = torch.as_tensor(u0.ravel().copy(), device="cuda")
+    ok, st = g.project_pressure(u, rtol=1e-10, lin_rtol=1e-12)
+    ug = u.cpu().numpy().reshape(-1, 2)
+    g.close()
+    print(f"[project] gpu {st} oracle {info['newton']} {info['history']}", flush=True)
+    assert ok and info["converged"] and st["newton"] == info["newton"]
+    np.testing.assert_array_equal(ug[:, 1], u0[:, 1])
+    d = np.linalg.norm(ug[:, 0] - uo.reshape(-1, 2)[:, 0]) / np.linalg.norm(uo.reshape(-1, 2)[:, 0] - u0[:, 0])
+    assert d < 1e-9, d
+
+
+def oracle_driver(scn, attempts, stages, dt0, tol=5e-3, safety=0.75, dt_max=8.64e6):
+    """The oracle's LIMEX loop with its own copy of the consistency rule."""
+    ref = ST.Stage(scn)
+    rule = ST.StallRule()
+    u = scn.u0.ravel().copy()
+    t, dt = 0.0, dt0
+    log = []
+    for _ in range(attempts):
+        out, info = ref.limex_step(u, dt, stages=stages, tol=tol, safety=safety, dt_max=dt_max, rtol=1e-10)
+        tau = dt
+        if info["accepted"]:
+            u, t = out, t + dt
+        proj = None
+        if rule.after_step(info["accepted"], tau, info["eps"]):
+            u, pin = ref.project_pressure(u, rtol=1e-10)
+            proj = pin["newton"]
+        log.append((info["accepted"], tau, info["eps"], proj))
+        dt = info["dt_next"]
+    return u, t, log
+
+
+def test_layered_cube_run_with_the_consistency_rule_matches_oracle():
+    """The 17^3 layered recipe over 20 attempted k = 3 steps with the consistency rule
+    (projection when eps stalls as the step shrinks) on both sides: the same accept /
+    reject sequence and projections, eps to 1e-6, the final state to 1e-8; the run no
+    longer collapses (it passes the step where the plain run stalls)."""
+    from paper_2506_04763_amd import driver as DR
+    scn = W.cube_c4_scaled(17)
+    uo, to, olog = oracle_driver(scn, 20, 3, 32.0)
+    g = tpf.Grid(scn, precision="fp64", limex_stages=3)
+    u = torch.as_tensor(scn.u0.ravel().copy(), device="cuda")
+    glog = []
+    res = DR.limex_run(lambda t: (g, float("inf")), u, 0.0, float("inf"), 32.0, 3, 5e-3, 0.75, 8.64e6, 1e-10,
+                       maxit=400, max_attempts=20, on_step=glog.append)
+    ug = u.cpu().numpy()
+    g.close()
+    for k, (o, gr) in enumerate(zip(olog, glog)):
+        print(f"[consistency] {k}: oracle acc={o[0]} eps={o[2]:.4g} proj={o[3]} | gpu acc={gr['accepted']} "
+              f"eps={gr['eps']:.4g} proj={gr['projected']}", flush=True)
+        assert o[0] == gr["accepted"]
+        assert gr["eps"] == pytest.approx(o[2], rel=1e-6)
+        assert (o[3] is None) == (gr["projected"] is None)
+        if o[3] is not None:
+            assert gr["projected"]["converged"] and gr["projected"]["newton"] == o[3]
+    assert res["t"] == pytest.approx(to, rel=1e-10)
+    assert res["projections"] >= 1 and to > 250.0   # beyond the 167 s where the plain run stalls
+    assert per_field(ug, uo) < 1e-8

@@ -698,3 +698,49 @@ def test_error_estimate_uses_the_convective_pressure():
     assert nm.err_ratio(kk, km) == pytest.approx(want, rel=1e-12)
     gn = gw + np.array([750.0, 0.0])
     assert abs(nm.err_ratio(kk, km) / np.sqrt(0.5 * np.sum(dg ** 2) / np.sum(gn ** 2)) - 1) > 0.5
+
+
+# ---------------------------------------------------------------------------------
+# Consistency of the algebraic pressure (reading of the index-1 structure of
+# M(u) u' = F(u), Section 4).
+# ---------------------------------------------------------------------------------
+def test_pressure_projection_satisfies_the_volume_balance():
+    """After the projection the volume balance F_w/rho_w + F_n/rho_n vanishes at every
+    vertex without a Dirichlet component (the incompressible constraint: the two
+    storages cancel in it), the saturation is untouched bit for bit, and Newton
+    converges fast (quadratically once close)."""
+    scn = W.lens_2d(17, 9)
+    scn.levels = 3
+    st = ST.Stage(scn)
+    u0 = W.perturbed_state(scn, 12, dp=80.0, sn_lo=0.05, sn_hi=0.5)
+    F0 = st.residual(u0.ravel()).reshape(-1, 2)
+    vol0 = F0[:, 0] / scn.rho[0] + F0[:, 1] / scn.rho[1]
+    u, info = st.project_pressure(u0.ravel(), rtol=1e-12)
+    u = u.reshape(-1, 2)
+    assert info["converged"] and info["newton"] <= 8, info
+    np.testing.assert_array_equal(u[:, 1], u0[:, 1])
+    F = st.residual(u.ravel()).reshape(-1, 2)
+    vol = F[:, 0] / scn.rho[0] + F[:, 1] / scn.rho[1]
+    free = scn.dir_mask == 0
+    print("volume balance before / after:", np.abs(vol0[free]).max(), np.abs(vol[free]).max(), info["history"])
+    assert np.abs(vol[free]).max() <= 1e-8 * np.abs(vol0[free]).max()
+    # what remains is the O(h_p) of the vanishing step: a 100 times smaller h_p leaves
+    # a 100 times smaller volume balance
+    u2, _ = st.project_pressure(u0.ravel(), h_p=1e-8, rtol=1e-13)
+    F2 = st.residual(u2).reshape(-1, 2)
+    vol2 = F2[:, 0] / scn.rho[0] + F2[:, 1] / scn.rho[1]
+    assert 50.0 < np.abs(vol[free]).max() / np.abs(vol2[free]).max() < 200.0
+    # the non-wetting balance itself is not zeroed: the saturation has its own dynamics
+    assert np.abs(F[free, 1]).max() > 1e-3 * np.abs(F0[free, 1]).max()
+
+
+def test_stall_rule_by_hand():
+    r = ST.StallRule()
+    assert not r.after_step(False, 80.0, 0.16)      # first rejection: the reference
+    assert not r.after_step(False, 22.7, 0.017)     # tau/3.5, eps/9.6: falling, new reference
+    assert not r.after_step(False, 13.8, 0.016)     # tau not yet halved
+    assert r.after_step(False, 8.4, 0.0176)         # tau/2.7 but eps flat: project
+    assert not r.after_step(False, 5.0, 0.001)      # the reference was cleared
+    assert not r.after_step(False, 1.0, float("inf"))
+    assert not r.after_step(True, 1.0, 1e-3)
+    assert r.ref is None
