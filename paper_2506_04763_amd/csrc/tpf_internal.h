@@ -178,7 +178,7 @@ __host__ __device__ __forceinline__ long long tiled_blocks(long long N, int nst)
 // Logical block index of an XCD-aware launch: the hardware dispatches block k to
 // XCD k mod 8; this mapping gives every XCD one contiguous eighth of the grid so
 // that neighbouring rows (which share x entries) meet in the same L2.
-__device__ __forceinline__ unsigned xcd_block(unsigned bid, unsigned nblk) {
+__host__ __device__ __forceinline__ unsigned xcd_block(unsigned bid, unsigned nblk) {
   const unsigned per = nblk >> 3;
   const unsigned full = per << 3;
   if (bid >= full) return bid;
