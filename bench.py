@@ -46,23 +46,35 @@ HBM_PEAK_GBS = 8000.0
 NST = 27
 
 
-def algorithmic_bytes(cls: str, N: int, Nc_levels) -> float:
-    """Bytes one launch of a kernel class must move (3D, per the data layout).
+def nonzero_blocks(n) -> int:
+    """2x2 blocks of the 27-point stencil matrix that lie in the grid: prod(3 n_a - 2)."""
+    out = 1
+    for v in n:
+        out *= 3 * v - 2
+    return out
 
-    smooth0 / resid0 (FP32): 27 blocks x 16 B of matrix + x, b, out (3 x 8 B) per vertex
-    spmv64 (FP64): 27 x 32 B of matrix + x, y and the fused dot operand (3 x 16 B)
-    assemble (mixed): FP64 + FP32 matrix writes (864 + 432 B), F write, state and
+
+def algorithmic_bytes(cls: str, n, Nc_levels) -> float:
+    """Bytes one launch of a kernel class must move (3D): the matrix blocks that exist
+    (neighbours inside the grid; the stored zero blocks of out-of-grid neighbours are
+    not counted) and the vectors.
+
+    smooth0 / resid0 (FP32): blocks x 16 B + x, b, out (3 x 8 B per vertex)
+    spmv64 (FP64): blocks x 32 B + x, y and the fused dot operand (3 x 16 B per vertex)
+    assemble (mixed): FP64 + FP32 matrix writes (48 B per block), F write, state and
       per-vertex data reads (u, pv 32 B, p_dmin 8 B, Q 16 B, mask 1 B), cell data 32 B
     rap: per coarse level, the FP64 fine matrix read and FP64 + FP32 coarse writes.
     """
+    N = n[0] * n[1] * n[2]
+    B = nonzero_blocks(n)
     if cls in ("smooth0", "resid0"):
-        return N * (NST * 16 + 24)
+        return B * 16 + N * 24
     if cls == "smooth0_first":
         return N * (16 + 16)
     if cls == "spmv64":
-        return N * (NST * 32 + 48)
+        return B * 32 + N * 48
     if cls == "assemble":
-        return N * (NST * 48 + 16 + 32 + 8 + 16 + 1 + 32)
+        return B * 48 + N * (16 + 32 + 8 + 16 + 1 + 32)
     if cls == "rap":
         return sum(nf * NST * 32 + nc * NST * 48 for nf, nc in Nc_levels) / max(len(Nc_levels), 1)
     return float("nan")
@@ -161,8 +173,26 @@ def run(args):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         kt = g.profile_end() if prof else None
+        graph = None
+        if prof:
+            # the coarse levels as stream launches against one captured graph, both without
+            # kernel timing (which forces stream launches)
+            graph = {}
+            for mode in (False, True):
+                g.set_coarse_graph(mode)
+                g.assemble_stage(u0, h, f0_out=f)
+                g.solve_stage(f, rtol=rtol, maxit=500, out=x)
+                torch.cuda.synchronize()
+                ta = time.perf_counter()
+                for _ in range(args.steps):
+                    g.assemble_stage(u0, h, f0_out=f)
+                    x, st_ = g.solve_stage(f, rtol=rtol, maxit=500, out=x)
+                torch.cuda.synchronize()
+                graph["graph" if mode else "stream"] = round((time.perf_counter() - ta) * 1e3 / args.steps, 3)
+            g.set_coarse_graph(False)
         results[prec] = dict(ms=(t1 - t0) * 1e3 / args.steps, iters=iters, stats=stats, kt=kt, breakdown=breakdown,
-                             dom=dom, levels=[g.level_dims(l) for l in range(g.levels)], bytes=g.nbytes)
+                             dom=dom, levels=[g.level_dims(l) for l in range(g.levels)], bytes=g.nbytes,
+                             graph=graph)
         g.close()
         del g
         torch.cuda.empty_cache()
@@ -175,13 +205,13 @@ def run(args):
         if cnt == 0:
             continue
         avg = tot / cnt
-        b = algorithmic_bytes(cls, N, nlev)
+        b = algorithmic_bytes(cls, scn.n, nlev)
         kernels[cls] = {"launches": cnt, "avg_ms": round(avg, 5), "ms_per_step": round(tot, 3),
                         "gbs": (round(b / (avg * 1e-3) / 1e9, 1) if b == b else None)}
     dom = mixed["dom"]
     cnt, tot = mixed["kt"][dom]  # live: every launch of the class inside the timed steps
     avg_ms = tot / cnt
-    ach = algorithmic_bytes(dom, N, nlev) / (avg_ms * 1e-3) / 1e9
+    ach = algorithmic_bytes(dom, scn.n, nlev) / (avg_ms * 1e-3) / 1e9
     traffic = None
     tfile = os.path.join(ROOT, "profiles", "traffic.json")
     if os.path.exists(tfile):
@@ -214,6 +244,7 @@ def run(args):
         "rel_res_true": mixed["stats"]["rel_res_true"],
         "kernels": kernels,
         "arena_gb": round(mixed["bytes"] / 1e9, 3),
+        "coarse_graph_ms_per_step": mixed["graph"],
     }
     if "fp64" in results:
         r = results["fp64"]
@@ -545,6 +576,60 @@ def _source_hash(kernel="smooth0"):
     for f in KERNEL_SOURCES.get(kernel, sorted(os.listdir(os.path.join(ROOT, "paper_2506_04763_amd", "csrc")))):
         h.update(open(os.path.join(ROOT, "paper_2506_04763_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
+
+
+def _csv_rows(directory, suffix):
+    import csv
+    import glob
+    rows = []
+    for f in sorted(glob.glob(os.path.join(directory, "**", f"*{suffix}"), recursive=True)):
+        with open(f, newline="") as fh:
+            rows.extend(csv.DictReader(fh))
+    return rows
+
+
+def summarise_trace(directory, steps):
+    """Kernel-trace summary (rocprofv3 --kernel-trace CSV under `directory`): per kernel
+    and grid size the launches, average/min/max duration and the time per step."""
+    rows = _csv_rows(directory, "kernel_trace.csv")
+    agg = {}
+    for r in rows:
+        key = (r["Kernel_Name"], int(r.get("Grid_Size", r.get("Grid_Size_X", 0)) or 0))
+        d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3  # us
+        agg.setdefault(key, []).append(d)
+    total = sum(sum(v) for v in agg.values())
+    out = ["| kernel | grid (threads) | launches | avg us | min us | max us | ms per step | % of kernel time |",
+           "|---|---:|---:|---:|---:|---:|---:|---:|"]
+    for (name, grid), v in sorted(agg.items(), key=lambda kv: -sum(kv[1])):
+        short = name.split("(")[0].replace("tpf::(anonymous namespace)::", "")
+        out.append(f"| `{short}` | {grid} | {len(v)} | {sum(v) / len(v):.2f} | {min(v):.2f} | {max(v):.2f} | "
+                   f"{sum(v) / 1e3 / steps:.3f} | {100 * sum(v) / total:.1f} |")
+    out.append(f"\nTotal kernel time {total / 1e3:.1f} ms over {sum(len(v) for v in agg.values())} launches.")
+    return "\n".join(out)
+
+
+def summarise_counters(fetch_dir, write_dir, copy_bytes=1 << 30):
+    """FETCH_SIZE / WRITE_SIZE per kernel and grid (one rocprofv3 --pmc pass per directory),
+    calibrated by the device-to-device copy of copy_bytes bytes in the same workload."""
+    def per_kernel(directory, counter):
+        agg = {}
+        for r in _csv_rows(directory, "counter_collection.csv"):
+            if r.get("Counter_Name") != counter:
+                continue
+            key = (r["Kernel_Name"], int(r.get("Grid_Size", 0) or 0))
+            agg.setdefault(key, []).append(float(r["Counter_Value"]))
+        return {k: sum(v) / len(v) for k, v in agg.items()}
+    fetch, write = per_kernel(fetch_dir, "FETCH_SIZE"), per_kernel(write_dir, "WRITE_SIZE")
+    copy = [k for k in fetch if "copyBuffer" in k[0] or "copy" in k[0].lower()]
+    cf = max((fetch[k] for k in copy), default=float("nan")) * 1024 / copy_bytes
+    cw = max((write.get(k, 0.0) for k in copy), default=float("nan")) * 1024 / copy_bytes
+    rows = {}
+    for k in fetch:
+        if k in copy:
+            continue
+        hb = fetch[k] * 1024 / cf + write.get(k, 0.0) * 1024 / cw
+        rows[k] = dict(fetch_kib=fetch[k], write_kib=write.get(k, 0.0), bytes=hb)
+    return rows, dict(fetch_factor=cf, write_factor=cw, copy_bytes=copy_bytes)
 
 
 def main():

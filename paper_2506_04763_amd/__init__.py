@@ -239,6 +239,10 @@ class Grid:
         L.check(status, "tpf_project_pressure", soft_ok=True)
         return status == TPF_OK, st.as_dict()
 
+    def set_coarse_graph(self, enable=True):
+        """Replay the V-cycle's coarse levels as one captured HIP graph (or not)."""
+        L.check(self.lib.tpf_set_coarse_graph(self.handle, int(bool(enable))), "tpf_set_coarse_graph")
+
     # -- inspection ------------------------------------------------------------------
     def level_dims(self, level):
         n = (C.c_int32 * 3)()

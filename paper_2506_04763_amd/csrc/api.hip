@@ -418,6 +418,9 @@ static void prof_release(tpf_grid *g);
 void tpf_destroy_grid(tpf_grid *g) {
   if (!g) return;
   prof_release(g);
+  if (g->vgraph_exec) (void)hipGraphExecDestroy(g->vgraph_exec);
+  if (g->vgraph) (void)hipGraphDestroy(g->vgraph);
+  if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
   if (g->scal_ev) (void)hipEventDestroy(g->scal_ev);
   if (g->hscal) (void)hipHostFree(g->hscal);
   delete g;
@@ -561,6 +564,13 @@ tpf_status tpf_project_pressure(tpf_grid *g, double *u, double h_p, const tpf_ne
     return TPF_EINVAL;
   }
   return project_pressure(g, u, h_p, opts, stats, reinterpret_cast<hipStream_t>(stream));
+}
+
+tpf_status tpf_set_coarse_graph(tpf_grid *g, int32_t enable) {
+  g_err[0] = 0;
+  if (!g) { set_error("NULL argument"); return TPF_EINVAL; }
+  g->coarse_graph = enable ? 1 : 0;
+  return TPF_OK;
 }
 
 int32_t tpf_levels(const tpf_grid *g) { return g ? g->L : 0; }

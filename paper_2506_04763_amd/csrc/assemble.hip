@@ -541,7 +541,9 @@ k_assemble3_split(const Phys P, const CellIn in, const uint8_t *__restrict__ dma
   __shared__ double xch[SPLIT_V][9 * 4 + 4];
   const int half = threadIdx.x / SPLIT_V;  // waves 0-1: half 0, waves 2-3: half 1
   const int lv = threadIdx.x % SPLIT_V;
-  const long long v = (long long)blockIdx.x * SPLIT_V + lv;
+  // XCD-aware order: consecutive vertex rows run on one XCD, whose L2 then holds the
+  // per-(cell, corner) laws that neighbouring rows share
+  const long long v = (long long)xcd_block(blockIdx.x, gridDim.x) * SPLIT_V + lv;
   const bool valid = v < P.N;
   double acc[18][4];
 #pragma unroll

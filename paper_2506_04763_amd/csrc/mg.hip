@@ -1060,7 +1060,9 @@ tpf_status vcycle_t(tpf_grid *g, const double *bin, double *xout, hipStream_t s,
   bl[0] = b0;
   // levels whose first sweep runs inside the restriction (not the FP16 levels)
   auto fused_first = [&](int l) { return l >= 1 && l < L - 1 && g->prec != TPF_MIXED16; };
-  for (int l = 0; l < L - 1; ++l) {
+  // pre-smoothing, residual and restriction of level l (into l + 1, with l + 1's first
+  // sweep when it is fused into the restriction)
+  auto down = [&](int l, hipStream_t s) -> tpf_status {
     Level &lv = g->lv[l];
     const Geo G = geo(lv);
     const unsigned nb = blocks_for(lv.N);
@@ -1113,16 +1115,20 @@ tpf_status vcycle_t(tpf_grid *g, const double *bin, double *xout, hipStream_t s,
     else
       TPF_HIP(launch(g, c_tr, k_restrict<DIM, T>, blocks_for(lc.N), BS, s, G, geo(lc), (const T *)R, fm, vr, bc));
     bl[l + 1] = bc;
-  }
+    return TPF_OK;
+  };
   // coarsest level: x = A^{-1} b, one wavefront per row of the inverse
-  {
+  auto coarsest = [&](hipStream_t s) -> tpf_status {
     Level &lc = g->lv[L - 1];
     T *X = reinterpret_cast<T *>(lc.x);
     TPF_HIP(launch(g, TPF_K_COARSE_LEVELS, k_coarse_solve<T>, (unsigned)((g->nc + 3) / 4), 256u, s,
                    (const double *)g->ainv, g->nc, bl[L - 1], X));
     cur[L - 1] = X;
-  }
-  for (int l = L - 2; l >= 0; --l) {
+    return TPF_OK;
+  };
+  // prolongation from level l + 1 and post-smoothing of level l (the finest level's
+  // last sweep writes the FP64 result)
+  auto up = [&](int l, hipStream_t s) -> tpf_status {
     Level &lv = g->lv[l];
     const Geo G = geo(lv);
     const unsigned nb = blocks_for(lv.N);
@@ -1160,8 +1166,55 @@ tpf_status vcycle_t(tpf_grid *g, const double *bin, double *xout, hipStream_t s,
       TPF_LAUNCH_CHECK();
     }
     cur[l] = X;
+    return TPF_OK;
+  };
+  // the coarse tail: every level below the finest, down and up again; it reads level
+  // 1's right-hand side and writes cur[1], both at addresses fixed for the grid
+  auto tail = [&](hipStream_t s) -> tpf_status {
+    for (int l = 1; l < L - 1; ++l) {
+      const tpf_status st = down(l, s);
+      if (st != TPF_OK) return st;
+    }
+    tpf_status st = coarsest(s);
+    if (st != TPF_OK) return st;
+    for (int l = L - 2; l >= 1; --l) {
+      st = up(l, s);
+      if (st != TPF_OK) return st;
+    }
+    return TPF_OK;
+  };
+  tpf_status st = down(0, s);
+  if (st != TPF_OK) return st;
+  if (g->coarse_graph && L >= 3 && !g->prof.active) {
+    // the tail as one captured graph (recorded on the grid's capture stream the first
+    // time; the same launches as below, replayed)
+    if (!g->vgraph_exec) {
+      if (!g->cap_stream) TPF_HIP(hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking));
+      TPF_HIP(hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal));
+      const tpf_status cst = tail(g->cap_stream);
+      hipGraph_t graph = nullptr;
+      const hipError_t e = hipStreamEndCapture(g->cap_stream, &graph);
+      if (cst != TPF_OK || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cst != TPF_OK) return cst;
+        TPF_HIP(e);
+      }
+      const hipError_t ei = hipGraphInstantiate(&g->vgraph_exec, graph, nullptr, nullptr, 0);
+      if (ei != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        g->vgraph_exec = nullptr;
+        TPF_HIP(ei);
+      }
+      g->vgraph = graph;
+      g->vgraph_cur1 = cur[1];
+    }
+    cur[1] = reinterpret_cast<T *>(g->vgraph_cur1);
+    TPF_HIP(hipGraphLaunch(g->vgraph_exec, s));
+  } else {
+    st = tail(s);
+    if (st != TPF_OK) return st;
   }
-  return TPF_OK;
+  return up(0, s);
 }
 
 template <int DIM>

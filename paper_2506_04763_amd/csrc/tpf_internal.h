@@ -99,6 +99,12 @@ struct tpf_grid {
   bool assembled;
   bool has_f0;
   double h_stage;  // step of the assembled stage operator
+  // V-cycle coarse tail as a captured graph (levels below the finest)
+  int coarse_graph;           // use it (tpf_set_coarse_graph)
+  hipStream_t cap_stream;     // capture stream (default priority)
+  hipGraph_t vgraph;
+  hipGraphExec_t vgraph_exec;
+  void *vgraph_cur1;          // level-1 correction the tail leaves (fixed per grid)
   size_t bytes;
   int device;
   tpf::Prof prof;

@@ -45,11 +45,13 @@ def harness():
     os.makedirs(BUILD, exist_ok=True)
     fresh = os.path.exists(EXE) and all(os.path.getmtime(EXE) > os.path.getmtime(f) for f in _sources())
     if not fresh:
+        tmp = f"{EXE}.{os.getpid()}.tmp"  # parallel test workers each build, then rename atomically
         cmd = [HIPCC, "--offload-arch=gfx950", "-O1", "-g", "-std=c++20", "-Xclang", "-target-feature", "-Xclang",
                "-packed-fp32-ops", "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-               "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fno-omit-frame-pointer", SRC, "-o", EXE]
+               "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fno-omit-frame-pointer", SRC, "-o", tmp]
         r = subprocess.run(cmd, capture_output=True, text=True)
         assert r.returncode == 0, r.stderr[-3000:]
+        os.replace(tmp, EXE)
     return EXE
 
 
