@@ -162,21 +162,10 @@ def run(args):
             torch.cuda.synchronize()
             breakdown = g.profile_end()
             dom = max((k for k in hot if breakdown[k][0]), key=lambda k: breakdown[k][1])
-            # the timed steps record events around the dominant kernel class only
-            g.profile_begin(200000, classes=[dom])
-        t0 = time.perf_counter()
-        iters = []
-        for _ in range(args.steps):
-            g.assemble_stage(u0, h, f0_out=f)
-            x, stats = g.solve_stage(f, rtol=rtol, maxit=500, out=x)
-            iters.append(stats["iters"])
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        kt = g.profile_end() if prof else None
         graph = None
         if prof:
-            # the coarse levels as stream launches against one captured graph, both without
-            # kernel timing (which forces stream launches)
+            # the coarse levels as stream launches against one captured graph (identical
+            # results), both without kernel timing; the timed steps use the faster
             graph = {}
             for mode in (False, True):
                 g.set_coarse_graph(mode)
@@ -189,7 +178,19 @@ def run(args):
                     x, st_ = g.solve_stage(f, rtol=rtol, maxit=500, out=x)
                 torch.cuda.synchronize()
                 graph["graph" if mode else "stream"] = round((time.perf_counter() - ta) * 1e3 / args.steps, 3)
-            g.set_coarse_graph(False)
+            graph["timed_with"] = "graph" if graph["graph"] < graph["stream"] else "stream"
+            g.set_coarse_graph(graph["timed_with"] == "graph")
+            # the timed steps record events around the dominant kernel class only
+            g.profile_begin(200000, classes=[dom])
+        t0 = time.perf_counter()
+        iters = []
+        for _ in range(args.steps):
+            g.assemble_stage(u0, h, f0_out=f)
+            x, stats = g.solve_stage(f, rtol=rtol, maxit=500, out=x)
+            iters.append(stats["iters"])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        kt = g.profile_end() if prof else None
         results[prec] = dict(ms=(t1 - t0) * 1e3 / args.steps, iters=iters, stats=stats, kt=kt, breakdown=breakdown,
                              dom=dom, levels=[g.level_dims(l) for l in range(g.levels)], bytes=g.nbytes,
                              graph=graph)
@@ -236,7 +237,8 @@ def run(args):
         "data": "synthetic",
         "config": {"workload": "cube129_lognormal_sigma2_seed3_mixed", "vertices": [129, 129, 129], "dof": 2 * N,
                    "levels": len(lv), "precision": "FP32 multigrid in FP64 BiCGSTAB", "rtol": rtol, "h_s": h,
-                   "smoother": "V(2,2) block-Jacobi omega=2/3"},
+                   "smoother": "V(2,2) block-Jacobi omega=2/3",
+                   "coarse_levels": (mixed["graph"] or {}).get("timed_with", "stream")},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "launches_timed": cnt, "avg_us": round(avg_ms * 1e3, 2)},
@@ -244,7 +246,7 @@ def run(args):
         "rel_res_true": mixed["stats"]["rel_res_true"],
         "kernels": kernels,
         "arena_gb": round(mixed["bytes"] / 1e9, 3),
-        "coarse_graph_ms_per_step": mixed["graph"],
+        "coarse_levels_ms_per_step": mixed["graph"],
     }
     if "fp64" in results:
         r = results["fp64"]
@@ -588,20 +590,30 @@ def _csv_rows(directory, suffix):
     return rows
 
 
+def _short(name):
+    """Kernel name without namespace, return type and argument list."""
+    n = name.replace("void ", "", 1).replace("tpf::(anonymous namespace)::", "").replace("tpf::", "")
+    return n.split("(")[0]
+
+
 def summarise_trace(directory, steps):
     """Kernel-trace summary (rocprofv3 --kernel-trace CSV under `directory`): per kernel
     and grid size the launches, average/min/max duration and the time per step."""
     rows = _csv_rows(directory, "kernel_trace.csv")
     agg = {}
     for r in rows:
-        key = (r["Kernel_Name"], int(r.get("Grid_Size", r.get("Grid_Size_X", 0)) or 0))
+        if "Grid_Size_X" in r:
+            grid = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+        else:
+            grid = int(r.get("Grid_Size", 0) or 0)
+        key = (r["Kernel_Name"], grid)
         d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3  # us
         agg.setdefault(key, []).append(d)
     total = sum(sum(v) for v in agg.values())
     out = ["| kernel | grid (threads) | launches | avg us | min us | max us | ms per step | % of kernel time |",
            "|---|---:|---:|---:|---:|---:|---:|---:|"]
     for (name, grid), v in sorted(agg.items(), key=lambda kv: -sum(kv[1])):
-        short = name.split("(")[0].replace("tpf::(anonymous namespace)::", "")
+        short = _short(name)
         out.append(f"| `{short}` | {grid} | {len(v)} | {sum(v) / len(v):.2f} | {min(v):.2f} | {max(v):.2f} | "
                    f"{sum(v) / 1e3 / steps:.3f} | {100 * sum(v) / total:.1f} |")
     out.append(f"\nTotal kernel time {total / 1e3:.1f} ms over {sum(len(v) for v in agg.values())} launches.")
@@ -643,6 +655,12 @@ def main():
     ap.add_argument("--no-cases", action="store_true",
                     help="leave out the case-1 and case-5 summaries of the default line")
     ap.add_argument("--serve-requests", type=int, default=256)
+    ap.add_argument("--summarise-trace", metavar="DIR",
+                    help="print the per-kernel table of a rocprofv3 kernel trace under DIR (uses --steps)")
+    ap.add_argument("--summarise-counters", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "LOG"),
+                    help="print FETCH_SIZE/WRITE_SIZE per kernel (calibrated by the 1 GiB copy of --counters) "
+                         "and write profiles/traffic.json for the smoother; LOG is the stdout of one of the "
+                         "--counters runs (its source hashes are the ones recorded)")
     ap.add_argument("--counters", action="store_true",
                     help="run the short hardware-counter workload instead of the benchmark")
     ap.add_argument("--limex-run", type=int, default=0, metavar="K",
@@ -657,6 +675,35 @@ def main():
                     help="Table case4_2: implicit Euler + Newton against LIMEX on case 4 (256 x 128 cells, 10 years)")
     ap.add_argument("--schemes", default="limex,implicit_euler", help="schemes of --case4-compare")
     args = ap.parse_args()
+    if args.summarise_trace:
+        print(summarise_trace(args.summarise_trace, args.steps))
+        return
+    if args.summarise_counters:
+        fetch_dir, write_dir, log = args.summarise_counters
+        rows, cal = summarise_counters(fetch_dir, write_dir)
+        run_hash = None
+        with open(log) as fh:
+            for line in fh:
+                if '"counters_driver"' in line:
+                    run_hash = json.loads(line)["source_hash"]["smooth0"]
+        if run_hash is None:
+            raise SystemExit(f"{log}: no counters_driver line (the stdout of a --counters run)")
+        print(f"calibration: FETCH_SIZE factor {cal['fetch_factor']:.4f}, WRITE_SIZE factor {cal['write_factor']:.4f}\n")
+        print("| kernel | grid | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes (calibrated) |")
+        print("|---|---:|---:|---:|---:|")
+        for (name, grid), r in sorted(rows.items(), key=lambda kv: -kv[1]["bytes"]):
+            short = _short(name)
+            print(f"| `{short}` | {grid} | {r['fetch_kib']:.0f} | {r['write_kib']:.0f} | {r['bytes'] / 1e6:.1f} MB |")
+        sm = [(k, r) for k, r in rows.items() if "k_jacobi_stream" in k[0] and "float, float" in k[0]]
+        if sm:
+            (name, grid), r = max(sm, key=lambda kv: kv[0][1])
+            tj = {"kernel": "smooth0", "kernel_name": _short(name),
+                  "grid": grid, "source_hash": run_hash, "bytes_per_launch": round(r["bytes"]),
+                  "fetch_kib": r["fetch_kib"], "write_kib": r["write_kib"], "calibration": cal,
+                  "source": "profiles/cube129_mixed_hbm_counters.md"}
+            with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
+                json.dump(tj, fh, indent=1)
+        return
     if args.counters:
         counters_driver()
         return

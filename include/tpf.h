@@ -318,8 +318,8 @@ tpf_status tpf_project_pressure(tpf_grid *g, double *u, double h_p, const tpf_ne
  * HIP graph captured on the grid's own stream at the first V-cycle; 0: stream
  * launches, the default).  Both issue the same kernels in the same order, so results
  * are identical; the graph saves host and dispatch work per launch on the small,
- * latency-bound levels.  While kernel timing (tpf_profile_begin) is active the stream
- * launches are used.  Returns TPF_OK or TPF_EINVAL. */
+ * latency-bound levels.  While the TPF_K_COARSE_LEVELS class is being timed
+ * (tpf_profile_begin) the stream launches are used.  Returns TPF_OK or TPF_EINVAL. */
 tpf_status tpf_set_coarse_graph(tpf_grid *g, int32_t enable);
 
 /* ---- inspection hooks (used by the parity tests and the benchmark) ---------- */

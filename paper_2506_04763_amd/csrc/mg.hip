@@ -1185,7 +1185,10 @@ tpf_status vcycle_t(tpf_grid *g, const double *bin, double *xout, hipStream_t s,
   };
   tpf_status st = down(0, s);
   if (st != TPF_OK) return st;
-  if (g->coarse_graph && L >= 3 && !g->prof.active) {
+  // (the graph's launches carry no timing events: it is skipped while the coarse-level
+  // class itself is being timed)
+  const bool timing_coarse = g->prof.active && ((g->prof.mask >> TPF_K_COARSE_LEVELS) & 1u);
+  if (g->coarse_graph && L >= 3 && !timing_coarse) {
     // the tail as one captured graph (recorded on the grid's capture stream the first
     // time; the same launches as below, replayed)
     if (!g->vgraph_exec) {
