@@ -32,6 +32,14 @@ here:
     block-Jacobi smoother stable on every level;
   * smoother: damped point-block Jacobi with the 2x2 diagonal blocks D,
     x <- x + omega D^{-1} (b - A x), zero initial guess on every level;
+  * optional smoother for transport along the gravity axis (not in the paper; an
+    option of this implementation): damped line-block Jacobi,
+    x <- x + omega A_L^{-1} (b - A x), where A_L keeps the entries of A that couple two
+    DoFs of the same vertex line along the last active axis (y in 2D, z in 3D) and
+    drops all others: a block tridiagonal matrix with 2x2 blocks per line.  Like
+    point-block Jacobi it is invariant under the block-diagonal row transform, so it
+    also smooths with A_0 itself.  It is applied here by a sparse LU of A_L, the
+    plain definition;
   * V(nu1, nu2) cycle; the coarsest level is solved with a dense LU factorisation
     with partial pivoting (scipy.linalg.lu_factor / lu_solve).
 """
@@ -40,6 +48,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.linalg as sla
 import scipy.sparse as sp
+import scipy.sparse.linalg as spla
 
 
 def coarse_size(n: int) -> int:
@@ -113,6 +122,17 @@ def block_diag_inverse(A: sp.csr_matrix) -> np.ndarray:
     return inv
 
 
+def line_part(A: sp.csr_matrix, n, dim) -> sp.csr_matrix:
+    """A_L: the entries of A between DoFs of vertices on the same line along the last
+    active axis (vertices x-fastest, so the line of vertex v is v mod nx in 2D and
+    v mod nx*ny in 3D)."""
+    nx, ny, _ = n
+    stride = nx if dim == 2 else nx * ny
+    C = sp.coo_matrix(A)
+    keep = (C.row // 2) % stride == (C.col // 2) % stride
+    return sp.csr_matrix((C.data[keep], (C.row[keep], C.col[keep])), shape=A.shape)
+
+
 def lumped_storage(P, S):
     """Row sums of P^T S P placed on the S_n column of each 2x2 diagonal block."""
     d = np.asarray((P.T @ S @ P).sum(axis=1)).ravel()
@@ -135,10 +155,15 @@ def volume_balance(dir_mask, rho) -> sp.csr_matrix:
 
 
 class Hierarchy:
-    def __init__(self, A0, n, dim, levels, dir_mask, omega=2.0 / 3.0, nu1=2, nu2=2, S0=None, T0=None):
+    def __init__(self, A0, n, dim, levels, dir_mask, omega=2.0 / 3.0, nu1=2, nu2=2, S0=None, T0=None,
+                 smoother="jacobi"):
         """S0: storage part of A0 (block diagonal, S_n column only); None means zero.
         T0: row transform of the finest level for the coarse-grid correction (None:
-        identity)."""
+        identity).  smoother: 'jacobi' (point-block) or 'line' (line-block along the
+        last active axis)."""
+        if smoother not in ("jacobi", "line"):
+            raise ValueError(f"unknown smoother {smoother!r}")
+        self.smoother = smoother
         self.sizes = level_sizes(n, dim, levels)
         self.A = [sp.csr_matrix(A0)]
         S = sp.csr_matrix(A0.shape) if S0 is None else sp.csr_matrix(S0)
@@ -161,14 +186,19 @@ class Hierarchy:
             self.A.append(sp.csr_matrix(Ac))
             self.S.append(Sc)
         self.Dinv = [block_diag_inverse(A) for A in self.A]
+        self.line_lu = ([spla.splu(sp.csc_matrix(line_part(A, nl, dim))) for A, nl in zip(self.A, self.sizes)]
+                        if smoother == "line" else None)
         self.lu = sla.lu_factor(self.A[-1].toarray())
         self.omega, self.nu1, self.nu2 = omega, nu1, nu2
 
     def smooth(self, l, x, b, sweeps):
         A, Di = self.A[l], self.Dinv[l]
         for _ in range(sweeps):
-            r = (b - A @ x).reshape(-1, 2)
-            x = x + self.omega * np.einsum("nij,nj->ni", Di, r).ravel()
+            r = b - A @ x
+            if self.line_lu is not None:
+                x = x + self.omega * self.line_lu[l].solve(r)
+            else:
+                x = x + self.omega * np.einsum("nij,nj->ni", Di, r.reshape(-1, 2)).ravel()
         return x
 
     def vcycle(self, b, l=0):

@@ -12,8 +12,9 @@ from . import limex as _lx
 
 
 class Stage:
-    def __init__(self, scn, levels=None, omega=2.0 / 3.0, nu1=2, nu2=2):
+    def __init__(self, scn, levels=None, omega=2.0 / 3.0, nu1=2, nu2=2, smoother="jacobi"):
         self.scn = scn
+        self.smoother = smoother
         self.fv = _fv.FV(scn)
         self.levels = scn.levels if levels is None else levels
         self.omega, self.nu1, self.nu2 = omega, nu1, nu2
@@ -30,7 +31,7 @@ class Stage:
         S0 = self.fv.storage_part(u0.reshape(-1, 2), h)
         T0 = _gmg.volume_balance(self.fv.dir_mask, self.scn.rho)
         self.H = _gmg.Hierarchy(self.A, self.scn.n, self.scn.dim, self.levels, self.fv.dir_mask,
-                                self.omega, self.nu1, self.nu2, S0=S0, T0=T0)
+                                self.omega, self.nu1, self.nu2, S0=S0, T0=T0, smoother=self.smoother)
         return self.A
 
     def solve(self, f, rtol=1e-10, maxit=500):
