@@ -98,6 +98,18 @@ typedef struct tpf_patch {
  *                   (the printed laws of Tables case4 and case5: 0.9 and 0.5). */
 enum { TPF_KR_BURDINE = 0, TPF_KR_POLY = 1 };
 
+/* Multigrid smoother (the paper names the multigrid preconditioner, not its parts):
+ *   TPF_SMOOTH_POINT  damped 2x2-block Jacobi, x += omega D^{-1} (b - A x);
+ *   TPF_SMOOTH_LINE   damped line-block Jacobi along the last axis (y in 2D, z in
+ *                     3D: the gravity axis of the layered workloads of Section 5),
+ *                     x += omega A_L^{-1} (b - A x), A_L the couplings of A inside each
+ *                     vertex line (block tridiagonal, 2x2 blocks), solved exactly by a
+ *                     block LU per line factored in FP64 with the hierarchy.  It keeps
+ *                     BiCGSTAB + GMG convergent where layers and buoyant transport make
+ *                     point smoothing stall.  Needs 12 more level-type values per
+ *                     vertex on every level but the coarsest. */
+enum { TPF_SMOOTH_POINT = 0, TPF_SMOOTH_LINE = 1 };
+
 /* Scenario: the problem statement of Section 2 (domain, per-element porosity,
  * isotropic permeability and Brooks-Corey parameters, fluids, gravity, Dirichlet
  * and Neumann data) plus the multigrid settings.  Host pointers are read during
@@ -123,9 +135,9 @@ typedef struct tpf_grid_desc {
   int32_t nu_pre;        /* pre-smoothing sweeps (>= 1)                         */
   int32_t nu_post;       /* post-smoothing sweeps (>= 0)                        */
   int32_t limex_stages;  /* largest LIMEX stage count used with this grid (0: none) */
-  double omega;          /* block-Jacobi damping in (0, 2)                      */
+  double omega;          /* smoother damping in (0, 2)                          */
   int32_t kr_model;      /* TPF_KR_BURDINE or TPF_KR_POLY                       */
-  int32_t reserved;      /* 0                                                   */
+  int32_t smoother;      /* TPF_SMOOTH_POINT or TPF_SMOOTH_LINE (see above)     */
   double kr_coef[2];     /* TPF_KR_POLY: a_w, a_n > 0 (ignored otherwise)       */
   const double *vertex_source; /* host, 2 per vertex (w, n), kg/s into the vertex's
                                   control volume (point sources such as case 5's
@@ -360,6 +372,8 @@ enum {
   TPF_K_RESID0,         /* level residual on the finest level                     */
   TPF_K_COARSE_LEVELS,  /* every smoother/residual/transfer launch below level 0  */
   TPF_K_TRANSFER0,      /* restriction from and prolongation to the finest level  */
+  TPF_K_LINE0,          /* line solve of a TPF_SMOOTH_LINE sweep on the finest level
+                           (the sweep's residual is timed as TPF_K_RESID0)         */
   TPF_K_COUNT
 };
 

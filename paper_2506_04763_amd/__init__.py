@@ -20,13 +20,14 @@ from ._lib import (TPF_EBREAKDOWN, TPF_EINVAL, TPF_ENOMEM, TPF_ESTATE, TPF_FP64,
 __all__ = ["Grid", "make_desc", "grid_bytes", "validate", "TPFError"]
 
 PRECISIONS = {"fp64": TPF_FP64, "mixed": TPF_MIXED, "mixed16": L.TPF_MIXED16}
+SMOOTHERS = {"point": 0, "line": 1}  # TPF_SMOOTH_POINT, TPF_SMOOTH_LINE
 
 
 class _Desc:
     """A tpf_grid_desc plus the host arrays it points to (kept alive together)."""
 
     def __init__(self, scn, precision="fp64", levels=None, nu_pre=2, nu_post=2, omega=2.0 / 3.0,
-                 limex_stages=0):
+                 limex_stages=0, smoother="point"):
         self.keep = []
         d = L.GridDesc()
         d.dim = int(scn.dim)
@@ -64,6 +65,7 @@ class _Desc:
         d.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         d.nu_pre, d.nu_post = int(nu_pre), int(nu_post)
         d.omega = float(omega)
+        d.smoother = SMOOTHERS[smoother] if isinstance(smoother, str) else int(smoother)
         d.limex_stages = int(limex_stages)
         model = getattr(scn, "kr_model", "burdine")
         d.kr_model = {"burdine": L.TPF_KR_BURDINE, "poly": L.TPF_KR_POLY}[model]
@@ -102,7 +104,7 @@ class Grid:
     """One scenario resident on one GPU (all device state in a torch-owned arena)."""
 
     def __init__(self, scn, precision="fp64", levels=None, nu_pre=2, nu_post=2, omega=2.0 / 3.0,
-                 limex_stages=0, device=None, stream=None, arena=None):
+                 limex_stages=0, device=None, stream=None, arena=None, smoother="point"):
         import torch
         self.torch = torch
         self.lib = L.load()
@@ -114,7 +116,8 @@ class Grid:
         self.dim = int(scn.dim)
         self.nst = 27 if self.dim == 3 else 9
         self._dd = _Desc(scn, precision=precision, levels=levels, nu_pre=nu_pre, nu_post=nu_post,
-                         omega=omega, limex_stages=limex_stages)
+                         omega=omega, limex_stages=limex_stages, smoother=smoother)
+        self.smoother = smoother
         self.precision = self._dd.desc.precision
         nbytes = self.lib.tpf_grid_bytes(C.byref(self._dd.desc))
         if nbytes == 0:

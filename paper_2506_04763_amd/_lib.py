@@ -40,7 +40,7 @@ class GridDesc(C.Structure):
                 ("patches", C.POINTER(Patch)), ("n_patches", C.c_int32), ("levels", C.c_int32),
                 ("precision", C.c_int32), ("nu_pre", C.c_int32), ("nu_post", C.c_int32),
                 ("limex_stages", C.c_int32), ("omega", C.c_double), ("kr_model", C.c_int32),
-                ("reserved", C.c_int32), ("kr_coef", C.c_double * 2), ("vertex_source", C.POINTER(C.c_double))]
+                ("smoother", C.c_int32), ("kr_coef", C.c_double * 2), ("vertex_source", C.POINTER(C.c_double))]
 
 
 class SolveStats(C.Structure):
@@ -84,7 +84,7 @@ class KernelTime(C.Structure):
 
 
 KERNEL_CLASSES = ["assemble", "rap", "coarse_lu", "spmv64", "smooth0", "smooth0_first", "resid0",
-                  "coarse_levels", "transfer0"]
+                  "coarse_levels", "transfer0", "line0"]
 
 VP = C.c_void_p
 DP = C.c_void_p  # device pointers are passed as integers

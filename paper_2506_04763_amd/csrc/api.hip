@@ -34,7 +34,8 @@ struct Layout {
   int L, nst, nc;
   int n[MAXL][3];
   long long Nl[MAXL];
-  size_t off_cells, off_vert, off_lv[MAXL], off_coarse, off_rapb, off_kry, off_part, off_scal, off_lx, total;
+  size_t off_cells, off_vert, off_lv[MAXL], off_coarse, off_rapb, off_kry, off_part, off_scal, off_flags, off_lx,
+      total;
   long long npart;
 };
 
@@ -109,6 +110,8 @@ tpf_status validate(const tpf_grid_desc *d) {
   if (!(d->omega > 0.0 && d->omega < 2.0)) BAD("omega must be in (0, 2)");
   if (d->limex_stages < 0 || d->limex_stages > MAXK) BAD("limex_stages must be in [0, %d]", MAXK);
   if (d->kr_model != TPF_KR_BURDINE && d->kr_model != TPF_KR_POLY) BAD("kr_model must be TPF_KR_BURDINE or TPF_KR_POLY");
+  if (d->smoother != TPF_SMOOTH_POINT && d->smoother != TPF_SMOOTH_LINE)
+    BAD("smoother must be TPF_SMOOTH_POINT or TPF_SMOOTH_LINE");
   if (d->kr_model == TPF_KR_POLY)
     for (int k = 0; k < 2; ++k)
       if (!(d->kr_coef[k] > 0.0) || !finite(d->kr_coef[k])) BAD("kr_coef[%d] must be positive and finite", k);
@@ -147,6 +150,7 @@ void layout(const tpf_grid_desc *d, Layout &L) {
       o += align_up((size_t)L.nst * 4 * L.Nl[l] * sizeof(uint16_t)) + align_up(2 * L.Nl[l] * sizeof(float));
     o += align_up(2 * L.Nl[l] * sizeof(double));
     o += 4 * align_up(2 * L.Nl[l] * vsz);
+    if (d->smoother == TPF_SMOOTH_LINE && l + 1 < L.L) o += align_up(12 * L.Nl[l] * vsz);  // line LU
   }
   L.off_coarse = o;
   o += 2 * align_up((size_t)L.nc * L.nc * sizeof(double)) + align_up(L.nc * sizeof(int));
@@ -159,6 +163,8 @@ void layout(const tpf_grid_desc *d, Layout &L) {
   o += align_up(4 * L.npart * sizeof(double));
   L.off_scal = o;
   o += align_up(NSCAL * sizeof(double));
+  L.off_flags = o;  // device flags (line LU)
+  o += align_up(sizeof(int));
   L.off_lx = o;
   o += align_up(2 * L.N * sizeof(double)) * (4 + (d->limex_stages > 0 ? 1 + d->limex_stages : 0));
   L.total = o;
@@ -264,6 +270,7 @@ tpf_status tpf_create_grid(const tpf_grid_desc *d, void *arena, size_t arena_byt
   g->nu_post = d->nu_post;
   g->kmax = d->limex_stages;
   g->omega = d->omega;
+  g->smoother = d->smoother;
   g->ncells = L.ncells;
   g->bytes = L.total;
   Phys &P = g->P;
@@ -325,6 +332,11 @@ tpf_status tpf_create_grid(const tpf_grid_desc *d, void *arena, size_t arena_byt
     lv.y = base + o; o += align_up(2 * lv.N * vsz);
     lv.b = base + o; o += align_up(2 * lv.N * vsz);
     lv.r = base + o; o += align_up(2 * lv.N * vsz);
+    lv.lf = nullptr;
+    if (d->smoother == TPF_SMOOTH_LINE && l + 1 < L.L) {
+      lv.lf = base + o;
+      o += align_up(12 * lv.N * vsz);
+    }
   }
   g->nc = L.nc;
   o = L.off_coarse;
@@ -338,6 +350,7 @@ tpf_status tpf_create_grid(const tpf_grid_desc *d, void *arena, size_t arena_byt
   g->part = reinterpret_cast<double *>(base + L.off_part);
   g->npart = L.npart;
   g->scal = reinterpret_cast<double *>(base + L.off_scal);
+  g->line_bad = reinterpret_cast<int *>(base + L.off_flags);
   o = L.off_lx;
   g->u0 = reinterpret_cast<double *>(base + o); o += align_up(2 * L.N * sizeof(double));
   g->f0 = reinterpret_cast<double *>(base + o); o += align_up(2 * L.N * sizeof(double));

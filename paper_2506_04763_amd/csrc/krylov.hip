@@ -203,6 +203,20 @@ static tpf_status read_scalars(tpf_grid *g, hipStream_t s) {
   return TPF_OK;
 }
 
+tpf_status check_line_factors(tpf_grid *g, hipStream_t s) {
+  if (g->smoother != TPF_SMOOTH_LINE) return TPF_OK;
+  if (g->line_unchecked) {
+    TPF_HIP(hipMemcpyAsync(&g->line_bad_count, g->line_bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    TPF_HIP(hipStreamSynchronize(s));
+    g->line_unchecked = false;
+  }
+  if (g->line_bad_count > 0) {
+    set_error("line smoother: %d vertex lines met a singular pivot block in their block LU", g->line_bad_count);
+    return TPF_EBREAKDOWN;
+  }
+  return TPF_OK;
+}
+
 tpf_status bicgstab(tpf_grid *g, const double *f, double *x, double rtol, int maxit, tpf_solve_stats *st,
                     hipStream_t s) {
   const long long n = 2 * g->P.N;
@@ -219,6 +233,14 @@ tpf_status bicgstab(tpf_grid *g, const double *f, double *x, double rtol, int ma
   const double ff = g->hscal[S_FF];
   tpf_solve_stats local{};
   local.fnorm = sqrt(ff);
+  {
+    const tpf_status lc = check_line_factors(g, s);
+    if (lc != TPF_OK) {
+      local.rel_res = local.rel_res_true = 1.0;
+      if (st) *st = local;
+      return lc;
+    }
+  }
   if (!(ff > 0.0)) {
     local.iters = 0;
     local.rel_res = 0.0;

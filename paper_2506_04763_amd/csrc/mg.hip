@@ -10,6 +10,9 @@
 // never dereference x.  P acts per component between vertex-halved grids: (bi/tri)
 // linear interpolation of the pressure, piecewise-constant aggregation of the
 // saturation; on the finest level its rows at Dirichlet components are zero.
+#include <type_traits>
+
+#include "line.h"
 #include "stencil.h"
 
 namespace tpf {
@@ -576,6 +579,11 @@ __global__ void k_zero(double *p, long long n) {
     p[i] = 0.0;
 }
 
+__global__ void k_zero_int(int *p, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
 // Blocked right-looking LU with partial pivoting of the column-major n x n coarsest
 // matrix (P A = L U, L unit lower, both factors in place), in panels of LU_NB
 // columns: the panel is factored by one workgroup, its row interchanges are then
@@ -988,6 +996,52 @@ __global__ void __launch_bounds__(BS) k_rescale(const Geo G, double *__restrict_
 // ---- V-cycle driver ----------------------------------------------------------
 // TPF_MIXED16 coarse levels: sweep (first: zero initial guess) and residual with the
 // FP16 matrix; return false where the level is not stored in FP16.
+// ---- line-block Jacobi (TPF_SMOOTH_LINE): one thread per vertex line -----------
+// Few threads walk long lines, so the launches use one wavefront per block to spread
+// the lines over the compute units.
+constexpr int LINE_BS = 64;
+#ifndef TPF_LINE_CHUNK
+#define TPF_LINE_CHUNK 8
+#endif
+
+template <int DIM, typename TO>
+__global__ void __launch_bounds__(LINE_BS) k_line_factor(const Geo G, const double *__restrict__ A,
+                                                         TO *__restrict__ lf, int *__restrict__ bad) {
+  const long long l = (long long)blockIdx.x * LINE_BS + threadIdx.x;
+  if (l >= line_geo<DIM>(G).S) return;
+  if (!line_factor<DIM, TO>(G, A, lf, l)) atomicAdd(bad, 1);
+}
+
+template <int DIM, typename T, typename TO>
+__global__ void __launch_bounds__(LINE_BS) k_line(const Geo G, const T *__restrict__ lf, const T *rin, T *cbuf,
+                                                  const T *__restrict__ xi, TO *__restrict__ xo, const T omega) {
+  const long long l = (long long)blockIdx.x * LINE_BS + threadIdx.x;
+  if (l >= line_geo<DIM>(G).S) return;
+  line_solve<DIM, T, TO, TPF_LINE_CHUNK>(G, lf, rin, cbuf, xi, xo, omega, l);
+}
+
+// Line LU of every level but the coarsest from its FP64 matrix, in the level type.
+// Singular pivot blocks are counted into g->line_bad (a device int cleared here).
+template <int DIM>
+tpf_status line_factors_t(tpf_grid *g, hipStream_t s) {
+  if (g->smoother != TPF_SMOOTH_LINE) return TPF_OK;
+  k_zero_int<<<1, 64, 0, s>>>(g->line_bad, 1);
+  TPF_LAUNCH_CHECK();
+  for (int l = 0; l + 1 < g->L; ++l) {
+    const Level &lv = g->lv[l];
+    const unsigned nb = blocks_for(line_geo<DIM>(geo(lv)).S, LINE_BS);
+    if (g->prec == TPF_FP64)
+      k_line_factor<DIM, double><<<nb, LINE_BS, 0, s>>>(geo(lv), lv.A64, reinterpret_cast<double *>(lv.lf),
+                                                        g->line_bad);
+    else
+      k_line_factor<DIM, float><<<nb, LINE_BS, 0, s>>>(geo(lv), lv.A64, reinterpret_cast<float *>(lv.lf),
+                                                       g->line_bad);
+    TPF_LAUNCH_CHECK();
+  }
+  g->line_unchecked = true;
+  return TPF_OK;
+}
+
 template <int DIM, typename T>
 bool sweep16(tpf_grid *g, int l, bool first, const T *b, const T *xi, T *xo, T om, hipStream_t s) {
   if constexpr (sizeof(T) != sizeof(float)) {
@@ -1059,7 +1113,44 @@ tpf_status vcycle_t(tpf_grid *g, const double *bin, double *xout, hipStream_t s,
   T *cur[MAXL];
   bl[0] = b0;
   // levels whose first sweep runs inside the restriction (not the FP16 levels)
-  auto fused_first = [&](int l) { return l >= 1 && l < L - 1 && g->prec != TPF_MIXED16; };
+  auto fused_first = [&](int l) {
+    return l >= 1 && l < L - 1 && g->prec != TPF_MIXED16 && g->smoother == TPF_SMOOTH_POINT;
+  };
+  const bool line = g->smoother == TPF_SMOOTH_LINE;
+  // r = b - A x on level l into R
+  auto resid = [&](int l, const T *b, const T *x, T *R, hipStream_t s) -> tpf_status {
+    Level &lv = g->lv[l];
+    const Geo G = geo(lv);
+    const unsigned nb = blocks_for(lv.N);
+    const int c_re = l == 0 ? TPF_K_RESID0 : TPF_K_COARSE_LEVELS;
+    if (resid16<DIM, T>(g, l, b, x, R, s)) {
+      TPF_LAUNCH_CHECK();
+    } else if (l == 0 && NT0) {
+      TPF_HIP(launch(g, c_re, k_resid_stream<DIM, T>, nb, BS, s, G, A_of(l), b, x, R));
+    } else if (lv.N > LAT_NMAX) {
+      TPF_HIP(launch(g, c_re, k_resid<DIM, T>, nb, BS, s, G, A_of(l), b, x, R));
+    } else {
+      TPF_HIP(launch(g, c_re, k_resid<DIM, T, false, true>, nb, BS, s, G, A_of(l), b, x, R));
+    }
+    return TPF_OK;
+  };
+  // one line sweep on level l: xo = xi + omega A_L^{-1} (b - A xi) (xi == nullptr: a
+  // zero guess, xo = omega A_L^{-1} b); the level's residual vector holds r and c
+  auto line_sweep = [&](int l, const T *b, const T *xi, auto *xo, hipStream_t s) -> tpf_status {
+    using TO = std::remove_pointer_t<decltype(xo)>;
+    Level &lv = g->lv[l];
+    T *R = reinterpret_cast<T *>(lv.r);
+    const T *rin = b;
+    if (xi) {
+      const tpf_status st = resid(l, b, xi, R, s);
+      if (st != TPF_OK) return st;
+      rin = R;
+    }
+    const unsigned nb = blocks_for(line_geo<DIM>(geo(lv)).S, LINE_BS);
+    TPF_HIP(launch(g, l == 0 ? TPF_K_LINE0 : TPF_K_COARSE_LEVELS, k_line<DIM, T, TO>, nb, (unsigned)LINE_BS, s,
+                   geo(lv), (const T *)lv.lf, rin, R, xi, xo, om));
+    return TPF_OK;
+  };
   // pre-smoothing, residual and restriction of level l (into l + 1, with l + 1's first
   // sweep when it is fused into the restriction)
   auto down = [&](int l, hipStream_t s) -> tpf_status {
@@ -1068,7 +1159,14 @@ tpf_status vcycle_t(tpf_grid *g, const double *bin, double *xout, hipStream_t s,
     const unsigned nb = blocks_for(lv.N);
     T *X = reinterpret_cast<T *>(lv.x), *Y = reinterpret_cast<T *>(lv.y);
     const int c_sm = l == 0 ? TPF_K_SMOOTH0 : TPF_K_COARSE_LEVELS;
-    if (fused_first(l)) {
+    if (line) {
+      tpf_status st = line_sweep(l, bl[l], (const T *)nullptr, X, s);
+      for (int k = 1; k < g->nu_pre && st == TPF_OK; ++k) {
+        st = line_sweep(l, bl[l], (const T *)X, Y, s);
+        T *t = X; X = Y; Y = t;
+      }
+      if (st != TPF_OK) return st;
+    } else if (fused_first(l)) {
       // X already holds the first sweep, written with the restriction into this level
     } else if (sweep16<DIM, T>(g, l, true, bl[l], nullptr, X, om, s)) {
       TPF_LAUNCH_CHECK();
@@ -1079,7 +1177,7 @@ tpf_status vcycle_t(tpf_grid *g, const double *bin, double *xout, hipStream_t s,
       TPF_HIP(launch(g, l == 0 ? TPF_K_SMOOTH0_FIRST : TPF_K_COARSE_LEVELS, k_jacobi<DIM, T, T, true>, nb, BS, s,
                      G, A_of(l), bl[l], noT, X, om));
     }
-    for (int k = 1; k < g->nu_pre; ++k) {
+    for (int k = 1; k < g->nu_pre && !line; ++k) {
       if (sweep16<DIM, T>(g, l, false, bl[l], X, Y, om, s)) {
         TPF_LAUNCH_CHECK();
       } else if (l == 0 && NT0) {
@@ -1094,15 +1192,9 @@ tpf_status vcycle_t(tpf_grid *g, const double *bin, double *xout, hipStream_t s,
     }
     cur[l] = X;
     T *R = reinterpret_cast<T *>(lv.r);
-    const int c_re = l == 0 ? TPF_K_RESID0 : TPF_K_COARSE_LEVELS;
-    if (resid16<DIM, T>(g, l, bl[l], X, R, s)) {
-      TPF_LAUNCH_CHECK();
-    } else if (l == 0 && NT0) {
-      TPF_HIP(launch(g, c_re, k_resid_stream<DIM, T>, nb, BS, s, G, A_of(l), bl[l], (const T *)X, R));
-    } else if (lv.N > LAT_NMAX) {
-      TPF_HIP(launch(g, c_re, k_resid<DIM, T>, nb, BS, s, G, A_of(l), bl[l], (const T *)X, R));
-    } else {
-      TPF_HIP(launch(g, c_re, k_resid<DIM, T, false, true>, nb, BS, s, G, A_of(l), bl[l], (const T *)X, R));
+    {
+      const tpf_status st = resid(l, bl[l], (const T *)X, R, s);
+      if (st != TPF_OK) return st;
     }
     Level &lc = g->lv[l + 1];
     T *bc = reinterpret_cast<T *>(lc.b);
@@ -1139,6 +1231,17 @@ tpf_status vcycle_t(tpf_grid *g, const double *bin, double *xout, hipStream_t s,
                    geo(g->lv[l + 1]), (const T *)cur[l + 1], l == 0 ? (const uint8_t *)g->dmask : nomask, X));
     const int nu = g->nu_post;
     for (int k = 0; k < nu; ++k) {
+      if (line) {
+        const tpf_status st = (l == 0 && k == nu - 1) ? line_sweep(l, bl[l], (const T *)X, xout, s)
+                                                       : line_sweep(l, bl[l], (const T *)X, Y, s);
+        if (st != TPF_OK) return st;
+        if (l == 0 && k == nu - 1) {
+          X = nullptr;
+          break;
+        }
+        T *t = X; X = Y; Y = t;
+        continue;
+      }
       if (l == 0 && k == nu - 1) {
         if (NT0)
           TPF_HIP(launch(g, c_sm, k_jacobi_stream<DIM, T, double>, nb, BS, s, G, A_of(l), bl[l], (const T *)X,
@@ -1239,6 +1342,12 @@ tpf_status hierarchy_t(tpf_grid *g, hipStream_t s) {
     }
     prof_end(g, ps, s);
   }
+  {
+    const int ps = prof_begin(g, TPF_K_RAP, s);
+    const tpf_status st = line_factors_t<DIM>(g, s);
+    if (st != TPF_OK) return st;
+    prof_end(g, ps, s);
+  }
   return coarse_factor_t<DIM>(g, s);
 }
 
@@ -1307,6 +1416,10 @@ tpf_status rescale_t(tpf_grid *g, double ratio, hipStream_t s) {
       k_to16<DIM><<<blocks_for(lv.N), BS, 0, s>>>(geo(lv), lv.A64, lv.A16, lv.s16);
       TPF_LAUNCH_CHECK();
     }
+  }
+  {
+    const tpf_status st = line_factors_t<DIM>(g, s);
+    if (st != TPF_OK) return st;
   }
   prof_end(g, ps, s);
   return coarse_factor_t<DIM>(g, s);

@@ -66,13 +66,14 @@ struct Level {
   float *s16;     // [N][2] row scales of A16
   double *mst;  // [N][2] storage part of the centre block, (w,S) and (n,S) entries
   void *x, *y, *b, *r;  // level vectors, 2N entries of the level type
+  void *lf;     // TPF_SMOOTH_LINE: line-LU blocks G, V, W, [3][N][4] of the level type
 };
 
 }  // namespace tpf
 
 struct tpf_grid {
   tpf::Phys P;
-  int dim, nst, L, prec, nu_pre, nu_post, kmax;
+  int dim, nst, L, prec, nu_pre, nu_post, kmax, smoother;
   double omega;
   long long ncells;
   // scenario
@@ -91,6 +92,9 @@ struct tpf_grid {
   double *part;
   long long npart;
   double *scal;
+  int *line_bad;        // TPF_SMOOTH_LINE: lines whose LU met a singular pivot block
+  bool line_unchecked;  // line LU recomputed since line_bad was last read
+  int line_bad_count;   // line_bad as last read
   // LIMEX
   double *u0, *f0, *fv, *ua, *T[tpf::MAXK], *Tp;
   // host side
@@ -222,6 +226,9 @@ tpf_status spmv64(tpf_grid *g, int level, const double *x, double *y, hipStream_
 // ---- krylov.hip ----
 tpf_status bicgstab(tpf_grid *g, const double *f, double *x, double rtol, int maxit,
                     tpf_solve_stats *st, hipStream_t s);
+// TPF_SMOOTH_LINE: TPF_EBREAKDOWN (with the error text) if the last line LU met a
+// singular pivot block (synchronises s once per factorisation), else TPF_OK.
+tpf_status check_line_factors(tpf_grid *g, hipStream_t s);
 
 // ---- ie.hip ----
 tpf_status ie_step(tpf_grid *g, double *u, double tau, const tpf_newton_opts *o, tpf_newton_stats *st,

@@ -12,12 +12,15 @@
 //                             pass, and in 3D the two-thread split of the row)
 //   harness rap      in out   the two-pass Galerkin product over the launch's thread
 //                             mapping, with a count of the writes to every block
+//   harness line     in out   the line-block Jacobi bodies: the block LU of every line
+//                             and one sweep per line (in place, or from a zero guess)
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <vector>
 
 #include "assemble.hip"
+#include "line.h"
 #include "rap.hip"
 
 namespace tpf {
@@ -228,9 +231,53 @@ int run_rap(Reader &r, FILE *out) {
 
 }  // namespace
 
+// Line smoother of one level: factors every line from the FP64 stencil A into a
+// buffer of exactly 12 N values of T, then runs one sweep per line.  first: rin = b,
+// c kept in a separate buffer, no previous iterate; otherwise rin is the residual,
+// overwritten in place by c, and xi the previous iterate.  Writes xo (2N), the count
+// of lines with a singular pivot, and the factor buffer.
+template <int DIM, typename T>
+int line_level(Reader &r, FILE *out, const Geo &G, double omega, int first) {
+  constexpr int NST = DIM == 3 ? 27 : 9;
+  const long long N = G.N;
+  std::vector<double> A = r.vec((size_t)NST * 4 * N), rin = r.vec(2 * N), xi = r.vec(2 * N);
+  std::vector<T> lf(12 * N), rv(2 * N), cb(2 * N), xv(2 * N), xo(2 * N);
+  for (long long i = 0; i < 2 * N; ++i) {
+    rv[i] = (T)rin[i];
+    xv[i] = (T)xi[i];
+  }
+  const LineGeo lg = line_geo<DIM>(G);
+  double bad = 0;
+  for (long long l = 0; l < lg.S; ++l)
+    if (!line_factor<DIM, T>(G, A.data(), lf.data(), l)) bad += 1;
+  for (long long l = 0; l < lg.S; ++l) {
+    if (first)
+      line_solve<DIM, T, T, 8>(G, lf.data(), rv.data(), cb.data(), nullptr, xo.data(), (T)omega, l);
+    else
+      line_solve<DIM, T, T, 8>(G, lf.data(), rv.data(), rv.data(), xv.data(), xo.data(), (T)omega, l);
+  }
+  std::vector<double> o(xo.begin(), xo.end()), f(lf.begin(), lf.end());
+  put(out, o);
+  put(out, std::vector<double>{bad});
+  put(out, f);
+  return 0;
+}
+
+int run_line(Reader &r, FILE *out) {
+  const int dim = r.i();
+  int n[3];
+  for (int a = 0; a < 3; ++a) n[a] = r.i();
+  const double omega = r.d();
+  const int first = r.i();
+  const int single = r.i();
+  const Geo G{n[0], n[1], n[2], (long long)n[0] * n[1] * n[2]};
+  if (dim == 3) return single ? line_level<3, float>(r, out, G, omega, first) : line_level<3, double>(r, out, G, omega, first);
+  return single ? line_level<2, float>(r, out, G, omega, first) : line_level<2, double>(r, out, G, omega, first);
+}
+
 int main(int argc, char **argv) {
   if (argc != 4) {
-    fprintf(stderr, "usage: harness math|assemble|rap in out\n");
+    fprintf(stderr, "usage: harness math|assemble|rap|line in out\n");
     return 2;
   }
   FILE *in = fopen(argv[2], "rb");
@@ -244,6 +291,7 @@ int main(int argc, char **argv) {
   if (!strcmp(argv[1], "math")) rc = run_math(r, out);
   else if (!strcmp(argv[1], "assemble")) rc = run_assemble(r, out);
   else if (!strcmp(argv[1], "rap")) rc = run_rap(r, out);
+  else if (!strcmp(argv[1], "line")) rc = run_line(r, out);
   fclose(in);
   fclose(out);
   return rc;

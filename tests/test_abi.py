@@ -40,7 +40,7 @@ def test_struct_layouts_match_header():
     assert C.sizeof(L.LimexStats) == 40
 
 
-def _bytes_expected(scn, prec, limex=0):
+def _bytes_expected(scn, prec, limex=0, smoother="point"):
     """Independent re-derivation of the arena size from the documented layout."""
     al = lambda x: (x + 255) // 256 * 256  # noqa: E731
     nst = 27 if scn.dim == 3 else 9
@@ -63,11 +63,13 @@ def _bytes_expected(scn, prec, limex=0):
             tot += al(nst * 4 * Nl * 2) + al(2 * Nl * 4)
         tot += al(2 * Nl * 8)
         tot += 4 * al(2 * Nl * vb)
+        if smoother == "line" and lvl + 1 < len(sizes):  # line LU: three 2x2 blocks per vertex
+            tot += al(12 * Nl * vb)
     nc = 2 * sizes[-1][0] * sizes[-1][1] * sizes[-1][2]
     tot += 2 * al(nc * nc * 8) + al(nc * 4)
     tot += al(nst * 4 * N * 8) if scn.levels > 1 else 0   # Galerkin-product scratch
     tot += 10 * al(2 * N * 8)
-    tot += al(4 * max(1024, (N + 255) // 256) * 8) + al(32 * 8)
+    tot += al(4 * max(1024, (N + 255) // 256) * 8) + al(32 * 8) + al(4)  # partials, scalars, flags
     # step vectors: u0, F0, F(v) and the Newton base point, then the LIMEX tableau
     tot += al(2 * N * 8) * (4 + (1 + limex if limex else 0))
     return tot
@@ -80,6 +82,8 @@ def test_grid_bytes(prec):
     assert nb == _bytes_expected(scn, prec)
     scn2 = W.lens_2d()
     assert tpf.grid_bytes(scn2, precision=prec, limex_stages=2) == _bytes_expected(scn2, prec, 2)
+    for s_ in (scn, scn2):
+        assert tpf.grid_bytes(s_, precision=prec, smoother="line") == _bytes_expected(s_, prec, smoother="line")
 
 
 def test_grid_bytes_c3_fits_hbm():
@@ -127,6 +131,8 @@ def test_invalid_options_rejected():
     assert tpf.validate(scn, nu_pre=0) == L.TPF_EINVAL
     assert tpf.validate(scn, precision=7) == L.TPF_EINVAL
     assert tpf.validate(scn, limex_stages=9) == L.TPF_EINVAL
+    assert tpf.validate(scn, smoother=2) == L.TPF_EINVAL
+    assert tpf.validate(scn, smoother="line") == L.TPF_OK
     big = W.small_cube(9, levels=1)   # 729 vertices -> 1458 unknowns on the only level: allowed
     assert tpf.validate(big) == L.TPF_OK
     huge = W.small_cube(65, levels=2)  # 33^3 coarsest -> too many unknowns for the dense solve

@@ -7,7 +7,9 @@ AddressSanitizer on the host side) and checked without a GPU:
     pass, and (3D) through the two-thread split of the row, against the FP64 oracle;
   * the two-pass Galerkin product over the exact thread mapping of its launches
     (XCD-aware block order included): every scratch and coarse block written exactly
-    once, and the coarse operator equal to the oracle's.
+    once, and the coarse operator equal to the oracle's;
+  * the line-block Jacobi bodies (block LU of every line, one sweep per line in FP64
+    and FP32, from a zero guess and in place) against the oracle's line solve.
 
 Every launch's threads run over buffers of exactly the sizes the kernels get, so the
 sanitizer reports any access outside them; the harness must exit cleanly."""
@@ -34,7 +36,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 
 def _sources():
-    return [SRC] + [os.path.join(CSRC, f) for f in ("assemble.hip", "rap.hip", "stencil.h", "tpf_internal.h")] + \
+    return [SRC] + [os.path.join(CSRC, f) for f in ("assemble.hip", "rap.hip", "line.h", "stencil.h", "tpf_internal.h")] + \
         [os.path.join(ROOT, "include", "tpf.h")]
 
 
@@ -220,3 +222,49 @@ def test_galerkin_product_coverage_and_values(harness, tmp_path, case):
         np.testing.assert_allclose(mc.reshape(-1, 2)[:, 1], np.asarray(Sc[2 * np.arange(Nc) + 1,
                                                                            2 * np.arange(Nc) + 1]).ravel(),
                                    rtol=1e-12, atol=1e-300)
+
+
+LINE_CASES = [
+    ("lens17x9", lambda: W.lens_2d(17, 9), 3, 50.0),
+    ("cube9", lambda: W.small_cube(9, seed=22), 3, 50.0),
+    ("case4_64x32", lambda: W.case4(64), 3, 2e4),
+    ("case5_9", lambda: W.case5(9), 3, 2e4),
+]
+
+
+@pytest.mark.parametrize("case", LINE_CASES, ids=[c[0] for c in LINE_CASES])
+@pytest.mark.parametrize("single", [0, 1], ids=["fp64", "fp32"])
+def test_line_smoother_bodies(harness, tmp_path, case, single):
+    """The line LU and the per-line sweep over every line of every smoothed level
+    (finest 9/27-point operators and Galerkin coarse levels), from a zero guess and in
+    place on a residual, against the oracle's sparse LU of the line part:
+    xo = xi + omega A_L^{-1} r, 1e-11 in FP64, 1e-4 in FP32 (factors and sweep in FP32)."""
+    name, mk, levels, dp = case
+    scn = mk()
+    scn.levels = levels
+    u = W.perturbed_state(scn, 5, dp=dp, sn_lo=0.02, sn_hi=0.6)
+    st = ST.Stage(scn, smoother="line")
+    st.assemble(u.ravel(), 32.0)
+    H = st.H
+    dim = scn.dim
+    rng = np.random.default_rng(9)
+    omega = 2.0 / 3.0
+    for l in range(levels - 1):
+        n3 = tuple(H.sizes[l]) + (1,) * (3 - len(H.sizes[l]))
+        N = int(np.prod(n3))
+        A = H.A[l]
+        AL = G.line_part(A, n3, dim).tocsc()
+        import scipy.sparse.linalg as ssl
+        lu = ssl.splu(AL)
+        r, xi = rng.standard_normal(2 * N), rng.standard_normal(2 * N)
+        for first in (1, 0):
+            vals = [dim, *n3, omega, first, single, csr_to_stencil(A, n3, dim), r, xi]
+            xo, bad, lf = run(harness, "line", vals, tmp_path, [2 * N, 1, 12 * N])
+            assert bad[0] == 0.0
+            want = omega * lu.solve(r) + (0.0 if first else xi)
+            err = max(np.abs(xo[c::2] - want[c::2]).max() / np.abs(want[c::2]).max() for c in (0, 1))
+            print(f"{name} level {l} first={first} {'fp32' if single else 'fp64'}: {err:.2e}")
+            assert err < (1e-4 if single else 1e-11), err
+            # G_k is the inverse of the pivot block: G_k D'_k = I, D'_k = D_k - L_k W_{k-1}
+            Gk = lf[:4 * N].reshape(N, 2, 2)
+            assert np.all(np.isfinite(Gk))
