@@ -46,6 +46,21 @@ HBM_PEAK_GBS = 8000.0
 NST = 27
 
 
+
+# Multigrid settings of every grid the benchmark builds: line-block Jacobi along the
+# last axis, V(1, 1), omega = 2/3 (measured on the 129^3 stage, the 257^3 case-5 layers,
+# case 4 at 4096 x 2048 and stage systems captured from case-4 runs where point
+# smoothing failed).  --smoother point restores V(2, 2) point-block Jacobi.
+SOLVERS = {"line": {"smoother": "line", "nu_pre": 1, "nu_post": 1, "omega": 2.0 / 3.0},
+           "point": {"smoother": "point", "nu_pre": 2, "nu_post": 2, "omega": 2.0 / 3.0}}
+SOLVER = dict(SOLVERS["line"])
+
+
+def solver_label(sv=None):
+    sv = SOLVER if sv is None else sv
+    kind = "line-block Jacobi along the last axis" if sv["smoother"] == "line" else "point-block Jacobi"
+    return f"V({sv['nu_pre']},{sv['nu_post']}) {kind}, omega={sv['omega']:.4g}"
+
 def nonzero_blocks(n) -> int:
     """2x2 blocks of the 27-point stencil matrix that lie in the grid: prod(3 n_a - 2)."""
     out = 1
@@ -64,6 +79,12 @@ def algorithmic_bytes(cls: str, n, Nc_levels) -> float:
     assemble (mixed): FP64 + FP32 matrix writes (48 B per block), F write, state and
       per-vertex data reads (u, pv 32 B, p_dmin 8 B, Q 16 B, mask 1 B), cell data 32 B
     rap: per coarse level, the FP64 fine matrix read and FP64 + FP32 coarse writes.
+    line0 (FP32 line solve of a line sweep): the three line-LU blocks (48 B), the
+      right-hand side or residual read (8 B), c written and read back (16 B), the
+      result written (8 B; 16 B for the FP64 result of the cycle's last sweep) and the
+      previous iterate read (8 B, not for the first sweep from zero): 80, 88 and 96 B
+      per vertex for the first, middle and last sweep of a cycle, averaged over the
+      cycle's sweeps.
     """
     N = n[0] * n[1] * n[2]
     B = nonzero_blocks(n)
@@ -75,6 +96,9 @@ def algorithmic_bytes(cls: str, n, Nc_levels) -> float:
         return B * 32 + N * 48
     if cls == "assemble":
         return B * 48 + N * (16 + 32 + 8 + 16 + 1 + 32)
+    if cls == "line0":
+        k = SOLVER["nu_pre"] + SOLVER["nu_post"]
+        return N * (80 + 88 * max(k - 2, 0) + (96 if k >= 2 else 0)) / max(k, 1)
     if cls == "rap":
         return sum(nf * NST * 32 + nc * NST * 48 for nf, nc in Nc_levels) / max(len(Nc_levels), 1)
     return float("nan")
@@ -141,9 +165,9 @@ def run(args):
     h = 32.0
     rtol = 1e-8
     results = {}
-    hot = ("smooth0", "resid0", "spmv64", "assemble")  # level-0 matrix kernels
+    hot = ("smooth0", "resid0", "spmv64", "assemble", "line0")  # level-0 kernels
     for prec in (["mixed"] if args.no_fp64 else ["mixed", "fp64", "mixed16"]):
-        g = tpf.Grid(scn, precision=prec, levels=6)
+        g = tpf.Grid(scn, precision=prec, levels=6, **SOLVER)
         u0 = g.initial_state()
         f = g.empty()
         x = g.empty()
@@ -217,9 +241,9 @@ def run(args):
     tfile = os.path.join(ROOT, "profiles", "traffic.json")
     if os.path.exists(tfile):
         try:
-            tj = json.load(open(tfile))
-            if tj.get("kernel") == dom and tj.get("source_hash") == _source_hash(dom):
-                traffic = tj.get("bytes_per_launch")
+            tc = json.load(open(tfile)).get("classes", {}).get(dom, {})
+            if tc.get("source_hash") == _source_hash(dom):
+                traffic = tc.get("bytes_per_launch")
         except Exception:
             traffic = None
     line = {
@@ -237,7 +261,7 @@ def run(args):
         "data": "synthetic",
         "config": {"workload": "cube129_lognormal_sigma2_seed3_mixed", "vertices": [129, 129, 129], "dof": 2 * N,
                    "levels": len(lv), "precision": "FP32 multigrid in FP64 BiCGSTAB", "rtol": rtol, "h_s": h,
-                   "smoother": "V(2,2) block-Jacobi omega=2/3",
+                   "smoother": solver_label(),
                    "coarse_levels": (mixed["graph"] or {}).get("timed_with", "stream")},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -260,14 +284,15 @@ def run(args):
     sm = [kernels[k]["gbs"] for k in ("smooth0", "resid0") if k in kernels]
     line["spmv_smoother_gbs"] = {"spmv64": kernels.get("spmv64", {}).get("gbs"),
                                  "smoother_fp32": kernels.get("smooth0", {}).get("gbs"),
-                                 "resid_fp32": kernels.get("resid0", {}).get("gbs")}
+                                 "resid_fp32": kernels.get("resid0", {}).get("gbs"),
+                                 "line_fp32": kernels.get("line0", {}).get("gbs")}
     if not args.no_serve:
         from paper_2506_04763_amd import serve as SV
         prepared = SV.prepare_requests(args.serve_requests)
-        sv = SV.run_benchmark(count=args.serve_requests, quiet=True, prepared=prepared)
+        sv = SV.run_benchmark(count=args.serve_requests, quiet=True, prepared=prepared, solver=SOLVER)
         # the same requests replayed faster: where throughput stops following the rate
         sv["capacity"] = SV.capacity_sweep(rates=(80.0, 160.0, 320.0), count=args.serve_requests,
-                                           prepared=prepared)
+                                           prepared=prepared, solver=SOLVER)
         line["serving"] = sv
         line["p50_ms"], line["p99_ms"] = sv["p50_ms"], sv["p99_ms"]
     if not args.no_cases:
@@ -314,7 +339,7 @@ def limex_run(accepted_target=20, max_attempts=80):
     import workloads as W
     from paper_2506_04763_amd import driver as DR
     scn = W.cube_c4()
-    g = tpf.Grid(scn, precision="mixed", levels=6, limex_stages=3)
+    g = tpf.Grid(scn, precision="mixed", levels=6, limex_stages=3, **SOLVER)
     u = g.initial_state()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -359,7 +384,7 @@ def layered_run(case="case5", max_attempts=400, precision="mixed", rtol=1e-8, ma
     paper = PAPER_CASE5 if case == "case5" else PAPER_CASE4
     m = scn.meta
     t_setup = time.perf_counter()
-    g = tpf.Grid(scn, precision=precision, limex_stages=m["stages"])
+    g = tpf.Grid(scn, precision=precision, limex_stages=m["stages"], **SOLVER)
     u = g.initial_state()
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t_setup
@@ -427,7 +452,7 @@ def case4_compare(cells_x=256, years=10.0, inj_years=2.0, ie_dt=86400.0, precisi
            "levels": scn_on.levels, "precision": precision, "linear_rtol": lin_rtol,
            "paper_table_case4_2": {k: {"T_total_s": v[0], "N_time_step": v[1], "N_nonlinear": v[2], "N_linear": v[3]}
                                    for k, v in PAPER_CASE4_2.items()}}
-    grids = [tpf.Grid(s_, precision=precision, limex_stages=m["stages"]) for s_ in (scn_on, scn_off)]
+    grids = [tpf.Grid(s_, precision=precision, limex_stages=m["stages"], **SOLVER) for s_ in (scn_on, scn_off)]
     if "limex" in schemes:
         from paper_2506_04763_amd import driver as DR
         u = grids[0].initial_state()
@@ -509,7 +534,7 @@ def case1_run(elements=(64, 128, 256, 512)):
     rows, l1s, l2s = [], [], []
     for el in elements:
         scn = W.buckley_leverett(el)
-        g = tpf.Grid(scn, precision="fp64", limex_stages=scn.meta["stages"])
+        g = tpf.Grid(scn, precision="fp64", limex_stages=scn.meta["stages"], **SOLVER)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         u, st = BL.run_gpu(g, scn)
@@ -539,7 +564,7 @@ def case1_run(elements=(64, 128, 256, 512)):
 
 def counters_driver(cycles=4, copy_bytes=1 << 30):
     """Short workload for hardware-counter runs: one 129^3 mixed-precision stage
-    assembly, `cycles` V-cycles (4 fine-level smoother sweeps each), and a plain
+    assembly, `cycles` V-cycles and FP64 SpMVs on the finest level, and a plain
     device-to-device copy of `copy_bytes` bytes whose FETCH_SIZE / WRITE_SIZE readings
     calibrate the counters against a known byte count."""
     import torch
@@ -547,12 +572,13 @@ def counters_driver(cycles=4, copy_bytes=1 << 30):
     import paper_2506_04763_amd as tpf
     import workloads as W
     scn = W.cube_c3()
-    g = tpf.Grid(scn, precision="mixed", levels=6)
+    g = tpf.Grid(scn, precision="mixed", levels=6, **SOLVER)
     u0 = g.initial_state()
     f = g.empty()
     g.assemble_stage(u0, 32.0, f0_out=f)
     for _ in range(cycles):
         g.precondition(f)
+        g.spmv(f)
     a = torch.empty(copy_bytes // 4, dtype=torch.float32, device="cuda")
     a.fill_(1.0)
     b = torch.empty_like(a)
@@ -566,6 +592,7 @@ KERNEL_SOURCES = {  # files whose text defines each timed kernel class
     "smooth0": ["mg.hip", "stencil.h", "tpf_internal.h"],
     "resid0": ["mg.hip", "stencil.h", "tpf_internal.h"],
     "spmv64": ["mg.hip", "stencil.h", "tpf_internal.h"],
+    "line0": ["mg.hip", "line.h", "stencil.h", "tpf_internal.h"],
     "assemble": ["assemble.hip", "tpf_internal.h"],
 }
 
@@ -650,6 +677,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--smoother", choices=sorted(SOLVERS), default="line",
+                    help="multigrid smoother of every grid: line (V(1,1) line-block Jacobi, the default) or point "
+                         "(V(2,2) point-block Jacobi)")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cases", action="store_true",
@@ -675,18 +705,20 @@ def main():
                     help="Table case4_2: implicit Euler + Newton against LIMEX on case 4 (256 x 128 cells, 10 years)")
     ap.add_argument("--schemes", default="limex,implicit_euler", help="schemes of --case4-compare")
     args = ap.parse_args()
+    SOLVER.clear()
+    SOLVER.update(SOLVERS[args.smoother])
     if args.summarise_trace:
         print(summarise_trace(args.summarise_trace, args.steps))
         return
     if args.summarise_counters:
         fetch_dir, write_dir, log = args.summarise_counters
         rows, cal = summarise_counters(fetch_dir, write_dir)
-        run_hash = None
+        run_hashes = None
         with open(log) as fh:
             for line in fh:
                 if '"counters_driver"' in line:
-                    run_hash = json.loads(line)["source_hash"]["smooth0"]
-        if run_hash is None:
+                    run_hashes = json.loads(line)["source_hash"]
+        if run_hashes is None:
             raise SystemExit(f"{log}: no counters_driver line (the stdout of a --counters run)")
         print(f"calibration: FETCH_SIZE factor {cal['fetch_factor']:.4f}, WRITE_SIZE factor {cal['write_factor']:.4f}\n")
         print("| kernel | grid | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes (calibrated) |")
@@ -694,15 +726,23 @@ def main():
         for (name, grid), r in sorted(rows.items(), key=lambda kv: -kv[1]["bytes"]):
             short = _short(name)
             print(f"| `{short}` | {grid} | {r['fetch_kib']:.0f} | {r['write_kib']:.0f} | {r['bytes'] / 1e6:.1f} MB |")
-        sm = [(k, r) for k, r in rows.items() if "k_jacobi_stream" in k[0] and "float, float" in k[0]]
-        if sm:
-            (name, grid), r = max(sm, key=lambda kv: kv[0][1])
-            tj = {"kernel": "smooth0", "kernel_name": _short(name),
-                  "grid": grid, "source_hash": run_hash, "bytes_per_launch": round(r["bytes"]),
-                  "fetch_kib": r["fetch_kib"], "write_kib": r["write_kib"], "calibration": cal,
-                  "source": "profiles/cube129_mixed_hbm_counters.md"}
-            with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
-                json.dump(tj, fh, indent=1)
+        # per kernel class, its finest-level launch (the largest grid of the class's kernel)
+        pick = {"smooth0": lambda k: "k_jacobi_stream" in k and "float, float" in k,
+                "resid0": lambda k: "k_resid_stream" in k and "float" in k,
+                "line0": lambda k: k.startswith("void tpf::(anonymous namespace)::k_line<3, float"),
+                "spmv64": lambda k: "k_spmv64<3" in k}
+        out = {}
+        for cls, match in pick.items():
+            cand = [(k, r) for k, r in rows.items() if match(k[0])]
+            if not cand:
+                continue
+            (name, grid), r = max(cand, key=lambda kv: kv[0][1])
+            out[cls] = {"kernel_name": _short(name), "grid": grid, "source_hash": run_hashes.get(cls),
+                        "bytes_per_launch": round(r["bytes"]), "fetch_kib": r["fetch_kib"],
+                        "write_kib": r["write_kib"]}
+        tj = {"calibration": cal, "source": "profiles/cube129_mixed_hbm_counters.md", "classes": out}
+        with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
+            json.dump(tj, fh, indent=1)
         return
     if args.counters:
         counters_driver()

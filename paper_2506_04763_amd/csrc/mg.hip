@@ -1342,7 +1342,7 @@ tpf_status hierarchy_t(tpf_grid *g, hipStream_t s) {
     }
     prof_end(g, ps, s);
   }
-  {
+  if (g->smoother == TPF_SMOOTH_LINE) {  // the line LU, timed with the Galerkin products
     const int ps = prof_begin(g, TPF_K_RAP, s);
     const tpf_status st = line_factors_t<DIM>(g, s);
     if (st != TPF_OK) return st;

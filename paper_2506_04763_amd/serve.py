@@ -103,7 +103,9 @@ class _Extents:
 
 class Server:
     def __init__(self, budget_bytes: float = 200e9, slots: int = 8, precision: str = "mixed",
-                 device: str = "cuda:0", keep_resident: bool = True, levels_of=None):
+                 device: str = "cuda:0", keep_resident: bool = True, levels_of=None, solver=None):
+        """solver: multigrid settings of every grid (smoother, nu_pre, nu_post, omega);
+        None keeps the library's defaults."""
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -112,6 +114,7 @@ class Server:
             self._slab = torch.empty(self.budget, dtype=torch.uint8, device=self.device)
         self._extents = _Extents(self.budget)
         self.precision = precision
+        self.solver = dict(solver or {})
         self.keep_resident = keep_resident
         self.levels_of = levels_of
         self._lock = threading.Condition()
@@ -163,7 +166,7 @@ class Server:
         return self.levels_of(scn) if self.levels_of else scn.levels
 
     def _bytes(self, req):
-        n = grid_bytes(req.scenario, precision=self.precision, levels=self._levels(req.scenario))
+        n = grid_bytes(req.scenario, precision=self.precision, levels=self._levels(req.scenario), **self.solver)
         return (n + _ALIGN - 1) // _ALIGN * _ALIGN
 
     def _evict(self, key):
@@ -236,7 +239,7 @@ class Server:
                     if res.grid is None:
                         arena = self._slab[res.offset:res.offset + res.nbytes]
                         res.grid = Grid(req.scenario, precision=self.precision, levels=self._levels(req.scenario),
-                                        device=self.device, stream=stream, arena=arena)
+                                        device=self.device, stream=stream, arena=arena, **self.solver)
                     g = res.grid
                     g._stream = stream
                     u0 = g.initial_state()
@@ -283,14 +286,14 @@ def prepare_requests(count=256, rate_per_s=40.0, seed=5, workers=8):
 
 
 def run_benchmark(count=256, rate_per_s=40.0, seed=5, budget_bytes=200e9, slots=8, precision="mixed",
-                  quiet=False, prepared=None, time_scale=1.0):
+                  quiet=False, prepared=None, time_scale=1.0, solver=None):
     """Replays the requests' Poisson arrivals in real time (arrival times multiplied by
     time_scale: 0.5 replays the same requests at twice the rate) and reports latency
     percentiles and throughput."""
     import workloads as W
     reqs, scns = prepared if prepared is not None else prepare_requests(count, rate_per_s, seed)
     srv = Server(budget_bytes=budget_bytes, slots=slots, precision=precision,
-                 levels_of=lambda s: W.SERVE_LEVELS.get(s.n[0], s.levels))
+                 levels_of=lambda s: W.SERVE_LEVELS.get(s.n[0], s.levels), solver=solver)
     # warm the code paths (module load, first launches) outside the clock
     warm = srv.submit(StageRequest(-1, W.request_scenario(W.Request(-1, 0.0, 33, 1.0, 0.05, 999)), arrival=0.0))
     warm.result()

@@ -56,6 +56,39 @@ def test_launch_counts_follow_the_solver(cube):
         assert kt[cls][1] > 0.0, cls
 
 
+def test_launch_counts_follow_the_line_smoother(cube):
+    """V(1, 1) line smoothing: a sweep from zero is one line solve; every other sweep is
+    the level residual followed by a line solve."""
+    scn, u = cube
+    g = tpf.Grid(scn, precision="mixed", smoother="line", nu_pre=1, nu_post=1)
+    g.profile_begin(100000)
+    x, st = stage(g, u)
+    kt = g.profile_end()
+    g.close()
+    print(st, kt, flush=True)
+    assert st["status"] == "TPF_OK" and st["restarts"] == 0
+    it = st["iters"]
+    cyc = 2 * it
+    expect = {
+        "assemble": 1,
+        "rap": scn.levels,  # the Galerkin products and the line LU of all smoothed levels
+        "coarse_lu": 1,
+        "spmv64": 2 * it + 1,
+        "smooth0": 0,
+        "smooth0_first": 0,
+        "line0": 2 * cyc,  # the pre-sweep from zero and the post-sweep
+        "resid0": 2 * cyc,  # the post-sweep's residual and the restricted one
+        "transfer0": 2 * cyc,
+        # level 1: line solve, residual, restriction, the coarsest solve, prolongation,
+        # residual and line solve of the post-sweep
+        "coarse_levels": 7 * cyc,
+    }
+    for cls, n in expect.items():
+        assert kt[cls][0] == n, (cls, kt[cls], n)
+        if n:
+            assert kt[cls][1] > 0.0, cls
+
+
 def test_class_mask_and_results_unchanged(cube):
     scn, u = cube
     g = tpf.Grid(scn, precision="mixed")

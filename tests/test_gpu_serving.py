@@ -27,8 +27,8 @@ def small_requests():
     return reqs
 
 
-def run(reqs, slots, budget=50e9):
-    srv = serve.Server(budget_bytes=budget, slots=slots, precision="mixed")
+def run(reqs, slots, budget=50e9, solver=None):
+    srv = serve.Server(budget_bytes=budget, slots=slots, precision="mixed", solver=solver)
     futs = [srv.submit(q) for q in reqs]
     res = [f.result(timeout=120) for f in futs]
     stats = dict(peak=srv.peak_used, evictions=srv.evictions)
@@ -95,8 +95,8 @@ def test_served_results_match_the_oracle_under_eviction():
     slab again and again and idle grids are evicted: every served 17^3 and 33^3 result
     and one 65^3 result against the oracle's FP64 solve of the same request (assembled
     at the request's initial state, solved to 1e-12), per field, at the mixed-precision
-    bound of the parity suite (1e-5).  The oracle solves run in worker processes
-    while the GPU serves."""
+    bound of the parity suite (1e-5), once with point and once with line smoothing.
+    The oracle solves run in worker processes while the GPU serves."""
     import concurrent.futures as cf
     import multiprocessing as mp
 
@@ -106,21 +106,26 @@ def test_served_results_match_the_oracle_under_eviction():
     ex = cf.ProcessPoolExecutor(max_workers=min(8, len(specs)), mp_context=mp.get_context("spawn"))
     futs = {ex.submit(SO.oracle_stage_solution, sp): r for sp, r in zip(specs, check)}
     reqs = small_requests()
-    need = max(serve.grid_bytes(q.scenario, precision="mixed") for q in reqs)
-    res, st = run(reqs, slots=6, budget=int(need * 2.2))
-    print(f"[serving] served {len(res)} requests, evictions {st['evictions']}, peak {st['peak']}", flush=True)
-    assert st["evictions"] > 0 and all(r.stats["status"] == "TPF_OK" for r in res)
+    served = {}
+    for label, solver in (("point", None), ("line", dict(smoother="line", nu_pre=1, nu_post=1))):
+        need = max(serve.grid_bytes(q.scenario, precision="mixed", **(solver or {})) for q in reqs)
+        res, st = run(reqs, slots=6, budget=int(need * 2.2), solver=solver)
+        print(f"[serving] {label}: served {len(res)} requests, evictions {st['evictions']}, peak {st['peak']}",
+              flush=True)
+        assert st["evictions"] > 0 and all(r.stats["status"] == "TPF_OK" for r in res)
+        served[label] = res
     worst = 0.0
     try:
         for fut in cf.as_completed(futs, timeout=600):
             r = futs[fut]
             _, x_ref, info = fut.result()
-            x = res[r].x
-            err = max(np.linalg.norm(x[c::2] - x_ref[c::2]) / np.linalg.norm(x_ref[c::2]) for c in (0, 1))
-            worst = max(worst, err)
-            print(f"[serving] request {r} ({SIZES[r]}^3): iters {res[r].stats['iters']}, "
-                  f"rel_res_true {res[r].stats['rel_res_true']:.2e}, error vs oracle {err:.2e}", flush=True)
-            assert err < 1e-5, (r, err)
+            for label, res in served.items():
+                x = res[r].x
+                err = max(np.linalg.norm(x[c::2] - x_ref[c::2]) / np.linalg.norm(x_ref[c::2]) for c in (0, 1))
+                worst = max(worst, err)
+                print(f"[serving] {label} request {r} ({SIZES[r]}^3): iters {res[r].stats['iters']}, "
+                      f"rel_res_true {res[r].stats['rel_res_true']:.2e}, error vs oracle {err:.2e}", flush=True)
+                assert err < 1e-5, (label, r, err)
     finally:
         ex.shutdown(cancel_futures=True)
     print(f"[serving] worst error against the oracle: {worst:.2e}", flush=True)
