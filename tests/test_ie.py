@@ -77,6 +77,25 @@ def test_newton_converges_quadratically_on_a_lens_step():
             assert b <= 50.0 * a * a, (a, b)
 
 
+def test_newton_stops_on_a_negligible_update_below_the_rounding_floor():
+    """A relative defect of 1e-16 cannot be reached in FP64: the iteration stops once
+    its update is at rounding level (max|du_p| <= 1e-10 max|p|, max|du_S| <= 1e-10),
+    at the state a reachable tolerance gives; without the update criterion the same
+    step fails."""
+    scn = W.lens_2d(17, 9)
+    f = FV.FV(scn)
+    u0 = W.perturbed_state(scn, 3, dp=20.0, sn_lo=0.05, sn_hi=0.3)
+    u_ref, ref = IE.ie_step(f, u0, 600.0, rtol=1e-12, atol=0.0, xtol=0.0)
+    assert ref["criterion"] == "defect"
+    u, info = IE.ie_step(f, u0, 600.0, rtol=1e-16, atol=0.0, max_newton=12)
+    assert info["converged"] and info["criterion"] == "update"
+    assert info["newton"] <= ref["newton"] + 2
+    for c in (0, 1):
+        assert np.linalg.norm(u[:, c] - u_ref[:, c]) <= 1e-10 * np.linalg.norm(u_ref[:, c] - u0[:, c])
+    with pytest.raises(IE.NewtonFailed):
+        IE.ie_step(f, u0, 600.0, rtol=1e-16, atol=0.0, max_newton=12, xtol=0.0)
+
+
 def test_ie_step_is_conservative_and_consistent():
     """A converged step satisfies m(u_new) - m(u_old) = tau F(u_new) on every row
     without a Dirichlet component (the defect), and small steps move the saturation
