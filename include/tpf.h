@@ -179,15 +179,19 @@ typedef struct tpf_newton_opts {
   double atol;           /* absolute defect tolerance, kg (>= 0)                  */
   double rtol;           /* defect tolerance relative to the step's first (>= 0)  */
   double lin_rtol;       /* relative residual of every linear solve (> 0)         */
+  double xtol;           /* also converged when the accepted update is below it:
+                            max|du_p| <= xtol max|p| and max|du_S| <= xtol
+                            (>= 0; 0 turns the criterion off)                    */
 } tpf_newton_opts;
 
 typedef struct tpf_newton_stats {
-  int32_t converged;     /* 1: the defect met atol or rtol                        */
+  int32_t converged;     /* 1: converged                                          */
   int32_t newton;        /* Newton iterations (accepted steps of the iteration)   */
   int32_t halvings;      /* step halvings of the backtracking                     */
   int32_t linear_solves; /* BiCGSTAB solves                                       */
   int32_t linear_iters;  /* BiCGSTAB iterations summed over the solves            */
-  int32_t reserved;
+  int32_t criterion;     /* 0: not converged, 1: the defect met atol or rtol,
+                            2: the update met xtol                              */
   double defect0;        /* ||G(u_old)|| = tau ||F(u_old)|| (kg)                   */
   double defect;         /* ||G|| at exit                                         */
 } tpf_newton_stats;
@@ -300,7 +304,11 @@ tpf_status tpf_storage(tpf_grid *g, const double *u, double *m, tpf_stream strea
  * with BiCGSTAB + GMG to opts->lin_rtol.  The defect ||G|| (2-norm over the rows
  * without a Dirichlet component, kg) starts at tau ||F(u_old)||; the step converges when
  * it is <= opts->atol or <= opts->rtol times its initial value (the solver settings of
- * Section 5 use 1e-8 and 1e-6).  A trial whose defect does not fall below its base's is
+ * Section 5 use 1e-8 and 1e-6), or when the accepted update is negligible
+ * (opts->xtol, relative for the pressure, absolute for the saturation: the defect
+ * of a step near equilibrium can sit on its FP64 rounding floor above both
+ * tolerances, ~1e-7 kg for one-day steps of case 4 at 5e7 Pa).  A trial whose defect
+ * does not fall below its base's is
  * halved, at most opts->max_halvings times in a row.  u must satisfy the Dirichlet
  * values.  Leaves the last stage matrix assembled (at the final iterate).
  * Returns TPF_OK (u advanced), TPF_NOT_CONVERGED (no convergence within
@@ -320,7 +328,7 @@ tpf_status tpf_ie_step(tpf_grid *g, double *u, double tau, const tpf_newton_opts
  * opts->lin_rtol), p += delta_p with S untouched.  As h_p -> 0 that is the Newton step
  * of F_w/rho_w + F_n/rho_n = 0 (the storages cancel), which holds at the end up to
  * O(h_p).  Stops when max|delta_p| <= max(opts->atol, opts->rtol max|p|) (Pa);
- * opts->max_halvings is unused.  stats->defect0 / defect: the first and last
+ * opts->max_halvings and opts->xtol are unused.  stats->defect0 / defect: the first and last
  * max|delta_p|.  Leaves A(u; h_p) assembled.  Returns TPF_OK, TPF_NOT_CONVERGED (u
  * unchanged) or an error (u unchanged). */
 tpf_status tpf_project_pressure(tpf_grid *g, double *u, double h_p, const tpf_newton_opts *opts,

@@ -218,13 +218,14 @@ class Grid:
         L.check(self.lib.tpf_storage(self.handle, _ptr(u), _ptr(m), self._sptr()), "tpf_storage")
         return m
 
-    def ie_step(self, u, tau, atol=1e-8, rtol=1e-6, lin_rtol=1e-6, max_newton=30, max_halvings=8, maxit=500):
+    def ie_step(self, u, tau, atol=1e-8, rtol=1e-6, lin_rtol=1e-6, max_newton=30, max_halvings=8, maxit=500,
+                xtol=1e-10):
         """One implicit Euler step with Newton in place on the device tensor u; returns
         (converged, stats).  On failure u is unchanged."""
         if not (isinstance(u, self.torch.Tensor) and u.device == self.device and u.dtype == self.torch.float64):
             raise TypeError("u must be a float64 tensor on the grid's device")
         o = L.NewtonOpts(int(max_newton), int(max_halvings), int(maxit), 0, float(atol), float(rtol),
-                         float(lin_rtol))
+                         float(lin_rtol), float(xtol))
         st = L.NewtonStats()
         status = self.lib.tpf_ie_step(self.handle, _ptr(u), float(tau), C.byref(o), C.byref(st), self._sptr())
         L.check(status, "tpf_ie_step", soft_ok=True)

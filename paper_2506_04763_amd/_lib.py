@@ -67,12 +67,13 @@ class LimexStats(C.Structure):
 
 class NewtonOpts(C.Structure):
     _fields_ = [("max_newton", C.c_int32), ("max_halvings", C.c_int32), ("maxit", C.c_int32),
-                ("reserved", C.c_int32), ("atol", C.c_double), ("rtol", C.c_double), ("lin_rtol", C.c_double)]
+                ("reserved", C.c_int32), ("atol", C.c_double), ("rtol", C.c_double), ("lin_rtol", C.c_double),
+                ("xtol", C.c_double)]
 
 
 class NewtonStats(C.Structure):
     _fields_ = [("converged", C.c_int32), ("newton", C.c_int32), ("halvings", C.c_int32),
-                ("linear_solves", C.c_int32), ("linear_iters", C.c_int32), ("reserved", C.c_int32),
+                ("linear_solves", C.c_int32), ("linear_iters", C.c_int32), ("criterion", C.c_int32),
                 ("defect0", C.c_double), ("defect", C.c_double)]
 
     def as_dict(self):

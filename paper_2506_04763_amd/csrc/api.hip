@@ -559,7 +559,7 @@ tpf_status tpf_ie_step(tpf_grid *g, double *u, double tau, const tpf_newton_opts
   if (!g || !u || !opts) { set_error("NULL argument"); return TPF_EINVAL; }
   if (!(tau > 0.0) || !std::isfinite(tau)) { set_error("tau must be positive and finite"); return TPF_EINVAL; }
   if (opts->max_newton < 1 || opts->max_halvings < 0 || opts->maxit < 1 || !(opts->atol >= 0.0) ||
-      !(opts->rtol >= 0.0) || !(opts->lin_rtol > 0.0)) {
+      !(opts->rtol >= 0.0) || !(opts->lin_rtol > 0.0) || !(opts->xtol >= 0.0) || !std::isfinite(opts->xtol)) {
     set_error("invalid Newton options");
     return TPF_EINVAL;
   }

@@ -10,6 +10,9 @@
 // with its norm, and solve A delta = r with BiCGSTAB + GMG.  The defect is
 // ||G(u_k)|| = tau ||r||; u_0 = u_old.  Globalisation: a trial u_k + lam delta whose
 // defect is not below its base's is halved (at most max_halvings times in a row).
+// Convergence: the defect meets atol or rtol times its first value, or the accepted
+// update is negligible (xtol): near equilibrium the defect can sit on its FP64
+// rounding floor above both.
 #include <cmath>
 
 #include "tpf_internal.h"
@@ -72,12 +75,39 @@ __global__ void __launch_bounds__(BS) k_add_p(long long N, double *__restrict__ 
   }
 }
 
-// out[0], out[1] = maxima of the two rows of nblk partials (one block)
-__global__ void __launch_bounds__(1024) k_max2(const double *__restrict__ part, unsigned nblk,
-                                               double *__restrict__ out) {
-  __shared__ double sm[2][16];
+// block maxima of |u - ua| on the pressure and the saturation components and of the
+// updated |p| (grid-stride): the size of the accepted Newton update
+__global__ void __launch_bounds__(BS) k_upd_max(long long N, const double *__restrict__ u,
+                                                const double *__restrict__ ua, double *__restrict__ part) {
+  __shared__ double sm[3][BS / 64];
+  double m[3] = {0.0, 0.0, 0.0};
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < N; v += (long long)gridDim.x * blockDim.x) {
+    m[0] = fmax(m[0], fabs(u[2 * v] - ua[2 * v]));
+    m[1] = fmax(m[1], fabs(u[2 * v + 1] - ua[2 * v + 1]));
+    m[2] = fmax(m[2], fabs(u[2 * v]));
+  }
 #pragma unroll
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < 3; ++k) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m[k] = fmax(m[k], __shfl_down(m[k], off, 64));
+    if ((threadIdx.x & 63) == 0) sm[k][threadIdx.x >> 6] = m[k];
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    double r = 0.0;
+#pragma unroll
+    for (int w = 0; w < BS / 64; ++w) r = fmax(r, sm[threadIdx.x][w]);
+    part[(long long)threadIdx.x * gridDim.x + blockIdx.x] = r;
+  }
+}
+
+// out[0 .. K-1] = maxima of the K rows of nblk partials (one block)
+template <int K>
+__global__ void __launch_bounds__(1024) k_maxk(const double *__restrict__ part, unsigned nblk,
+                                               double *__restrict__ out) {
+  __shared__ double sm[K][16];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
     double m = 0.0;
     for (unsigned b = threadIdx.x; b < nblk; b += 1024) m = fmax(m, part[(long long)k * nblk + b]);
 #pragma unroll
@@ -85,7 +115,7 @@ __global__ void __launch_bounds__(1024) k_max2(const double *__restrict__ part, 
     if ((threadIdx.x & 63) == 0) sm[k][threadIdx.x >> 6] = m;
   }
   __syncthreads();
-  if (threadIdx.x < 2) {
+  if (threadIdx.x < K) {
     double m = 0.0;
     for (int w = 0; w < 16; ++w) m = fmax(m, sm[threadIdx.x][w]);
     out[threadIdx.x] = m;
@@ -129,6 +159,13 @@ tpf_status ie_step(tpf_grid *g, double *u, double tau, const tpf_newton_opts *o,
     TPF_TRY(build_hierarchy(g, s));
     g->assembled = true;
     g->has_f0 = false;
+    if (have_dir) {  // size of the update from the base point (read back with the defect;
+                     // three rows of partials, consumed before the defect reuses them)
+      k_upd_max<<<RED_BLOCKS, BS, 0, s>>>(g->P.N, u, g->ua, g->part);
+      TPF_LAUNCH_CHECK();
+      k_maxk<3><<<1, 1024, 0, s>>>(g->part, RED_BLOCKS, g->scal + S_IE_DP);
+      TPF_LAUNCH_CHECK();
+    }
     double rr = 0.0;
     TPF_TRY(rhs_norm2(g, u, inv_tau, rr, s));
     const double d = tau * sqrt(rr);
@@ -143,6 +180,7 @@ tpf_status ie_step(tpf_grid *g, double *u, double tau, const tpf_newton_opts *o,
       ns.defect = d;
       if (d <= o->atol) {
         ok = true;
+        ns.criterion = 1;
         break;
       }
     } else {
@@ -158,6 +196,13 @@ tpf_status ie_step(tpf_grid *g, double *u, double tau, const tpf_newton_opts *o,
       ns.defect = d;
       if (d <= o->atol || d <= o->rtol * d0) {
         ok = true;
+        ns.criterion = 1;
+        break;
+      }
+      const double up = g->hscal[S_IE_DP], us = g->hscal[S_IE_DS], pmax = g->hscal[S_IE_PMAX];
+      if (o->xtol > 0.0 && up <= o->xtol * pmax && us <= o->xtol) {  // the update is at rounding level
+        ok = true;
+        ns.criterion = 2;
         break;
       }
       if (ns.newton >= o->max_newton) break;
@@ -215,7 +260,7 @@ tpf_status project_pressure(tpf_grid *g, double *u, double h_p, const tpf_newton
     }
     k_add_p<<<RED_BLOCKS, BS, 0, s>>>(g->P.N, u, g->xb, g->part);
     TPF_LAUNCH_CHECK();
-    k_max2<<<1, 1024, 0, s>>>(g->part, RED_BLOCKS, g->scal + S_PROJ_DP);
+    k_maxk<2><<<1, 1024, 0, s>>>(g->part, RED_BLOCKS, g->scal + S_PROJ_DP);
     TPF_LAUNCH_CHECK();
     TPF_HIP(hipMemcpyAsync(g->hscal, g->scal, NSCAL * sizeof(double), hipMemcpyDeviceToHost, s));
     TPF_HIP(hipStreamSynchronize(s));

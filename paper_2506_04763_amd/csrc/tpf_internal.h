@@ -22,8 +22,9 @@ constexpr int NSCAL = 32;         // device scalars of the Krylov solver
 // Scalars of the Krylov recurrence kept on the device (indices into g->scal).
 enum Scal {
   S_RHO = 0, S_RHO_OLD, S_ALPHA, S_OMEGA, S_BETA, S_RV, S_TS, S_TT, S_RR, S_FF, S_WW,
-  S_NORM_A, S_NORM_B, S_NORM_C, S_NORM_D, S_IE_RR, S_PROJ_DP, S_PROJ_P, S_COUNT
+  S_NORM_A, S_NORM_B, S_NORM_C, S_NORM_D, S_IE_RR, S_PROJ_DP, S_PROJ_P, S_IE_DP, S_IE_DS, S_IE_PMAX, S_COUNT
 };
+static_assert(S_COUNT <= NSCAL, "device scalars exceed their array");
 
 // Physical and geometric constants passed by value to every kernel.
 struct Phys {

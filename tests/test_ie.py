@@ -236,3 +236,31 @@ def test_gpu_ie_case1_against_table_error1(el):
     print(f"[ie] case1 {el}: {info} L1 {l1:.4f} (paper {p1}) L2 {l2:.4f} (paper {p2})", flush=True)
     assert info["steps"] == steps and info["failures"] == 0
     assert abs(l1 / p1 - 1) < 0.03 and abs(l2 / p2 - 1) < 0.03
+
+
+@pytest.mark.gpu
+def test_gpu_ie_update_criterion_matches_the_oracle():
+    """An unreachable relative defect (1e-16): the GPU's Newton stops on the update
+    criterion like the oracle's, at the same state; with the criterion off it fails
+    and leaves u unchanged."""
+    torch = pytest.importorskip("torch")
+    tpf = pytest.importorskip("paper_2506_04763_amd")
+    scn = W.lens_2d(17, 9)
+    scn.levels = 3
+    u0 = W.perturbed_state(scn, 3, dp=20.0, sn_lo=0.05, sn_hi=0.3)
+    ref_u, ref = IE.ie_step(FV.FV(scn), u0, 600.0, rtol=1e-16, atol=0.0, max_newton=12)
+    assert ref["criterion"] == "update"
+    g = tpf.Grid(scn, precision="fp64")
+    u = torch.as_tensor(u0.ravel().copy(), device="cuda")
+    ok, st = g.ie_step(u, 600.0, atol=0.0, rtol=1e-16, lin_rtol=1e-12, maxit=500, max_newton=12)
+    print("[ie] update criterion gpu", st, "oracle", ref["newton"], ref["halvings"], flush=True)
+    assert ok and st["criterion"] == 2
+    assert abs(st["newton"] - ref["newton"]) <= 1
+    out = u.cpu().numpy().reshape(-1, 2)
+    for c in (0, 1):
+        assert np.linalg.norm(out[:, c] - ref_u[:, c]) <= 1e-9 * np.linalg.norm(ref_u[:, c] - u0[:, c])
+    u = torch.as_tensor(u0.ravel().copy(), device="cuda")
+    ok, st = g.ie_step(u, 600.0, atol=0.0, rtol=1e-16, lin_rtol=1e-12, maxit=500, max_newton=12, xtol=0.0)
+    assert not ok and st["criterion"] == 0
+    np.testing.assert_array_equal(u.cpu().numpy(), u0.ravel())
+    g.close()
