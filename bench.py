@@ -307,8 +307,8 @@ def run(args):
                              "paper_L2": [r["paper_limex"]["L2"] for r in c1["rows"]]}
         except Exception as e:  # reported, never fatal to the benchmark line
             line["case1"] = {"error": repr(e)}
-        keys = ("dof", "reached_t_end", "t_end_s", "T_total_s", "N_limex", "t_limex_s", "N_linear_solves",
-                "t_linear_solve_s", "bicgstab_iterations", "unconverged_solves", "sn_max")
+        keys = ("dof", "precision", "reached_t_end", "t_end_s", "T_total_s", "N_limex", "t_limex_s",
+                "N_linear_solves", "t_linear_solve_s", "bicgstab_iterations", "unconverged_solves", "sn_max")
         for case, pe in (("case5", "256"), ("case4", "64")):
             try:
                 c = layered_run(case)
@@ -369,11 +369,20 @@ PAPER_CASE4 = {64: (487.4, "47+1", 487.4 / 48, 307, 0.290), 128: (267.3, "47+1",
                256: (130.7, "47+1", 130.7 / 48, 307, 0.067), 512: (65.0, "47+1", 65.0 / 48, 311, 0.033)}
 
 
-def layered_run(case="case5", max_attempts=400, precision="mixed", rtol=1e-8, maxit=200):
+# Multigrid precision per layered case: case 4's 2D section runs its multigrid in FP64.
+# In FP32 its stage systems need 13-80 BiCGSTAB iterations where FP64 needs 6-19
+# (systems captured at 256 x 128 cells), and at 4096 x 2048 cells solves fail at the
+# 200-iteration cap (6-12 of about 460-1170 per run); each failure collapses the step
+# size, so the run's length depends on where failures fall.  In FP64: 1 failure.
+LAYERED_PRECISION = {"case5": "mixed", "case4": "fp64"}
+
+
+def layered_run(case="case5", max_attempts=400, precision=None, rtol=1e-8, maxit=200):
     """Section 5, case 5 (257^3 layered cube) or case 4 (4096 x 2048 layered section)
     on one GPU: adaptive LIMEX (k = 3, TOL 5e-3, safety 0.75, tau0 32 s, tau_max
-    100 d) from t = 0 to 128 min, FP32 multigrid inside FP64 BiCGSTAB to rtol with at
-    most maxit iterations per stage solve (a stage solve that fails rejects the step),
+    100 d) from t = 0 to 128 min, the multigrid in LAYERED_PRECISION[case] (None) inside
+    FP64 BiCGSTAB to rtol with at most maxit iterations per stage solve (a stage solve
+    that fails rejects the step),
     every step timed on the host around the device work (inputs resident; the state
     never leaves the GPU).  One progress line per attempted step on stderr."""
     import torch
@@ -382,6 +391,7 @@ def layered_run(case="case5", max_attempts=400, precision="mixed", rtol=1e-8, ma
     import workloads as W
     scn = W.case5(257) if case == "case5" else W.case4(4096)
     paper = PAPER_CASE5 if case == "case5" else PAPER_CASE4
+    precision = LAYERED_PRECISION[case] if precision is None else precision
     m = scn.meta
     t_setup = time.perf_counter()
     g = tpf.Grid(scn, precision=precision, limex_stages=m["stages"], **SOLVER)
@@ -423,7 +433,7 @@ def layered_run(case="case5", max_attempts=400, precision="mixed", rtol=1e-8, ma
 PAPER_CASE4_2 = {"implicit_euler": (3938.76, "3650", 176596, 375093), "limex": (275.28, "6206+75", None, 58093)}
 
 
-def case4_compare(cells_x=256, years=10.0, inj_years=2.0, ie_dt=86400.0, precision="mixed", lin_rtol=1e-6,
+def case4_compare(cells_x=256, years=10.0, inj_years=2.0, ie_dt=86400.0, precision="fp64", lin_rtol=1e-6,
                   max_limex_attempts=40000, schemes=("limex", "implicit_euler"), wall_limit_s=1000.0,
                   max_newton=50, ie_lin_rtol=1e-6):
     """Table case4_2 of Section 5: case 4 on 256 x 128 cells for 10 years with the
