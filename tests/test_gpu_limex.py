@@ -19,10 +19,12 @@ def per_field(a, b):
     return max(float(np.linalg.norm(a[c::2] - b[c::2]) / np.linalg.norm(b[c::2])) for c in (0, 1))
 
 
-def run_sequence(scn, steps, stages, dt0, tol=5e-3, safety=0.75, dt_max=8.64e6, precision="fp64"):
-    g = tpf.Grid(scn, precision=precision, limex_stages=stages)
+def run_sequence(scn, steps, stages, dt0, tol=5e-3, safety=0.75, dt_max=8.64e6, precision="fp64",
+                 smoother="point"):
+    kw = dict(smoother="line", nu_pre=1, nu_post=1) if smoother == "line" else {}
+    g = tpf.Grid(scn, precision=precision, limex_stages=stages, **kw)
     u = torch.as_tensor(scn.u0.ravel().copy(), device="cuda")
-    ref = ST.Stage(scn)
+    ref = ST.Stage(scn, smoother="line", nu1=1, nu2=1) if smoother == "line" else ST.Stage(scn)
     uo = scn.u0.ravel().copy()
     t = to = 0.0
     dt = dto = dt0
@@ -59,6 +61,19 @@ def test_limex_cube_three_stages():
     scn = W.small_cube(9, sigma=1.5, seed=31, levels=3)
     log, ug, uo = run_sequence(scn, steps=3, stages=3, dt0=32.0)
     print(log)
+    assert per_field(ug, uo) < 1e-8
+
+
+@pytest.mark.parametrize("name,mk,steps,stages", [
+    ("cube9", lambda: W.small_cube(9, sigma=1.5, seed=31, levels=3), 3, 3),
+    ("case4_64x32", lambda: W.case4(64), 4, 3),
+])
+def test_limex_steps_with_the_line_smoother(name, mk, steps, stages):
+    """The benchmark's multigrid (V(1,1) line-block Jacobi) inside LIMEX steps, against
+    the oracle with the same smoother: same decisions, eps, steps and states."""
+    scn = mk()
+    log, ug, uo = run_sequence(scn, steps=steps, stages=stages, dt0=32.0, smoother="line")
+    print(name, log)
     assert per_field(ug, uo) < 1e-8
 
 

@@ -23,8 +23,8 @@ def _static_solve(g, f, rtol, maxit=400):
     return status, x, st.as_dict()
 
 
-def _system(scn, prec, seed):
-    g = tpf.Grid(scn, precision=prec)
+def _system(scn, prec, seed, **solver):
+    g = tpf.Grid(scn, precision=prec, **solver)
     u = torch.as_tensor(W.perturbed_state(scn, seed, sn_lo=0.05, sn_hi=0.5).ravel(), device="cuda")
     f = g.empty()
     g.assemble_stage(u, 32.0, f0_out=f)
@@ -48,6 +48,23 @@ def test_static_solve_equals_arena_solve_twice_then_smaller():
         # the grid's own solve is unaffected by the static call
         x_again, _ = g.solve_stage(f, rtol=rtol, maxit=400)
         np.testing.assert_array_equal(x_again.cpu().numpy(), x_ref.cpu().numpy())
+        g.close()
+
+
+def test_static_solve_with_the_line_smoother():
+    """The benchmark's multigrid (V(1,1) line-block Jacobi): the static solve equals the
+    arena solve bit for bit, on a mixed 3D grid and then a smaller FP64 2D grid."""
+    cases = [(W.small_cube(17, sigma=2.0, seed=23, levels=3), "mixed", 1e-8), (W.lens_2d(17, 9), "fp64", 1e-10)]
+    cases[1][0].levels = 3
+    for scn, prec, rtol in cases:
+        g, f = _system(scn, prec, 6, smoother="line", nu_pre=1, nu_post=1)
+        x_ref, st_ref = g.solve_stage(f, rtol=rtol, maxit=400)
+        status, x, st = _static_solve(g, f, rtol)
+        torch.cuda.synchronize()
+        print(f"[no-alloc] line {scn.name} {prec}: arena {st_ref['iters']} its, static {st['iters']} its", flush=True)
+        assert status == L.TPF_OK, L.last_error()
+        assert st["iters"] == st_ref["iters"] and st["rel_res_true"] == st_ref["rel_res_true"]
+        np.testing.assert_array_equal(x.cpu().numpy(), x_ref.cpu().numpy())
         g.close()
 
 
