@@ -247,6 +247,10 @@ class Grid:
         """Replay the V-cycle's coarse levels as one captured HIP graph (or not)."""
         L.check(self.lib.tpf_set_coarse_graph(self.handle, int(bool(enable))), "tpf_set_coarse_graph")
 
+    def set_line_pairs(self, max_lines=32768):
+        """Line smoother: levels with fewer lines use two threads per line (identical results)."""
+        L.check(self.lib.tpf_set_line_pairs(self.handle, int(max_lines)), "tpf_set_line_pairs")
+
     # -- inspection ------------------------------------------------------------------
     def level_dims(self, level):
         n = (C.c_int32 * 3)()

@@ -108,6 +108,7 @@ _SIGS = {
     "tpf_ie_step": (C.c_int32, [VP, DP, C.c_double, C.POINTER(NewtonOpts), C.POINTER(NewtonStats), VP]),
     "tpf_project_pressure": (C.c_int32, [VP, DP, C.c_double, C.POINTER(NewtonOpts), C.POINTER(NewtonStats), VP]),
     "tpf_set_coarse_graph": (C.c_int32, [VP, C.c_int32]),
+    "tpf_set_line_pairs": (C.c_int32, [VP, C.c_int64]),
     "tpf_levels": (C.c_int32, [VP]),
     "tpf_level_dims": (C.c_int32, [VP, C.c_int32, C.POINTER(C.c_int32)]),
     "tpf_copy_matrix": (C.c_int32, [VP, C.c_int32, C.c_int32, DP, VP]),

@@ -271,6 +271,7 @@ tpf_status tpf_create_grid(const tpf_grid_desc *d, void *arena, size_t arena_byt
   g->kmax = d->limex_stages;
   g->omega = d->omega;
   g->smoother = d->smoother;
+  g->line_pair_max = TPF_LINE_PAIR_MAX_LINES;
   g->ncells = L.ncells;
   g->bytes = L.total;
   Phys &P = g->P;
@@ -583,6 +584,15 @@ tpf_status tpf_set_coarse_graph(tpf_grid *g, int32_t enable) {
   g_err[0] = 0;
   if (!g) { set_error("NULL argument"); return TPF_EINVAL; }
   g->coarse_graph = enable ? 1 : 0;
+  return TPF_OK;
+}
+
+tpf_status tpf_set_line_pairs(tpf_grid *g, int64_t max_lines) {
+  if (!g || max_lines < 0) {
+    set_error("need a grid and max_lines >= 0");
+    return TPF_EINVAL;
+  }
+  g->line_pair_max = max_lines;
   return TPF_OK;
 }
 

@@ -996,12 +996,17 @@ __global__ void __launch_bounds__(BS) k_rescale(const Geo G, double *__restrict_
 // ---- V-cycle driver ----------------------------------------------------------
 // TPF_MIXED16 coarse levels: sweep (first: zero initial guess) and residual with the
 // FP16 matrix; return false where the level is not stored in FP16.
-// ---- line-block Jacobi (TPF_SMOOTH_LINE): one thread per vertex line -----------
-// Few threads walk long lines, so the launches use one wavefront per block to spread
-// the lines over the compute units, and each thread keeps 16 steps of loads in flight
-// (measured against 8, 24 and 32: 718 -> 504 us per sweep on 4097 lines of 2049
-// vertices, 71 -> 57 us on 129^3, 310 -> 328 us on 257^3).
+// ---- line-block Jacobi (TPF_SMOOTH_LINE): two threads per vertex line ------------
+// The twisted factorisation splits every line at its middle: lanes l and l + 32 of a
+// wavefront run the top and the bottom chain of the same line and exchange their edge
+// values with a lane shuffle, so a wavefront covers 32 lines and each chain is half a
+// line long (against one thread per line: 504 -> 282 us per sweep on 4097 lines of 2049
+// vertices, 57 -> 46 us on 129^3).  Few threads walk long lines, so the launches use one wavefront per block
+// to spread the lines over the compute units, and each thread keeps 16 steps of loads
+// in flight (one thread per line, measured against 8, 24 and 32 steps: 718 -> 504 us
+// per sweep on 4097 lines of 2049 vertices, 71 -> 57 us on 129^3).
 constexpr int LINE_BS = 64;
+constexpr int LINES_PER_BLOCK = 32;
 #ifndef TPF_LINE_CHUNK
 #define TPF_LINE_CHUNK 16
 #endif
@@ -1014,12 +1019,35 @@ __global__ void __launch_bounds__(LINE_BS) k_line_factor(const Geo G, const doub
   if (!line_factor<DIM, TO>(G, A, lf, l)) atomicAdd(bad, 1);
 }
 
+// Levels with at least g->line_pair_max lines (default TPF_LINE_PAIR_MAX_LINES) have
+// parallelism enough with one thread per line (both chains in turn, the same operations
+// in the same order), which reads each step's blocks as 1 KB segments instead of two
+// 512 B ones: 257^3 (66049 lines) 328 us per sweep against 353 us with pairs.
+
 template <int DIM, typename T, typename TO>
-__global__ void __launch_bounds__(LINE_BS) k_line(const Geo G, const T *__restrict__ lf, const T *rin, T *cbuf,
-                                                  const T *__restrict__ xi, TO *__restrict__ xo, const T omega) {
+__global__ void __launch_bounds__(LINE_BS) k_line_single(const Geo G, const T *__restrict__ lf, const T *rin,
+                                                         T *cbuf, const T *__restrict__ xi, TO *__restrict__ xo,
+                                                         const T omega) {
   const long long l = (long long)blockIdx.x * LINE_BS + threadIdx.x;
   if (l >= line_geo<DIM>(G).S) return;
   line_solve<DIM, T, TO, TPF_LINE_CHUNK>(G, lf, rin, cbuf, xi, xo, omega, l);
+}
+
+template <int DIM, typename T, typename TO>
+__global__ void __launch_bounds__(LINE_BS) k_line(const Geo G, const T *__restrict__ lf, const T *rin, T *cbuf,
+                                                  const T *__restrict__ xi, TO *__restrict__ xo, const T omega) {
+  const int lane = threadIdx.x;  // the block is one wavefront
+  const bool top = lane < LINES_PER_BLOCK;
+  const long long l = (long long)blockIdx.x * LINES_PER_BLOCK + (lane & (LINES_PER_BLOCK - 1));
+  const bool valid = l < line_geo<DIM>(G).S;  // the same for both lanes of a pair
+  T c0 = 0, c1 = 0;
+  if (valid) line_forward<DIM, T, TPF_LINE_CHUNK>(G, lf, rin, cbuf, l, top, c0, c1);
+  // every lane takes part in the exchange: c_{m-1} from the top lane, c_{m+1} from the bottom
+  const T o0 = __shfl_xor(c0, LINES_PER_BLOCK, 64), o1 = __shfl_xor(c1, LINES_PER_BLOCK, 64);
+  if (!valid) return;
+  T z0, z1;
+  line_middle<DIM, T>(G, lf, rin, l, top ? c0 : o0, top ? c1 : o1, top ? o0 : c0, top ? o1 : c1, z0, z1);
+  line_backward<DIM, T, TO, TPF_LINE_CHUNK>(G, lf, cbuf, xi, xo, omega, l, top, z0, z1);
 }
 
 // Line LU of every level but the coarsest from its FP64 matrix, in the level type.
@@ -1148,9 +1176,14 @@ tpf_status vcycle_t(tpf_grid *g, const double *bin, double *xout, hipStream_t s,
       if (st != TPF_OK) return st;
       rin = R;
     }
-    const unsigned nb = blocks_for(line_geo<DIM>(geo(lv)).S, LINE_BS);
-    TPF_HIP(launch(g, l == 0 ? TPF_K_LINE0 : TPF_K_COARSE_LEVELS, k_line<DIM, T, TO>, nb, (unsigned)LINE_BS, s,
-                   geo(lv), (const T *)lv.lf, rin, R, xi, xo, om));
+    const long long nl = line_geo<DIM>(geo(lv)).S;
+    const int cls = l == 0 ? TPF_K_LINE0 : TPF_K_COARSE_LEVELS;
+    if (nl < g->line_pair_max)
+      TPF_HIP(launch(g, cls, k_line<DIM, T, TO>, blocks_for(nl, LINES_PER_BLOCK), (unsigned)LINE_BS, s, geo(lv),
+                     (const T *)lv.lf, rin, R, xi, xo, om));
+    else
+      TPF_HIP(launch(g, cls, k_line_single<DIM, T, TO>, blocks_for(nl, LINE_BS), (unsigned)LINE_BS, s, geo(lv),
+                     (const T *)lv.lf, rin, R, xi, xo, om));
     return TPF_OK;
   };
   // pre-smoothing, residual and restriction of level l (into l + 1, with l + 1's first

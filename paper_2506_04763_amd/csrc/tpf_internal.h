@@ -18,6 +18,7 @@ constexpr double SE_MIN = 1.0e-6; // lower clamp of the effective saturation
 constexpr int BS = 256;           // threads per block of the vertex kernels
 constexpr int RED_BLOCKS = 1024;  // fixed grid of the grid-stride reduction kernels
 constexpr int NSCAL = 32;         // device scalars of the Krylov solver
+constexpr long long TPF_LINE_PAIR_MAX_LINES = 32768;  // default of tpf_set_line_pairs
 
 // Scalars of the Krylov recurrence kept on the device (indices into g->scal).
 enum Scal {
@@ -96,6 +97,7 @@ struct tpf_grid {
   int *line_bad;        // TPF_SMOOTH_LINE: lines whose LU met a singular pivot block
   bool line_unchecked;  // line LU recomputed since line_bad was last read
   int line_bad_count;   // line_bad as last read
+  long long line_pair_max;  // levels with fewer lines solve each line with two threads
   // LIMEX
   double *u0, *f0, *fv, *ua, *T[tpf::MAXK], *Tp;
   // host side

@@ -142,3 +142,20 @@ def test_line_converges_where_point_smoothing_stalls():
     assert out["point"][1]["rel_res_true"] > 1e-3
     assert out["point"][0]["iters"] >= 10 * out["line"][0]["iters"]
     assert out["line"][0]["iters"] <= 10
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_one_thread_and_two_threads_per_line_agree(case, prec):
+    """Levels below the line-count threshold solve each line with a pair of threads
+    (the twisted factorisation's two chains), the others with one thread running both
+    chains in turn: the same operations in the same order, so one V-cycle is bitwise
+    identical either way (threshold 0 forces one thread everywhere), and matches the
+    oracle."""
+    g = _grid(case, prec)
+    b = torch.as_tensor(case["F"], device="cuda")
+    x_pairs = g.precondition(b).cpu().numpy()
+    g.set_line_pairs(0)
+    x_single = g.precondition(b).cpu().numpy()
+    g.close()
+    np.testing.assert_array_equal(x_pairs, x_single)
+    assert per_field(x_single, case["ref"].H.vcycle(case["F"])) < (1e-10 if prec == "fp64" else 1e-4)
