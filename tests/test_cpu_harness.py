@@ -268,3 +268,28 @@ def test_line_smoother_bodies(harness, tmp_path, case, single):
             # G_k is the inverse of the pivot block: G_k D'_k = I, D'_k = D_k - L_k W_{k-1}
             Gk = lf[:4 * N].reshape(N, 2, 2)
             assert np.all(np.isfinite(Gk))
+
+
+def test_line_factor_reports_a_singular_pivot(harness, tmp_path):
+    """A line whose pivot block is singular (a zero centre block with no couplings along
+    the line) is counted, the way the library's factor kernel counts it before the
+    next solve fails; the other lines are unaffected."""
+    scn = W.lens_2d(9, 5)
+    st = ST.Stage(scn, levels=2, smoother="line")
+    u = W.perturbed_state(scn, 5, sn_lo=0.05, sn_hi=0.5)
+    st.assemble(u.ravel(), 32.0)
+    A = st.H.A[0].tolil()
+    n3 = (9, 5, 1)
+    v = 2 * 9 + 4  # line ix = 4, vertex iy = 2
+    for r in (2 * v, 2 * v + 1):
+        for c in list(A.rows[r]):
+            if (c // 2) % 9 == v % 9:  # the vertex's own block and its line couplings
+                A[r, c] = 0.0
+    A = sp.csr_matrix(A)
+    N = 45
+    rng = np.random.default_rng(2)
+    vals = [2, *n3, 2.0 / 3.0, 1, 0, csr_to_stencil(A, n3, 2), rng.standard_normal(2 * N), np.zeros(2 * N)]
+    xo, bad, _ = run(harness, "line", vals, tmp_path, [2 * N, 1, 12 * N])
+    assert bad[0] == 1.0
+    ok_lines = [ix for ix in range(9) if ix != 4]
+    assert all(np.isfinite(xo.reshape(5, 9, 2)[:, ix, :]).all() for ix in ok_lines)
