@@ -744,3 +744,22 @@ def test_stall_rule_by_hand():
     assert not r.after_step(False, 1.0, float("inf"))
     assert not r.after_step(True, 1.0, 1e-3)
     assert r.ref is None
+
+
+@pytest.mark.parametrize("k,row,limit", [(3, 3, 1.0 / 3.0), (3, 2, 0.5), (2, 2, 0.5)])
+def test_error_estimate_of_a_tableau_dominated_by_one_row(k, row, limit):
+    """When the substeps of one tableau row diverge, that row dominates the extrapolation
+    and eps tends to a ratio of the Aitken-Neville coefficients: for k = 3 a dominant
+    T_31 gives T_32 ~ 3 T_31 and T_33 ~ 4.5 T_31, so both parts of Eq. norm_u tend to
+    1.5 / 4.5 and eps to 1/3; a dominant T_21 gives T_kk - T_k,k-1 ~ T_kk / 2, eps 1/2."""
+    scn = W.lens_2d(9, 5)
+    f = FV.FV(scn)
+    nm = LX.Norms(f)
+    rng = np.random.default_rng(3)
+    u = W.perturbed_state(scn, 2, sn_lo=0.1, sn_hi=0.3).ravel()
+    w = rng.standard_normal(u.size)
+    for scale in (1e6, 1e9):
+        T1 = [u + 1e-3 * rng.standard_normal(u.size) for _ in range(k)]
+        T1[row - 1] = T1[row - 1] + scale * w
+        kk, km = LX.extrapolate(T1)
+        assert nm.err_ratio(kk, km) == pytest.approx(limit, rel=1e-5 if scale == 1e9 else 1e-2)
