@@ -366,7 +366,8 @@ tpf_status tpf_copy_matrix(tpf_grid *g, int32_t level, int32_t precision, void *
 /* y = A_level x with the FP64 level matrix; x, y device double[2 N_level]. */
 tpf_status tpf_spmv(tpf_grid *g, int32_t level, const double *x, double *y, tpf_stream stream);
 
-/* x = one V-cycle applied to b (the preconditioner of solve_stage). */
+/* x = one V-cycle applied to b (the preconditioner of solve_stage).  With
+ * TPF_SMOOTH_LINE, TPF_EBREAKDOWN if the line factorisation met a singular pivot. */
 tpf_status tpf_precondition(tpf_grid *g, const double *b, double *x, tpf_stream stream);
 
 /* Copies the inverse of the coarsest matrix (row-major, double[nc*nc],

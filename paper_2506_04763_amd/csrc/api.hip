@@ -636,7 +636,10 @@ tpf_status tpf_precondition(tpf_grid *g, const double *b, double *x, tpf_stream 
   g_err[0] = 0;
   if (!g || !b || !x || b == x) { set_error("bad argument"); return TPF_EINVAL; }
   if (!g->assembled) { set_error("no assembled matrix"); return TPF_ESTATE; }
-  return vcycle(g, b, x, reinterpret_cast<hipStream_t>(stream));
+  const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const tpf_status lc = check_line_factors(g, s);  // a singular line pivot: no V-cycle
+  if (lc != TPF_OK) return lc;
+  return vcycle(g, b, x, s);
 }
 
 tpf_status tpf_copy_coarse_inverse(tpf_grid *g, double *dst, tpf_stream stream) {
