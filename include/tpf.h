@@ -18,7 +18,8 @@
  *                     9-point (2D) stencil rows, plus the geometric-multigrid
  *                     hierarchy (Galerkin coarse operators) used as preconditioner;
  *   - solve_stage:    A x = f by BiCGSTAB preconditioned with one GMG V-cycle
- *                     (the linear solver named in Section 1 and Section 5);
+ *                     (the linear solver named in Section 1 and Section 5), point-
+ *                     or line-block Jacobi smoothing (tpf_grid_desc.smoother);
  *   - limex_step:     one adaptive LIMEX step (Section 4: linearly implicit
  *                     extrapolation, error estimate in the scaled norm Eq. norm_u,
  *                     step-size rule with q = 2);

@@ -1,7 +1,8 @@
 // Geometric multigrid on structured vertex grids (gfx950): stencil SpMV, damped 2x2
-// block-Jacobi smoothing, residual, restriction (P^T), prolongation, Galerkin coarse
-// operators A_c = P^T A P, dense coarsest-level LU with partial pivoting and its
-// inverse, and the V(nu1, nu2) cycle used as BiCGSTAB preconditioner.
+// point-block Jacobi or line-block Jacobi smoothing (the per-line bodies in line.h),
+// residual, restriction (P^T), prolongation, Galerkin coarse operators A_c = P^T A P,
+// dense coarsest-level LU with partial pivoting and its inverse, and the V(nu1, nu2)
+// cycle used as BiCGSTAB preconditioner.
 //
 // Matrices are 27-point (3D) / 9-point (2D) stencils of 2x2 blocks stored
 // [offset][vertex][4]: for a fixed offset, consecutive lanes read consecutive 16-byte
