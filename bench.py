@@ -48,12 +48,17 @@ NST = 27
 
 
 # Multigrid settings of every grid the benchmark builds: line-block Jacobi along the
-# last axis, V(1, 1), omega = 2/3 (measured on the 129^3 stage, the 257^3 case-5 layers,
-# case 4 at 4096 x 2048 and stage systems captured from case-4 runs where point
-# smoothing failed).  --smoother point restores V(2, 2) point-block Jacobi.
+# last axis, V(1, 1).  Damping per workload family: omega = 2/3 on the layered
+# workloads (cases 4 and 5, the 257^3 layered cube, Table case4_2) and case 1, where
+# stage systems captured from case-4 runs converge in 10-34 iterations against 22-37
+# at 0.9 and fail at 1.0; omega = 0.9 on the log-normal cubes (the 129^3 stage and the
+# serving requests): 62 iterations over six 129^3 cubes (sigma 1-2) against 67 at 2/3.
+# --smoother point restores V(2, 2) point-block Jacobi with omega = 2/3 everywhere.
 SOLVERS = {"line": {"smoother": "line", "nu_pre": 1, "nu_post": 1, "omega": 2.0 / 3.0},
            "point": {"smoother": "point", "nu_pre": 2, "nu_post": 2, "omega": 2.0 / 3.0}}
-SOLVER = dict(SOLVERS["line"])
+CUBE_OMEGA = {"line": 0.9, "point": 2.0 / 3.0}
+SOLVER = dict(SOLVERS["line"])              # layered workloads and case 1
+SOLVER_CUBE = dict(SOLVER, omega=CUBE_OMEGA["line"])  # log-normal cubes
 
 
 def solver_label(sv=None):
@@ -167,7 +172,7 @@ def run(args):
     results = {}
     hot = ("smooth0", "resid0", "spmv64", "assemble", "line0")  # level-0 kernels
     for prec in (["mixed"] if args.no_fp64 else ["mixed", "fp64", "mixed16"]):
-        g = tpf.Grid(scn, precision=prec, levels=6, **SOLVER)
+        g = tpf.Grid(scn, precision=prec, levels=6, **SOLVER_CUBE)
         u0 = g.initial_state()
         f = g.empty()
         x = g.empty()
@@ -261,7 +266,7 @@ def run(args):
         "data": "synthetic",
         "config": {"workload": "cube129_lognormal_sigma2_seed3_mixed", "vertices": [129, 129, 129], "dof": 2 * N,
                    "levels": len(lv), "precision": "FP32 multigrid in FP64 BiCGSTAB", "rtol": rtol, "h_s": h,
-                   "smoother": solver_label(),
+                   "smoother": solver_label(SOLVER_CUBE),
                    "coarse_levels": (mixed["graph"] or {}).get("timed_with", "stream")},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -289,10 +294,10 @@ def run(args):
     if not args.no_serve:
         from paper_2506_04763_amd import serve as SV
         prepared = SV.prepare_requests(args.serve_requests)
-        sv = SV.run_benchmark(count=args.serve_requests, quiet=True, prepared=prepared, solver=SOLVER)
+        sv = SV.run_benchmark(count=args.serve_requests, quiet=True, prepared=prepared, solver=SOLVER_CUBE)
         # the same requests replayed faster: where throughput stops following the rate
         sv["capacity"] = SV.capacity_sweep(rates=(80.0, 160.0, 320.0), count=args.serve_requests,
-                                           prepared=prepared, solver=SOLVER)
+                                           prepared=prepared, solver=SOLVER_CUBE)
         line["serving"] = sv
         line["p50_ms"], line["p99_ms"] = sv["p50_ms"], sv["p99_ms"]
     if not args.no_cases:
@@ -584,7 +589,7 @@ def counters_driver(cycles=4, copy_bytes=1 << 30):
     import paper_2506_04763_amd as tpf
     import workloads as W
     scn = W.cube_c3()
-    g = tpf.Grid(scn, precision="mixed", levels=6, **SOLVER)
+    g = tpf.Grid(scn, precision="mixed", levels=6, **SOLVER_CUBE)
     u0 = g.initial_state()
     f = g.empty()
     g.assemble_stage(u0, 32.0, f0_out=f)
@@ -721,6 +726,8 @@ def main():
     args = ap.parse_args()
     SOLVER.clear()
     SOLVER.update(SOLVERS[args.smoother])
+    SOLVER_CUBE.clear()
+    SOLVER_CUBE.update(SOLVERS[args.smoother], omega=CUBE_OMEGA[args.smoother])
     if args.summarise_trace:
         print(summarise_trace(args.summarise_trace, args.steps))
         return

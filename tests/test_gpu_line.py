@@ -159,3 +159,28 @@ def test_one_thread_and_two_threads_per_line_agree(case, prec):
     g.close()
     np.testing.assert_array_equal(x_pairs, x_single)
     assert per_field(x_single, case["ref"].H.vcycle(case["F"])) < (1e-10 if prec == "fp64" else 1e-4)
+
+
+@pytest.mark.parametrize("name,mk,levels", [("cube9", lambda: W.small_cube(9, seed=22), 3),
+                                            ("cube17", lambda: W.small_cube(17, sigma=2.0, seed=23), 3)])
+def test_line_smoother_at_the_cube_damping(name, mk, levels):
+    """The damping the log-normal cube workloads use (omega = 0.9): one FP64 V(1,1)
+    cycle against the oracle's, and a mixed solve against the oracle's tight solution."""
+    scn = mk()
+    scn.levels = levels
+    u = W.perturbed_state(scn, 5, sn_lo=0.02, sn_hi=0.6)
+    ref = ST.Stage(scn, smoother="line", omega=0.9, nu1=1, nu2=1)
+    ref.assemble(u.ravel(), 32.0)
+    F = ref.residual(u.ravel())
+    for prec in ("fp64", "mixed"):
+        g = tpf.Grid(scn, precision=prec, smoother="line", nu_pre=1, nu_post=1, omega=0.9)
+        g.assemble_stage(torch.as_tensor(u.ravel(), device="cuda"), 32.0)
+        if prec == "fp64":
+            x = g.precondition(torch.as_tensor(F, device="cuda")).cpu().numpy()
+            assert per_field(x, ref.H.vcycle(F)) < 1e-10
+        x, st = g.solve_stage(torch.as_tensor(F, device="cuda"), rtol=1e-8, maxit=400)
+        x_tight, _ = ref.solve(F, rtol=1e-13, maxit=400)
+        err = per_field(x.cpu().numpy(), x_tight)
+        print(name, prec, "omega 0.9", st, "err vs oracle", err, flush=True)
+        assert st["status"] == "TPF_OK" and st["rel_res_true"] <= 1e-8 and err < 1e-5
+        g.close()
