@@ -435,6 +435,10 @@ void tpf_destroy_grid(tpf_grid *g) {
   if (g->vgraph_exec) (void)hipGraphExecDestroy(g->vgraph_exec);
   if (g->vgraph) (void)hipGraphDestroy(g->vgraph);
   if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
+  if (g->lu_pending) (void)hipEventSynchronize(g->lu_done);  // the arena is freed after this call
+  if (g->lu_stream) (void)hipStreamDestroy(g->lu_stream);
+  if (g->lu_fork) (void)hipEventDestroy(g->lu_fork);
+  if (g->lu_done) (void)hipEventDestroy(g->lu_done);
   if (g->scal_ev) (void)hipEventDestroy(g->scal_ev);
   if (g->hscal) (void)hipHostFree(g->hscal);
   delete g;
@@ -646,6 +650,8 @@ tpf_status tpf_copy_coarse_inverse(tpf_grid *g, double *dst, tpf_stream stream) 
   g_err[0] = 0;
   if (!g || !dst) { set_error("bad argument"); return TPF_EINVAL; }
   if (!g->assembled) { set_error("no assembled matrix"); return TPF_ESTATE; }
+  const tpf_status lj = lu_join(g, reinterpret_cast<hipStream_t>(stream));
+  if (lj != TPF_OK) return lj;
   TPF_HIP(hipMemcpyAsync(dst, g->ainv, (size_t)g->nc * g->nc * sizeof(double), hipMemcpyDeviceToDevice,
                          reinterpret_cast<hipStream_t>(stream)));
   return TPF_OK;

@@ -711,6 +711,10 @@ tpf_status launch_residual(tpf_grid *g, const double *u, double *f, hipStream_t 
 }
 
 tpf_status launch_assemble(tpf_grid *g, const double *u0, double h, double *f0, hipStream_t s) {
+  {  // (one level: the finest matrix is the one a pending coarsest factorisation reads)
+    const tpf_status st = lu_join(g, s);
+    if (st != TPF_OK) return st;
+  }
   const unsigned nb = blocks_for(g->P.N);
   g->h_stage = h;
   k_vertex_pc<<<nb, BS, 0, s>>>(g->P, u0, g->pdmin, g->lamref, g->pv);

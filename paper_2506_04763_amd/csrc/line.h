@@ -102,49 +102,75 @@ __host__ __device__ __forceinline__ void line_blocks(const Geo &G, const double 
   }
 }
 
-// Twisted factorisation of line l from the level's FP64 matrix A ([offset][vertex][4])
-// into lf.  Returns false if a pivot block is singular or not finite.
-template <int DIM, typename TO>
-__host__ __device__ inline bool line_factor(const Geo &G, const double *__restrict__ A, TO *__restrict__ lf,
-                                            long long l) {
+// One half of the twisted factorisation of line l from the level's FP64 matrix A
+// ([offset][vertex][4]) into lf: top (k = 0 .. m-1) or bottom (k = n-1 .. m+1).  Returns in
+// cpl the coupling block the middle row needs (W_{m-1} of the top, V_{m+1} of the
+// bottom; zero for an empty half), and false if a pivot block is singular or not finite.
+// Steps are taken in chunks of CH whose loads are all issued before the chunk's
+// recurrence (a chunk past the end of the half re-reads its last vertex).
+template <int DIM, typename TO, int CH>
+__host__ __device__ inline bool line_factor_half(const Geo &G, const double *__restrict__ A, TO *__restrict__ lf,
+                                                 long long l, bool top, double (&cpl)[4]) {
   const LineGeo lg = line_geo<DIM>(G);
   const long long N = G.N;
   const int m = lg.n / 2;
+  const int len = top ? m : lg.n - 1 - m;
+  const int k0 = top ? 0 : lg.n - 1, dk = top ? 1 : -1;
   bool ok = true;
-  double d[4], lo[4], up[4], t[4], vv[4], ww[4];
-  double wtop[4] = {0.0, 0.0, 0.0, 0.0};  // W_{k-1} of the top half (FP64)
-  for (int k = 0; k < m; ++k) {
-    const long long v = l + (long long)k * lg.S;
-    line_blocks<DIM>(G, A, v, d, lo, up);
-    mul22(lo, wtop, t);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) d[i] -= t[i];
-    ok = line_store<DIM, TO>(d, lo, up, lf, N, v, vv, ww) && ok;
+  for (int i = 0; i < 4; ++i) cpl[i] = 0.0;
+  for (int j0 = 0; j0 < len; j0 += CH) {
+    double d[CH][4], lo[CH][4], up[CH][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) wtop[i] = ww[i];
-  }
-  double vbot[4] = {0.0, 0.0, 0.0, 0.0};  // V_{k+1} of the bottom half (FP64)
-  for (int k = lg.n - 1; k > m; --k) {
-    const long long v = l + (long long)k * lg.S;
-    line_blocks<DIM>(G, A, v, d, lo, up);
-    mul22(up, vbot, t);
+    for (int j = 0; j < CH; ++j) {
+      const int jj = j0 + j < len ? j0 + j : len - 1;
+      line_blocks<DIM>(G, A, l + (long long)(k0 + dk * jj) * lg.S, d[j], lo[j], up[j]);
+    }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) d[i] -= t[i];
-    ok = line_store<DIM, TO>(d, lo, up, lf, N, v, vv, ww) && ok;
+    for (int j = 0; j < CH; ++j) {
+      if (j0 + j < len) {
+        const long long v = l + (long long)(k0 + dk * (j0 + j)) * lg.S;
+        double t[4], vv[4], ww[4];
+        if (top)
+          mul22(lo[j], cpl, t);  // L_k W_{k-1}
+        else
+          mul22(up[j], cpl, t);  // U_k V_{k+1}
 #pragma unroll
-    for (int i = 0; i < 4; ++i) vbot[i] = vv[i];
-  }
-  {  // the middle vertex, eliminated from both sides
-    const long long v = l + (long long)m * lg.S;
-    line_blocks<DIM>(G, A, v, d, lo, up);
-    double t2[4];
-    mul22(lo, wtop, t);
-    mul22(up, vbot, t2);
+        for (int i = 0; i < 4; ++i) d[j][i] -= t[i];
+        ok = line_store<DIM, TO>(d[j], lo[j], up[j], lf, N, v, vv, ww) && ok;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) d[i] -= t[i] + t2[i];
-    ok = line_store<DIM, TO>(d, lo, up, lf, N, v, vv, ww) && ok;
+        for (int i = 0; i < 4; ++i) cpl[i] = top ? ww[i] : vv[i];
+      }
+    }
   }
   return ok;
+}
+
+// The middle vertex of line l, eliminated from both sides with W_{m-1} (wtop) and
+// V_{m+1} (vbot).
+template <int DIM, typename TO>
+__host__ __device__ inline bool line_factor_middle(const Geo &G, const double *__restrict__ A, TO *__restrict__ lf,
+                                                   long long l, const double (&wtop)[4], const double (&vbot)[4]) {
+  const LineGeo lg = line_geo<DIM>(G);
+  const long long v = l + (long long)(lg.n / 2) * lg.S;
+  double d[4], lo[4], up[4], t[4], t2[4], vv[4], ww[4];
+  line_blocks<DIM>(G, A, v, d, lo, up);
+  mul22(lo, wtop, t);
+  mul22(up, vbot, t2);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) d[i] -= t[i] + t2[i];
+  return line_store<DIM, TO>(d, lo, up, lf, G.N, v, vv, ww);
+}
+
+// Twisted factorisation of line l by one thread (both halves in turn, then the middle).
+// Returns false if a pivot block is singular or not finite.
+template <int DIM, typename TO, int CH = 4>
+__host__ __device__ inline bool line_factor(const Geo &G, const double *__restrict__ A, TO *__restrict__ lf,
+                                            long long l) {
+  double wtop[4], vbot[4];
+  const bool ok_top = line_factor_half<DIM, TO, CH>(G, A, lf, l, true, wtop);
+  const bool ok_bot = line_factor_half<DIM, TO, CH>(G, A, lf, l, false, vbot);
+  return line_factor_middle<DIM, TO>(G, A, lf, l, wtop, vbot) && ok_top && ok_bot;
 }
 
 // Forward chain of one half of line l: top (k = 0 .. m-1, coupling block V) or bottom

@@ -12,6 +12,7 @@
 // linear interpolation of the pressure, piecewise-constant aggregation of the
 // saturation; on the finest level its rows at Dirichlet components are zero.
 #include <type_traits>
+#include <utility>
 
 #include "line.h"
 #include "stencil.h"
@@ -646,76 +647,96 @@ __global__ void __launch_bounds__(1024) k_lu_panel(double *__restrict__ a, int n
   }
 }
 
-// The same panel factorisation with the panel held in LDS (rows j0..n-1 of its w
-// columns, column by column), for panels of at most LU_LDS_ROWS rows.
-constexpr int LU_LDS_ROWS = 256;  // 256 x 32 doubles = 64 KB
+// One column step of k_lu_panel_reg, column C of the panel held in x (row r).
+template <int ROWS, int C>
+__device__ __forceinline__ void lu_panel_column(double (&x)[LU_NB], int r, int m, int j0, int w,
+                                                int *__restrict__ piv, double (*prow)[LU_NB],
+                                                double (*crow)[LU_NB], double (*wbest)[ROWS / 64],
+                                                int (*wrow)[ROWS / 64]) {
+  constexpr int NW = ROWS / 64, q = C & 1;
+  if (C >= w) return;
+  const int lane = r & 63, wv = r >> 6;
+  const bool in = r < m;
+  double best = -1.0;
+  int bi = C;  // a column without a comparable entry (NaN) keeps its own row
+  if (in && r >= C) {
+    best = fabs(x[C]);
+    bi = r;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ob = __shfl_down(best, off, 64);
+    const int oi = __shfl_down(bi, off, 64);
+    if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+  }
+  if (lane == 0) {
+    wbest[q][wv] = best;
+    wrow[q][wv] = bi;
+  }
+  __syncthreads();
+  best = wbest[q][0];
+  bi = wrow[q][0];
+#pragma unroll
+  for (int k = 1; k < NW; ++k)
+    if (wbest[q][k] > best || (wbest[q][k] == best && wrow[q][k] < bi)) { best = wbest[q][k]; bi = wrow[q][k]; }
+  const int p = bi;
+  if (r == p) {
+#pragma unroll
+    for (int cc = 0; cc < LU_NB; ++cc) prow[q][cc] = x[cc];
+  }
+  if (r == C) {
+#pragma unroll
+    for (int cc = 0; cc < LU_NB; ++cc) crow[q][cc] = x[cc];
+  }
+  __syncthreads();
+  if (r == 0) piv[j0 + C] = j0 + p;
+  if (p != C && r == C) {
+#pragma unroll
+    for (int cc = 0; cc < LU_NB; ++cc) x[cc] = prow[q][cc];
+  } else if (p != C && r == p) {
+#pragma unroll
+    for (int cc = 0; cc < LU_NB; ++cc) x[cc] = crow[q][cc];
+  }
+  const double inv = 1.0 / prow[q][C];
+  if (in && r > C) {
+    const double l = x[C] * inv;
+#pragma unroll
+    for (int cc = C + 1; cc < LU_NB; ++cc) x[cc] -= l * prow[q][cc];
+    x[C] = l;
+  }
+}
 
-__global__ void __launch_bounds__(1024) k_lu_panel_lds(double *__restrict__ a, int n, int j0, int w,
+template <int ROWS, int... C>
+__device__ __forceinline__ void lu_panel_columns(std::integer_sequence<int, C...>, double (&x)[LU_NB], int r,
+                                                 int m, int j0, int w, int *__restrict__ piv,
+                                                 double (*prow)[LU_NB], double (*crow)[LU_NB],
+                                                 double (*wbest)[ROWS / 64], int (*wrow)[ROWS / 64]) {
+  (lu_panel_column<ROWS, C>(x, r, m, j0, w, piv, prow, crow, wbest, wrow), ...);
+}
+
+// The same panel factorisation for panels of at most ROWS rows (256 or 1024), with each
+// row's LU_NB entries in the registers of one thread (one column step per compile-time
+// column index, so the row needs no LDS or scratch).  A column step is a pivot search
+// (wavefront shuffles, then the wavefront maxima through LDS), the row interchange
+// through LDS, and the rank-1 update of every thread's own row with the pivot row read
+// from LDS: two barriers per column.  The LDS
+// buffers alternate between columns, so a column's writes never meet the previous
+// column's reads.  The arithmetic is that of the other panel kernels, entry for entry.
+template <int ROWS>
+__global__ void __launch_bounds__(ROWS) k_lu_panel_reg(double *__restrict__ a, int n, int j0, int w,
                                                        int *__restrict__ piv) {
-  __shared__ double P[LU_NB * LU_LDS_ROWS];
-  __shared__ double wbest[16];
-  __shared__ int wrow[16];
-  __shared__ int sp;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int m = n - j0;  // rows of the panel, <= LU_LDS_ROWS
-  const int row = tid & (LU_LDS_ROWS - 1), grp = tid / LU_LDS_ROWS;  // 4 groups of 256 rows
-  for (int t = tid; t < m * w; t += 1024) {
-    const int c = t / m, r = t % m;
-    P[c * m + r] = a[(long long)(j0 + c) * n + j0 + r];
-  }
-  __syncthreads();
-  for (int c = 0; c < w; ++c) {
-    double *colk = P + c * m;
-    double best = -1.0;
-    int bi = c;
-    if (tid >= c && tid < m) {  // m <= 256 < 1024: one row per thread
-      best = fabs(colk[tid]);
-      bi = tid;
-    }
+  __shared__ double prow[2][LU_NB], crow[2][LU_NB], wbest[2][ROWS / 64];
+  __shared__ int wrow[2][ROWS / 64];
+  const int r = threadIdx.x;
+  const int m = n - j0;  // rows of the panel, <= ROWS
+  const bool in = r < m;
+  double x[LU_NB];
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const double ob = __shfl_down(best, off, 64);
-      const int oi = __shfl_down(bi, off, 64);
-      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-    }
-    if (lane == 0) { wbest[wv] = best; wrow[wv] = bi; }
-    __syncthreads();
-    if (wv == 0) {  // 16 partial maxima reduced by the first wavefront
-      best = lane < 16 ? wbest[lane] : -1.0;
-      bi = lane < 16 ? wrow[lane] : c;
+  for (int c = 0; c < LU_NB; ++c) x[c] = (in && c < w) ? a[(long long)(j0 + c) * n + j0 + r] : 0.0;
+  lu_panel_columns<ROWS>(std::make_integer_sequence<int, LU_NB>{}, x, r, m, j0, w, piv, prow, crow, wbest, wrow);
 #pragma unroll
-      for (int off = 8; off > 0; off >>= 1) {
-        const double ob = __shfl_down(best, off, 64);
-        const int oi = __shfl_down(bi, off, 64);
-        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-      }
-      if (lane == 0) {
-        sp = bi;
-        piv[j0 + c] = j0 + bi;
-      }
-    }
-    __syncthreads();
-    const int p = sp;
-    if (p != c && tid < w) {
-      const double t = P[tid * m + c];
-      P[tid * m + c] = P[tid * m + p];
-      P[tid * m + p] = t;
-    }
-    __syncthreads();
-    // rank-1 update of the panel's remaining columns: row `row`, columns c+1+grp, +4, ...
-    const double inv = 1.0 / colk[c];
-    if (row > c && row < m) {
-      const double l = colk[row] * inv;
-      for (int cc = c + 1 + grp; cc < w; cc += 4) P[cc * m + row] -= l * P[cc * m + c];
-    }
-    __syncthreads();
-    if (grp == 0 && row > c && row < m) colk[row] *= inv;  // multipliers (read again only after barriers)
-  }
-  __syncthreads();
-  for (int t = tid; t < m * w; t += 1024) {
-    const int c = t / m, r = t % m;
-    a[(long long)(j0 + c) * n + j0 + r] = P[c * m + r];
-  }
+  for (int c = 0; c < LU_NB; ++c)
+    if (in && c < w) a[(long long)(j0 + c) * n + j0 + r] = x[c];
 }
 
 // Row interchanges of panel j0..j0+w-1 applied, in order, to every column outside it.
@@ -1011,13 +1032,38 @@ constexpr int LINES_PER_BLOCK = 32;
 #ifndef TPF_LINE_CHUNK
 #define TPF_LINE_CHUNK 16
 #endif
+#ifndef TPF_LINE_FACTOR_CHUNK
+#define TPF_LINE_FACTOR_CHUNK 4
+#endif
 
 template <int DIM, typename TO>
 __global__ void __launch_bounds__(LINE_BS) k_line_factor(const Geo G, const double *__restrict__ A,
                                                          TO *__restrict__ lf, int *__restrict__ bad) {
   const long long l = (long long)blockIdx.x * LINE_BS + threadIdx.x;
   if (l >= line_geo<DIM>(G).S) return;
-  if (!line_factor<DIM, TO>(G, A, lf, l)) atomicAdd(bad, 1);
+  if (!line_factor<DIM, TO, TPF_LINE_FACTOR_CHUNK>(G, A, lf, l)) atomicAdd(bad, 1);
+}
+
+// The same factorisation with the two halves of a line on lanes l and l + 32 of one
+// wavefront (the layout of k_line), which exchange W_{m-1} and V_{m+1} for the middle
+// row; the top lane stores the middle and counts the line if any of its pivots is bad.
+template <int DIM, typename TO>
+__global__ void __launch_bounds__(LINE_BS) k_line_factor2(const Geo G, const double *__restrict__ A,
+                                                          TO *__restrict__ lf, int *__restrict__ bad) {
+  const int lane = threadIdx.x;  // the block is one wavefront
+  const bool top = lane < LINES_PER_BLOCK;
+  const long long l = (long long)blockIdx.x * LINES_PER_BLOCK + (top ? lane : lane - LINES_PER_BLOCK);
+  const bool valid = l < line_geo<DIM>(G).S;
+  double cpl[4] = {0.0, 0.0, 0.0, 0.0};
+  bool ok = true;
+  if (valid) ok = line_factor_half<DIM, TO, TPF_LINE_FACTOR_CHUNK>(G, A, lf, l, top, cpl);
+  double other[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) other[i] = __shfl_xor(cpl[i], LINES_PER_BLOCK, 64);
+  const bool ok_other = __shfl_xor((int)ok, LINES_PER_BLOCK, 64) != 0;
+  if (!valid || !top) return;
+  ok = line_factor_middle<DIM, TO>(G, A, lf, l, cpl, other) && ok && ok_other;
+  if (!ok) atomicAdd(bad, 1);
 }
 
 // Levels with at least g->line_pair_max lines (default TPF_LINE_PAIR_MAX_LINES) have
@@ -1060,13 +1106,22 @@ tpf_status line_factors_t(tpf_grid *g, hipStream_t s) {
   TPF_LAUNCH_CHECK();
   for (int l = 0; l + 1 < g->L; ++l) {
     const Level &lv = g->lv[l];
-    const unsigned nb = blocks_for(line_geo<DIM>(geo(lv)).S, LINE_BS);
-    if (g->prec == TPF_FP64)
-      k_line_factor<DIM, double><<<nb, LINE_BS, 0, s>>>(geo(lv), lv.A64, reinterpret_cast<double *>(lv.lf),
-                                                        g->line_bad);
-    else
-      k_line_factor<DIM, float><<<nb, LINE_BS, 0, s>>>(geo(lv), lv.A64, reinterpret_cast<float *>(lv.lf),
-                                                       g->line_bad);
+    const long long nl = line_geo<DIM>(geo(lv)).S;
+    const bool pairs = nl < g->line_pair_max;
+    const unsigned nb = pairs ? blocks_for(nl, LINES_PER_BLOCK) : blocks_for(nl, LINE_BS);
+    if (g->prec == TPF_FP64) {
+      double *lf = reinterpret_cast<double *>(lv.lf);
+      if (pairs)
+        k_line_factor2<DIM, double><<<nb, LINE_BS, 0, s>>>(geo(lv), lv.A64, lf, g->line_bad);
+      else
+        k_line_factor<DIM, double><<<nb, LINE_BS, 0, s>>>(geo(lv), lv.A64, lf, g->line_bad);
+    } else {
+      float *lf = reinterpret_cast<float *>(lv.lf);
+      if (pairs)
+        k_line_factor2<DIM, float><<<nb, LINE_BS, 0, s>>>(geo(lv), lv.A64, lf, g->line_bad);
+      else
+        k_line_factor<DIM, float><<<nb, LINE_BS, 0, s>>>(geo(lv), lv.A64, lf, g->line_bad);
+    }
     TPF_LAUNCH_CHECK();
   }
   g->line_unchecked = true;
@@ -1130,6 +1185,10 @@ tpf_status vcycle_t(tpf_grid *g, const double *bin, double *xout, hipStream_t s,
   const T *const noT = nullptr;
   const uint8_t *const nomask = nullptr;
   if (L == 1) {  // single level: the dense solve is the whole cycle
+    {
+      const tpf_status st = lu_join(g, s);
+      if (st != TPF_OK) return st;
+    }
     Level &lc = g->lv[0];
     T *X = sizeof(T) == sizeof(double) ? reinterpret_cast<T *>(xout) : reinterpret_cast<T *>(lc.x);
     TPF_HIP(launch(g, TPF_K_COARSE_LEVELS, k_coarse_solve<T>, (unsigned)((g->nc + 3) / 4), 256u, s,
@@ -1246,7 +1305,12 @@ tpf_status vcycle_t(tpf_grid *g, const double *bin, double *xout, hipStream_t s,
     return TPF_OK;
   };
   // coarsest level: x = A^{-1} b, one wavefront per row of the inverse
+  bool capturing = false;  // the tail is being recorded into the grid's graph
   auto coarsest = [&](hipStream_t s) -> tpf_status {
+    if (!capturing) {  // (a captured tail is launched after a wait of its own)
+      const tpf_status st = lu_join(g, s);
+      if (st != TPF_OK) return st;
+    }
     Level &lc = g->lv[L - 1];
     T *X = reinterpret_cast<T *>(lc.x);
     TPF_HIP(launch(g, TPF_K_COARSE_LEVELS, k_coarse_solve<T>, (unsigned)((g->nc + 3) / 4), 256u, s,
@@ -1333,7 +1397,9 @@ tpf_status vcycle_t(tpf_grid *g, const double *bin, double *xout, hipStream_t s,
     if (!g->vgraph_exec) {
       if (!g->cap_stream) TPF_HIP(hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking));
       TPF_HIP(hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal));
+      capturing = true;
       const tpf_status cst = tail(g->cap_stream);
+      capturing = false;
       hipGraph_t graph = nullptr;
       const hipError_t e = hipStreamEndCapture(g->cap_stream, &graph);
       if (cst != TPF_OK || e != hipSuccess) {
@@ -1351,6 +1417,8 @@ tpf_status vcycle_t(tpf_grid *g, const double *bin, double *xout, hipStream_t s,
       g->vgraph_cur1 = cur[1];
     }
     cur[1] = reinterpret_cast<T *>(g->vgraph_cur1);
+    st = lu_join(g, s);
+    if (st != TPF_OK) return st;
     TPF_HIP(hipGraphLaunch(g->vgraph_exec, s));
   } else {
     st = tail(s);
@@ -1364,6 +1432,10 @@ tpf_status coarse_factor_t(tpf_grid *g, hipStream_t s);
 
 template <int DIM>
 tpf_status hierarchy_t(tpf_grid *g, hipStream_t s) {
+  {  // the Galerkin products overwrite the matrix a pending factorisation reads
+    const tpf_status st = lu_join(g, s);
+    if (st != TPF_OK) return st;
+  }
   for (int l = 0; l + 1 < g->L; ++l) {
     const Level &f = g->lv[l];
     Level &c = g->lv[l + 1];
@@ -1378,18 +1450,43 @@ tpf_status hierarchy_t(tpf_grid *g, hipStream_t s) {
     }
     prof_end(g, ps, s);
   }
+  {  // the coarsest factorisation, forked to the grid's own stream
+    const tpf_status st = coarse_factor_t<DIM>(g, s);
+    if (st != TPF_OK) return st;
+  }
   if (g->smoother == TPF_SMOOTH_LINE) {  // the line LU, timed with the Galerkin products
     const int ps = prof_begin(g, TPF_K_RAP, s);
     const tpf_status st = line_factors_t<DIM>(g, s);
     if (st != TPF_OK) return st;
     prof_end(g, ps, s);
   }
-  return coarse_factor_t<DIM>(g, s);
+  return TPF_OK;
 }
 
-// Dense LU with partial pivoting of the coarsest level and its inverse.
+// Dense LU with partial pivoting of the coarsest level and its inverse.  Its kernels
+// occupy one or a few workgroups at a time, so outside stream capture they run on the
+// grid's own stream, forked from s: the line LU, the solver's set-up and the first
+// V-cycle's descent, queued on s meanwhile, fill the rest of the device, and s waits
+// for the factors only where it first needs them (lu_join).
 template <int DIM>
-tpf_status coarse_factor_t(tpf_grid *g, hipStream_t s) {
+tpf_status coarse_factor_t(tpf_grid *g, hipStream_t s0) {
+  {
+    const tpf_status st = lu_join(g, s0);
+    if (st != TPF_OK) return st;
+  }
+  hipStream_t s = s0;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  TPF_HIP(hipStreamIsCapturing(s0, &cs));
+  if (cs == hipStreamCaptureStatusNone) {
+    if (!g->lu_stream) {
+      TPF_HIP(hipStreamCreateWithFlags(&g->lu_stream, hipStreamNonBlocking));
+      TPF_HIP(hipEventCreateWithFlags(&g->lu_fork, hipEventDisableTiming));
+      TPF_HIP(hipEventCreateWithFlags(&g->lu_done, hipEventDisableTiming));
+    }
+    TPF_HIP(hipEventRecord(g->lu_fork, s0));
+    TPF_HIP(hipStreamWaitEvent(g->lu_stream, g->lu_fork, 0));
+    s = g->lu_stream;
+  }
   Level &lc = g->lv[g->L - 1];
   const int n = g->nc;
   const int pl = prof_begin(g, TPF_K_COARSE_LU, s);
@@ -1400,8 +1497,10 @@ tpf_status coarse_factor_t(tpf_grid *g, hipStream_t s) {
   TPF_LAUNCH_CHECK();
   for (int j0 = 0; j0 < n; j0 += LU_NB) {
     const int w = n - j0 < LU_NB ? n - j0 : LU_NB;
-    if (n - j0 <= LU_LDS_ROWS)
-      k_lu_panel_lds<<<1, 1024, 0, s>>>(g->lu, n, j0, w, g->piv);
+    if (n - j0 <= 256)
+      k_lu_panel_reg<256><<<1, 256, 0, s>>>(g->lu, n, j0, w, g->piv);
+    else if (n - j0 <= 1024)
+      k_lu_panel_reg<1024><<<1, 1024, 0, s>>>(g->lu, n, j0, w, g->piv);
     else
       k_lu_panel<<<1, 1024, 0, s>>>(g->lu, n, j0, w, g->piv);
     TPF_LAUNCH_CHECK();
@@ -1427,6 +1526,10 @@ tpf_status coarse_factor_t(tpf_grid *g, hipStream_t s) {
     TPF_LAUNCH_CHECK();
   }
   prof_end(g, pl, s);
+  if (s != s0) {
+    TPF_HIP(hipEventRecord(g->lu_done, s));
+    g->lu_pending = true;
+  }
   return TPF_OK;
 }
 
@@ -1442,6 +1545,10 @@ tpf_status spmv_t(tpf_grid *g, int level, const double *x, double *y, hipStream_
 // ratio), the FP32 / FP16 copies refreshed, the coarsest level refactored.
 template <int DIM>
 tpf_status rescale_t(tpf_grid *g, double ratio, hipStream_t s) {
+  {  // the rescaling overwrites the matrix a pending factorisation reads
+    const tpf_status st = lu_join(g, s);
+    if (st != TPF_OK) return st;
+  }
   const int ps = prof_begin(g, TPF_K_ASSEMBLE, s);
   for (int l = 0; l < g->L; ++l) {
     Level &lv = g->lv[l];
@@ -1453,12 +1560,15 @@ tpf_status rescale_t(tpf_grid *g, double ratio, hipStream_t s) {
       TPF_LAUNCH_CHECK();
     }
   }
+  prof_end(g, ps, s);
   {
-    const tpf_status st = line_factors_t<DIM>(g, s);
+    const tpf_status st = coarse_factor_t<DIM>(g, s);
     if (st != TPF_OK) return st;
   }
-  prof_end(g, ps, s);
-  return coarse_factor_t<DIM>(g, s);
+  const int pl = prof_begin(g, TPF_K_ASSEMBLE, s);
+  const tpf_status st = line_factors_t<DIM>(g, s);
+  prof_end(g, pl, s);
+  return st;
 }
 
 }  // namespace

@@ -112,6 +112,11 @@ struct tpf_grid {
   hipGraph_t vgraph;
   hipGraphExec_t vgraph_exec;
   void *vgraph_cur1;          // level-1 correction the tail leaves (fixed per grid)
+  // the coarsest factorisation runs on the grid's own stream, forked from the caller's
+  // stream after the Galerkin products; lu_pending until a stream has waited for it
+  hipStream_t lu_stream = nullptr;  // default priority
+  hipEvent_t lu_fork = nullptr, lu_done = nullptr;
+  bool lu_pending = false;
   size_t bytes;
   int device;
   tpf::Prof prof;
@@ -164,6 +169,18 @@ void set_error(const char *fmt, ...);
   } while (0)
 
 #define TPF_LAUNCH_CHECK() TPF_HIP(hipGetLastError())
+
+// Orders stream s after the pending coarsest factorisation, if there is one: called
+// before anything on s reads the coarse factors, or writes a matrix the factorisation
+// reads.  Once one stream has waited, the work it queues after the wait is ordered
+// after the factorisation (a grid is used from one stream at a time).
+inline tpf_status lu_join(tpf_grid *g, hipStream_t s) {
+  if (g->lu_pending) {
+    TPF_HIP(hipStreamWaitEvent(s, g->lu_done, 0));
+    g->lu_pending = false;
+  }
+  return TPF_OK;
+}
 
 inline unsigned blocks_for(long long n, int bs = BS) { return (unsigned)((n + bs - 1) / bs); }
 

@@ -225,6 +225,7 @@ def test_galerkin_product_coverage_and_values(harness, tmp_path, case):
 
 
 LINE_CASES = [
+    ("lens9x5", lambda: W.lens_2d(9, 5), 3, 50.0),  # level 1: lines of 3 vertices
     ("lens17x9", lambda: W.lens_2d(17, 9), 3, 50.0),
     ("cube9", lambda: W.small_cube(9, seed=22), 3, 50.0),
     ("case4_64x32", lambda: W.case4(64), 3, 2e4),

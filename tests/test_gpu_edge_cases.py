@@ -145,3 +145,38 @@ def test_dense_inverse_of_hundreds_of_unknowns(name, make):
     u = W.perturbed_state(scn, 9, sn_lo=0.05, sn_hi=0.5)
     st = parity(scn, u, 32.0)
     assert st["status"] == "TPF_OK" and st["iters"] <= 2
+
+
+@pytest.mark.parametrize("side_stream", [False, True], ids=["current_stream", "own_stream"])
+def test_coarsest_factorisation_is_awaited_before_use(side_stream):
+    """The coarsest LU runs on the grid's own stream, forked after the Galerkin products;
+    the caller's stream waits for it before the first coarse solve.  With a coarsest
+    level of 1122 unknowns (its LU takes far longer than the finest level's descent) a
+    V-cycle issued right after the assembly must equal one issued after the device has
+    gone idle, bit for bit, and also the V-cycle of a grid that held a different
+    operator before (stale factors would show), on the current stream and on a stream
+    of the caller's own."""
+    scn = W.lens_2d(65, 33)
+    scn.levels = 2
+    u_old = torch.as_tensor(W.perturbed_state(scn, 4, sn_lo=0.05, sn_hi=0.5).ravel(), device="cuda")
+    u = torch.as_tensor(W.perturbed_state(scn, 5, sn_lo=0.05, sn_hi=0.5).ravel(), device="cuda")
+    stream = torch.cuda.Stream() if side_stream else None
+    with torch.cuda.stream(stream):  # (None: the current stream)
+        g = tpf.Grid(scn, precision="fp64", stream=stream)
+        f = g.empty()
+        g.assemble_stage(u_old, 32.0)
+        torch.cuda.synchronize()
+        g.assemble_stage(u, 32.0, f0_out=f)
+        x_now = g.precondition(f).clone()      # queued right behind the assembly
+        inv_now = g.coarse_inverse().clone()
+        torch.cuda.synchronize()
+        x_idle = g.precondition(f)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(x_now.cpu().numpy(), x_idle.cpu().numpy())
+        np.testing.assert_array_equal(inv_now.cpu().numpy(), g.coarse_inverse().cpu().numpy())
+        fresh = tpf.Grid(scn, precision="fp64", stream=stream)
+        fresh.assemble_stage(u, 32.0)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(fresh.precondition(f).cpu().numpy(), x_idle.cpu().numpy())
+        fresh.close()
+        g.close()
