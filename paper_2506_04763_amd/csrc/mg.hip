@@ -647,6 +647,52 @@ __global__ void __launch_bounds__(1024) k_lu_panel(double *__restrict__ a, int n
   }
 }
 
+// (best, bi) <- the larger of (best, bi) and (ob, oi): larger magnitude first, then the
+// lower row (a total order, so any reduction order gives the same pivot)
+__device__ __forceinline__ void amax_take(double &best, int &bi, double ob, int oi) {
+  const bool take = (ob > best) | ((ob == best) & (oi < bi));
+  best = take ? ob : best;
+  bi = take ? oi : bi;
+}
+
+// One step of a prefix maximum within each 16-lane row: lane i meets lane i - K (DPP
+// row shift; lanes without a source keep their own pair).
+template <int K>
+__device__ __forceinline__ void amax_row_step(double &best, int &bi) {
+  constexpr int CTRL = 0x110 + K;  // row_shr:K
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, best);
+  const int lo = __builtin_amdgcn_update_dpp((int)(unsigned)b, (int)(unsigned)b, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(unsigned)(b >> 32), (int)(unsigned)(b >> 32), CTRL, 0xf, 0xf,
+                                             false);
+  const int oi = __builtin_amdgcn_update_dpp(bi, bi, CTRL, 0xf, 0xf, false);
+  const double ob = __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+  amax_take(best, bi, ob, oi);
+}
+
+// The wavefront's maximum pair, in every lane: row prefix maxima by DPP (lanes 15, 31,
+// 47 and 63 then hold their rows' maxima), combined from those lanes by readlane.
+__device__ __forceinline__ void amax_wave(double &best, int &bi) {
+  amax_row_step<1>(best, bi);
+  amax_row_step<2>(best, bi);
+  amax_row_step<4>(best, bi);
+  amax_row_step<8>(best, bi);
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, best);
+  const int lo = (int)(unsigned)b, hi = (int)(unsigned)(b >> 32);
+  double wb[4];
+  int wi[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const unsigned l = (unsigned)__builtin_amdgcn_readlane(lo, 16 * k + 15);
+    const unsigned h = (unsigned)__builtin_amdgcn_readlane(hi, 16 * k + 15);
+    wb[k] = __builtin_bit_cast(double, ((unsigned long long)h << 32) | l);
+    wi[k] = __builtin_amdgcn_readlane(bi, 16 * k + 15);
+  }
+  best = wb[0];
+  bi = wi[0];
+#pragma unroll
+  for (int k = 1; k < 4; ++k) amax_take(best, bi, wb[k], wi[k]);
+}
+
 // One column step of k_lu_panel_reg, column C of the panel held in x (row r).
 template <int ROWS, int C>
 __device__ __forceinline__ void lu_panel_column(double (&x)[LU_NB], int r, int m, int j0, int w,
@@ -663,23 +709,24 @@ __device__ __forceinline__ void lu_panel_column(double (&x)[LU_NB], int r, int m
     best = fabs(x[C]);
     bi = r;
   }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const double ob = __shfl_down(best, off, 64);
-    const int oi = __shfl_down(bi, off, 64);
-    if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-  }
+  amax_wave(best, bi);
   if (lane == 0) {
     wbest[q][wv] = best;
     wrow[q][wv] = bi;
   }
   __syncthreads();
-  best = wbest[q][0];
-  bi = wrow[q][0];
+  double wb[NW];
+  int wi[NW];
 #pragma unroll
-  for (int k = 1; k < NW; ++k)
-    if (wbest[q][k] > best || (wbest[q][k] == best && wrow[q][k] < bi)) { best = wbest[q][k]; bi = wrow[q][k]; }
-  const int p = bi;
+  for (int k = 0; k < NW; ++k) {  // all loads first, then the comparisons
+    wb[k] = wbest[q][k];
+    wi[k] = wrow[q][k];
+  }
+  best = wb[0];
+  bi = wi[0];
+#pragma unroll
+  for (int k = 1; k < NW; ++k) amax_take(best, bi, wb[k], wi[k]);
+  const int p = __builtin_amdgcn_readfirstlane(bi);
   if (r == p) {
 #pragma unroll
     for (int cc = 0; cc < LU_NB; ++cc) prow[q][cc] = x[cc];
