@@ -236,7 +236,12 @@ tpf_status tpf_residual(tpf_grid *g, const double *u, double *f, tpf_stream stre
  * coarsest matrix from an LU factorisation with partial pivoting.  u0: device
  * double[2N]; h > 0 seconds.  F(u0) is produced by the same kernel: if f0_out is
  * not NULL it receives F(u0) (device double[2N], the right-hand side of the first
- * substep of a stage). */
+ * substep of a stage).  The coarsest factorisation and inverse run on a stream the
+ * grid creates for them (default priority), forked from `stream` by an event; the
+ * grid's later work on `stream` waits for it where it first needs it (the first
+ * coarse solve, tpf_copy_coarse_inverse, the next assembly or rescale), and
+ * tpf_destroy_grid waits for it on the host.  While `stream` is being captured the
+ * factorisation stays on it. */
 tpf_status tpf_assemble_stage(tpf_grid *g, const double *u0, double h, double *f0_out, tpf_stream stream);
 
 /* Moves the assembled stage operator to another step h > 0 without re-assembling:

@@ -176,7 +176,12 @@ void set_error(const char *fmt, ...);
 // after the factorisation (a grid is used from one stream at a time).
 inline tpf_status lu_join(tpf_grid *g, hipStream_t s) {
   if (g->lu_pending) {
-    TPF_HIP(hipStreamWaitEvent(s, g->lu_done, 0));
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    TPF_HIP(hipStreamIsCapturing(s, &cs));
+    if (cs == hipStreamCaptureStatusNone)
+      TPF_HIP(hipStreamWaitEvent(s, g->lu_done, 0));
+    else  // a stream being captured cannot wait for an event recorded outside the capture
+      TPF_HIP(hipEventSynchronize(g->lu_done));
     g->lu_pending = false;
   }
   return TPF_OK;
