@@ -137,6 +137,23 @@ def test_vcycle_parity_fp64(case):
     g.close()
 
 
+def test_vcycle_parity_mixed(case):
+    """The FP32 V-cycle (FP32 level matrices, FP32 arithmetic, the FP64 coarsest
+    inverse applied to an FP32 right-hand side) against the oracle's FP64 cycle: the
+    FP32 rounding of the matrices (6e-8 relative) and of about a dozen sweeps per level,
+    amplified by the coarse correction, stays below 1e-5 per field (5e-8 to 1.3e-6 on
+    these grids, the layered case 4 the largest)."""
+    scn = case["scn"]
+    g = tpf.Grid(scn, precision="mixed")
+    g.assemble_stage(torch.as_tensor(case["u"].ravel(), device="cuda"), case["h"])
+    b = case["F"]
+    x = g.precondition(torch.as_tensor(b, device="cuda")).cpu().numpy()
+    err = per_field(x, case["ref"].H.vcycle(b))
+    print(case["name"], "mixed V-cycle", err, flush=True)
+    assert err < 1e-5
+    g.close()
+
+
 def test_solve_parity_fp64(case):
     scn = case["scn"]
     g = tpf.Grid(scn, precision="fp64")
@@ -218,23 +235,39 @@ def test_repeat_runs_bitwise_equal(case):
     g.close()
 
 
-def test_corner_pass_rows_equal_inline_rows(case):
+# grids whose finest level can also run as a one-level grid (at most 4096 unknowns), with
+# the layered and polynomial-k_r recipes of Section 5's cases 4 and 5
+CORNER_CASES = [
+    ("lens9x5", lambda: W.lens_2d(9, 5), 2, 50.0),
+    ("lens17x9", lambda: W.lens_2d(17, 9), 3, 50.0),
+    ("cube5", lambda: W.small_cube(5, seed=21), 2, 50.0),
+    ("cube9", lambda: W.small_cube(9, seed=22), 3, 50.0),
+    ("case5_9", lambda: W.case5(9), 3, 2e4),
+    ("case4_16x8", lambda: W.case4(16), 3, 2e4),
+]
+
+
+@pytest.mark.parametrize("name,mk,levels,dp", CORNER_CASES, ids=[c[0] for c in CORNER_CASES])
+def test_corner_pass_rows_equal_inline_rows(name, mk, levels, dp):
     """Grids of several levels evaluate the per-(cell, corner) laws once per pair in a
     corner pass; a one-level grid has no scratch for it, and its rows evaluate the laws
     themselves.  The same state must give the same finest matrix, F(u0) and residual
-    on both, bit for bit (FP64 and the FP32 copy)."""
+    on both, bit for bit (FP64 and the FP32 copy).  One-level grids stop at 4096
+    unknowns (the dense coarsest solve); the larger parity grids are covered by the
+    oracle comparisons above."""
     import copy
-    scn = case["scn"]
-    if 2 * scn.nverts > 4096:
-        pytest.skip("one level only up to 4096 unknowns (the dense coarsest solve)")
+    scn = mk()
+    scn.levels = levels
+    assert 2 * scn.nverts <= 4096
+    u = W.perturbed_state(scn, 5, dp=dp, sn_lo=0.02, sn_hi=0.6)
     one = copy.copy(scn)
     one.levels = 1
-    ut = torch.as_tensor(case["u"].ravel(), device="cuda")
+    ut = torch.as_tensor(u.ravel(), device="cuda")
     out = []
     for s_ in (scn, one):
         g = tpf.Grid(s_, precision="mixed")
         f0 = g.empty()
-        g.assemble_stage(ut, case["h"], f0_out=f0)
+        g.assemble_stage(ut, 32.0, f0_out=f0)
         out.append((g.matrix(0).cpu().numpy(), g.matrix(0, precision="mixed").cpu().numpy(), f0.cpu().numpy(),
                     g.residual(ut).cpu().numpy()))
         g.close()
