@@ -271,7 +271,9 @@ tpf_status tpf_solve_stage(tpf_grid *g, const double *f, double *x, double rtol,
  * the grid's arena.  The assembled hierarchy and the V-cycle's level vectors stay in
  * the arena.  Grids needing more than the array holds (above about 460,000 vertices,
  * e.g. 65^3 fits, 97^3 does not) get TPF_EINVAL with a message.  Calls nothing that
- * allocates.  Every call on one GPU shares that GPU's array: calls that overlap on one
+ * allocates: with tpf_set_coarse_graph on, it replays a graph an earlier
+ * tpf_solve_stage or tpf_precondition captured and never captures one itself (until
+ * then the coarse levels are stream launches).  Every call on one GPU shares that GPU's array: calls that overlap on one
  * GPU (different streams or threads) race and must be serialised by the caller.  The
  * array keeps the last call's contents; the solve initialises everything it reads.
  * The grid's device must be current.  Returns as tpf_solve_stage. */

@@ -508,7 +508,11 @@ tpf_status tpf_solve_stage_static(tpf_grid *g, const double *f, double *x, doubl
   g->part = reinterpret_cast<double *>(c);
   c += align_up(4 * (size_t)g->npart * sizeof(double));
   g->scal = reinterpret_cast<double *>(c);
+  // a coarse-level graph is replayed if one exists; capturing one would allocate
+  const int saved_graph = g->coarse_graph;
+  if (!g->vgraph_exec) g->coarse_graph = 0;
   st = bicgstab(g, f, x, rtol, maxit, stats, reinterpret_cast<hipStream_t>(stream));
+  g->coarse_graph = saved_graph;
   for (int k = 0; k < 9; ++k) *kv[k] = saved[k];
   g->part = saved_part;
   g->scal = saved_scal;

@@ -68,6 +68,29 @@ def test_static_solve_with_the_line_smoother():
         g.close()
 
 
+def test_static_solve_with_the_coarse_graph_enabled():
+    """With the coarse-level graph switched on before any V-cycle has captured it, the
+    static solve runs the coarse levels as stream launches (capturing would allocate);
+    after an arena solve has captured the graph, the static solve replays it.  Both equal
+    the arena solve bit for bit."""
+    scn = W.small_cube(17, sigma=1.5, seed=41, levels=4)
+    g, f = _system(scn, "mixed", 8)
+    g.set_coarse_graph(True)
+    status, x0, st0 = _static_solve(g, f, 1e-8)  # no graph yet
+    torch.cuda.synchronize()
+    assert status == L.TPF_OK, L.last_error()
+    x_ref, st_ref = g.solve_stage(f, rtol=1e-8, maxit=400)  # captures the graph
+    status, x1, st1 = _static_solve(g, f, 1e-8)  # replays it
+    torch.cuda.synchronize()
+    assert status == L.TPF_OK, L.last_error()
+    print(f"[no-alloc] coarse graph: static {st0['iters']} / {st1['iters']} its, arena {st_ref['iters']} its",
+          flush=True)
+    for x, st in ((x0, st0), (x1, st1)):
+        assert st["iters"] == st_ref["iters"]
+        np.testing.assert_array_equal(x.cpu().numpy(), x_ref.cpu().numpy())
+    g.close()
+
+
 def test_static_solve_rejects_an_oversize_grid():
     scn = W.small_cube(81, seed=3, levels=5)  # 531,441 vertices: 76 MB of Krylov vectors
     g, f = _system(scn, "mixed", 2)
