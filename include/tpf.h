@@ -350,11 +350,13 @@ tpf_status tpf_project_pressure(tpf_grid *g, double *u, double h_p, const tpf_ne
  * (tpf_profile_begin) the stream launches are used.  Returns TPF_OK or TPF_EINVAL. */
 tpf_status tpf_set_coarse_graph(tpf_grid *g, int32_t enable);
 
-/* TPF_SMOOTH_LINE: levels with fewer than max_lines vertex lines solve each line with
- * two threads (the two chains of its twisted factorisation, exchanging their edge
- * values), levels with more with one thread per line running both chains in turn
- * (default 32768; 0: one thread per line everywhere).  Both do the same operations in
- * the same order, so results are identical.  Returns TPF_OK or TPF_EINVAL. */
+/* TPF_SMOOTH_LINE: levels with fewer than max_lines vertex lines factor and solve each
+ * line with two threads (the two halves of its twisted factorisation, exchanging their
+ * edge values), levels with more with one thread per line running both halves in turn
+ * (default 32768; 0: one thread per line everywhere).  The solve follows the setting at
+ * once, the factorisation from the next assembly or rescale.  Both do the same
+ * operations in the same order, so results are identical.  Returns TPF_OK or
+ * TPF_EINVAL. */
 tpf_status tpf_set_line_pairs(tpf_grid *g, int64_t max_lines);
 
 /* ---- inspection hooks (used by the parity tests and the benchmark) ---------- */

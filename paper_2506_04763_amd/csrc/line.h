@@ -50,8 +50,9 @@ struct LineOff {
   static constexpr int P = DIM == 3 ? 22 : 7;  // +1 along the last axis
 };
 
-// a b + c, rounded once: the recurrences below spell out every fused multiply-add, so
-// that each kernel built from them (and the CPU build) rounds alike.
+// a b + c, rounded once: the factorisation and the recurrences below spell out every
+// fused multiply-add, so that each kernel built from them (and the CPU build) rounds
+// alike.
 __host__ __device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __host__ __device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
@@ -62,10 +63,10 @@ __host__ __device__ __forceinline__ T dot2(T a0, T a1, T x0, T x1) {
 }
 
 __host__ __device__ __forceinline__ void mul22(const double (&a)[4], const double (&b)[4], double (&c)[4]) {
-  c[0] = a[0] * b[0] + a[1] * b[2];
-  c[1] = a[0] * b[1] + a[1] * b[3];
-  c[2] = a[2] * b[0] + a[3] * b[2];
-  c[3] = a[2] * b[1] + a[3] * b[3];
+  c[0] = dot2(a[0], a[1], b[0], b[2]);
+  c[1] = dot2(a[0], a[1], b[1], b[3]);
+  c[2] = dot2(a[2], a[3], b[0], b[2]);
+  c[3] = dot2(a[2], a[3], b[1], b[3]);
 }
 
 // Pivot block d (FP64) of vertex v -> G, V = G L, W = G U stored in lf; returns false if d
@@ -74,7 +75,7 @@ template <int DIM, typename TO>
 __host__ __device__ __forceinline__ bool line_store(const double (&d)[4], const double (&lo)[4],
                                                    const double (&up)[4], TO *__restrict__ lf, long long N,
                                                    long long v, double (&vv)[4], double (&ww)[4]) {
-  const double det = d[0] * d[3] - d[1] * d[2];
+  const double det = fma_(d[0], d[3], -(d[1] * d[2]));
   double gi[4];
   gi[0] = d[3] / det;
   gi[1] = -d[1] / det;

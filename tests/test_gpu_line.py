@@ -146,11 +146,12 @@ def test_line_converges_where_point_smoothing_stalls():
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_one_thread_and_two_threads_per_line_agree(case, prec):
-    """Levels below the line-count threshold solve each line with a pair of threads
-    (the twisted factorisation's two chains), the others with one thread running both
-    chains in turn: the same operations in the same order, so one V-cycle is bitwise
-    identical either way (threshold 0 forces one thread everywhere), and matches the
-    oracle."""
+    """Levels below the line-count threshold factor and solve each line with a pair of
+    threads (the twisted factorisation's two halves), the others with one thread running
+    both halves in turn: the same operations in the same order, so one V-cycle is bitwise
+    identical either way (threshold 0 forces one thread everywhere: set after the
+    assembly it switches the solve, set before it the factorisation too), and matches
+    the oracle."""
     g = _grid(case, prec)
     b = torch.as_tensor(case["F"], device="cuda")
     x_pairs = g.precondition(b).cpu().numpy()
@@ -158,6 +159,12 @@ def test_one_thread_and_two_threads_per_line_agree(case, prec):
     x_single = g.precondition(b).cpu().numpy()
     g.close()
     np.testing.assert_array_equal(x_pairs, x_single)
+    g1 = tpf.Grid(case["scn"], precision=prec, smoother="line")
+    g1.set_line_pairs(0)
+    g1.assemble_stage(torch.as_tensor(case["u"].ravel(), device="cuda"), case["h"])
+    x_single_lu = g1.precondition(b).cpu().numpy()
+    g1.close()
+    np.testing.assert_array_equal(x_pairs, x_single_lu)
     assert per_field(x_single, case["ref"].H.vcycle(case["F"])) < (1e-10 if prec == "fp64" else 1e-4)
 
 
