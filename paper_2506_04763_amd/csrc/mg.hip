@@ -764,11 +764,11 @@ __device__ __forceinline__ void lu_panel_columns(std::integer_sequence<int, C...
 // The same panel factorisation for panels of at most ROWS rows (256 or 1024), with each
 // row's LU_NB entries in the registers of one thread (one column step per compile-time
 // column index, so the row needs no LDS or scratch).  A column step is a pivot search
-// (wavefront shuffles, then the wavefront maxima through LDS), the row interchange
-// through LDS, and the rank-1 update of every thread's own row with the pivot row read
-// from LDS: two barriers per column.  The LDS
-// buffers alternate between columns, so a column's writes never meet the previous
-// column's reads.  The arithmetic is that of the other panel kernels, entry for entry.
+// (DPP row steps and readlanes within each wavefront, then the wavefront maxima through
+// LDS), the row interchange through LDS, and the rank-1 update of every thread's own row
+// with the pivot row read from LDS: two barriers per column.  The LDS buffers alternate
+// between columns, so a column's writes never meet the previous column's reads.  The
+// arithmetic is that of the other panel kernels, entry for entry.
 template <int ROWS>
 __global__ void __launch_bounds__(ROWS) k_lu_panel_reg(double *__restrict__ a, int n, int j0, int w,
                                                        int *__restrict__ piv) {
