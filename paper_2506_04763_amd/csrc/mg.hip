@@ -61,7 +61,10 @@ __device__ __forceinline__ void load_block(const T *p, T (&b)[4]) {
 // copied out for the smoother, which then needs no load after the row.  Neighbours
 // outside the grid have zero blocks; their x value is read at the clamped (valid)
 // position and masked to zero, so no load depends on a branch.
-template <int DIM, typename T, typename TX, bool NT = false, bool TILED = false, int GROUP = 0, typename AS = T>
+// SKIPLINE: the row of A - A_L, without the three blocks that couple the vertex with
+// itself and its two neighbours along the last axis (the line part; no loads for them).
+template <int DIM, typename T, typename TX, bool NT = false, bool TILED = false, int GROUP = 0, typename AS = T,
+          bool SKIPLINE = false>
 __device__ __forceinline__ void row_apply(const Geo &G, long long v, const AS *__restrict__ A,
                                           const TX *__restrict__ x, T &y0, T &y1, T (&dblk)[4],
                                           T *xc = nullptr) {
@@ -89,6 +92,7 @@ __device__ __forceinline__ void row_apply(const Geo &G, long long v, const AS *_
     for (int k = 0; k < GRP; ++k) {
       const int o = g0 + k;
       const int ax = o % 3, ay = (o / 3) % 3, az = DIM == 3 ? o / 9 : 1;
+      if (SKIPLINE && (DIM == 3 ? o % 9 == 4 : o % 3 == 1)) continue;
       if constexpr (sizeof(AS) == 2)
         load_block16(A + ((long long)o * G.N + v) * 4, b[k]);
       else
@@ -99,6 +103,7 @@ __device__ __forceinline__ void row_apply(const Geo &G, long long v, const AS *_
     for (int k = 0; k < GRP; ++k) {
       const int o = g0 + k;
       const int ax = o % 3, ay = (o / 3) % 3, az = DIM == 3 ? o / 9 : 1;
+      if (SKIPLINE && (DIM == 3 ? o % 9 == 4 : o % 3 == 1)) continue;
       if (o == CEN) {
         dblk[0] = b[k][0]; dblk[1] = b[k][1]; dblk[2] = b[k][2]; dblk[3] = b[k][3];
         if (xc) {
@@ -267,15 +272,22 @@ __global__ void __launch_bounds__(BS) TPF_STREAM_ATTR k_jacobi_stream(const Geo 
   jacobi_vertex<DIM, T, TO, false, true, true>(G, A, b, xi, xo, omega, v);
 }
 
-// r = b - A x at one vertex of a level.
-template <int DIM, typename T, bool NT = false, bool TILED = false, bool LAT = false>
+// r = b - A x at one vertex of a level.  OFFLINE: r = bscale b - (A - A_L) x, which is
+// b - A x for x = omega A_L^{-1} b and bscale = 1 - omega (A_L x = omega b): the
+// residual after a line sweep from a zero guess, without the line blocks.
+template <int DIM, typename T, bool NT = false, bool TILED = false, bool LAT = false, bool OFFLINE = false>
 __device__ __forceinline__ void resid_vertex(const Geo &G, const T *__restrict__ A, const T *__restrict__ b,
-                                             const T *__restrict__ x, T *__restrict__ r, long long v) {
+                                             const T *__restrict__ x, T *__restrict__ r, long long v,
+                                             T bscale = (T)1) {
   T a0, a1, d[4];
   typename Vec2<T>::type bb;
   if (LAT) bb = *reinterpret_cast<const typename Vec2<T>::type *>(b + 2 * v);
-  row_apply<DIM, T, T, NT, TILED, LAT ? (DIM == 3 ? 27 : 9) : 0>(G, v, A, x, a0, a1, d);
+  row_apply<DIM, T, T, NT, TILED, LAT ? (DIM == 3 ? 27 : 9) : 0, T, OFFLINE>(G, v, A, x, a0, a1, d);
   if (!LAT) bb = *reinterpret_cast<const typename Vec2<T>::type *>(b + 2 * v);
+  if constexpr (OFFLINE) {
+    bb.x *= bscale;
+    bb.y *= bscale;
+  }
   if constexpr (NT && TILED) {  // streaming residual: the result bypasses the caches
     __builtin_nontemporal_store(bb.x - a0, r + 2 * v);
     __builtin_nontemporal_store(bb.y - a1, r + 2 * v + 1);
@@ -287,28 +299,30 @@ __device__ __forceinline__ void resid_vertex(const Geo &G, const T *__restrict__
   }
 }
 
-template <int DIM, typename T>
+template <int DIM, typename T, bool OFFLINE = false>
 __global__ void __launch_bounds__(BS) TPF_STREAM_ATTR k_resid_stream(const Geo G, const T *__restrict__ A,
                                                                      const T *__restrict__ b,
-                                                                     const T *__restrict__ x, T *__restrict__ r);
+                                                                     const T *__restrict__ x, T *__restrict__ r,
+                                                                     const T bscale);
 
-template <int DIM, typename T, bool NT = false, bool LAT = false>
+template <int DIM, typename T, bool NT = false, bool LAT = false, bool OFFLINE = false>
 __global__ void __launch_bounds__(BS) k_resid(const Geo G, const T *__restrict__ A, const T *__restrict__ b,
-                                              const T *__restrict__ x, T *__restrict__ r) {
+                                              const T *__restrict__ x, T *__restrict__ r, const T bscale) {
   const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
   const long long v = (long long)blk * BS + threadIdx.x;
   if (v >= G.N) return;
-  resid_vertex<DIM, T, NT, false, LAT>(G, A, b, x, r, v);
+  resid_vertex<DIM, T, NT, false, LAT, OFFLINE>(G, A, b, x, r, v, bscale);
 }
 
-template <int DIM, typename T>
+template <int DIM, typename T, bool OFFLINE>
 __global__ void __launch_bounds__(BS) TPF_STREAM_ATTR k_resid_stream(const Geo G, const T *__restrict__ A,
                                                                      const T *__restrict__ b,
-                                                                     const T *__restrict__ x, T *__restrict__ r) {
+                                                                     const T *__restrict__ x, T *__restrict__ r,
+                                                                     const T bscale) {
   const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
   const long long v = (long long)blk * BS + threadIdx.x;
   if (v >= G.N) return;
-  resid_vertex<DIM, T, true, true>(G, A, b, x, r, v);
+  resid_vertex<DIM, T, true, true, false, OFFLINE>(G, A, b, x, r, v, bscale);
 }
 
 // Coarse levels stored in FP16 with a scale per scalar row (TPF_MIXED16): the raw
@@ -1255,19 +1269,31 @@ tpf_status vcycle_t(tpf_grid *g, const double *bin, double *xout, hipStream_t s,
   };
   const bool line = g->smoother == TPF_SMOOTH_LINE;
   // r = b - A x on level l into R
-  auto resid = [&](int l, const T *b, const T *x, T *R, hipStream_t s) -> tpf_status {
+  // r = b - A x; after_zero_sweep: x = omega A_L^{-1} b (one line sweep from a zero
+  // guess), so r = (1 - omega) b - (A - A_L) x needs 24 of the 27 blocks of each row
+  auto resid = [&](int l, const T *b, const T *x, T *R, hipStream_t s, bool after_zero_sweep = false) -> tpf_status {
     Level &lv = g->lv[l];
     const Geo G = geo(lv);
     const unsigned nb = blocks_for(lv.N);
     const int c_re = l == 0 ? TPF_K_RESID0 : TPF_K_COARSE_LEVELS;
+    const T one = (T)1, bs = (T)1 - om;
     if (resid16<DIM, T>(g, l, b, x, R, s)) {
       TPF_LAUNCH_CHECK();
     } else if (l == 0 && NT0) {
-      TPF_HIP(launch(g, c_re, k_resid_stream<DIM, T>, nb, BS, s, G, A_of(l), b, x, R));
+      if (after_zero_sweep)
+        TPF_HIP(launch(g, c_re, k_resid_stream<DIM, T, true>, nb, BS, s, G, A_of(l), b, x, R, bs));
+      else
+        TPF_HIP(launch(g, c_re, k_resid_stream<DIM, T, false>, nb, BS, s, G, A_of(l), b, x, R, one));
     } else if (lv.N > LAT_NMAX) {
-      TPF_HIP(launch(g, c_re, k_resid<DIM, T>, nb, BS, s, G, A_of(l), b, x, R));
+      if (after_zero_sweep)
+        TPF_HIP(launch(g, c_re, k_resid<DIM, T, false, false, true>, nb, BS, s, G, A_of(l), b, x, R, bs));
+      else
+        TPF_HIP(launch(g, c_re, k_resid<DIM, T>, nb, BS, s, G, A_of(l), b, x, R, one));
     } else {
-      TPF_HIP(launch(g, c_re, k_resid<DIM, T, false, true>, nb, BS, s, G, A_of(l), b, x, R));
+      if (after_zero_sweep)
+        TPF_HIP(launch(g, c_re, k_resid<DIM, T, false, true, true>, nb, BS, s, G, A_of(l), b, x, R, bs));
+      else
+        TPF_HIP(launch(g, c_re, k_resid<DIM, T, false, true>, nb, BS, s, G, A_of(l), b, x, R, one));
     }
     return TPF_OK;
   };
@@ -1335,7 +1361,7 @@ tpf_status vcycle_t(tpf_grid *g, const double *bin, double *xout, hipStream_t s,
     cur[l] = X;
     T *R = reinterpret_cast<T *>(lv.r);
     {
-      const tpf_status st = resid(l, bl[l], (const T *)X, R, s);
+      const tpf_status st = resid(l, bl[l], (const T *)X, R, s, line && g->nu_pre == 1);
       if (st != TPF_OK) return st;
     }
     Level &lc = g->lv[l + 1];
