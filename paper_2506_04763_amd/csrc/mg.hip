@@ -684,7 +684,9 @@ __device__ __forceinline__ void amax_row_step(double &best, int &bi) {
 }
 
 // The wavefront's maximum pair, in every lane: row prefix maxima by DPP (lanes 15, 31,
-// 47 and 63 then hold their rows' maxima), combined from those lanes by readlane.
+// 47 and 63 then hold their rows' maxima), combined from those lanes by readlane.  All
+// 64 lanes must be active (the panel kernels launch whole wavefronts and call this with
+// uniform control flow).
 __device__ __forceinline__ void amax_wave(double &best, int &bi) {
   amax_row_step<1>(best, bi);
   amax_row_step<2>(best, bi);
@@ -912,7 +914,7 @@ __global__ void __launch_bounds__(64) k_lu_inverse(const double *__restrict__ lu
   int pos = j;
 #pragma unroll
   for (int q = 0; q < NBMAX; ++q) {
-    if (q >= NB) break;
+    if (q >= NB) continue;  // (not break: a constant trip count unrolls fully)
     const int rmax = min(64, n - 64 * q);
     for (int r = 0; r < rmax; ++r) {
       const int k = 64 * q + r;
@@ -926,7 +928,7 @@ __global__ void __launch_bounds__(64) k_lu_inverse(const double *__restrict__ lu
   // L y = P e_j
 #pragma unroll
   for (int kb = 0; kb < NBMAX; ++kb) {
-    if (kb >= NB) break;
+    if (kb >= NB) continue;
     const int rc = min(64 * kb + lane, n - 1);
     const int cmax = min(64, n - 64 * kb);  // columns of this block inside the matrix
 #pragma unroll 16
@@ -939,7 +941,7 @@ __global__ void __launch_bounds__(64) k_lu_inverse(const double *__restrict__ lu
     // the blocks below, each staged in LDS by one burst of loads
 #pragma unroll
     for (int q = kb + 1; q < NBMAX; ++q) {
-      if (q >= NB) break;
+      if (q >= NB) continue;
       const int rq = min(64 * q + lane, n - 1);
 #pragma unroll 16
       for (int c = 0; c < 64; ++c) E[c * 64 + lane] = lu[(long long)min(64 * kb + c, n - 1) * n + rq];
