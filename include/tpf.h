@@ -212,7 +212,9 @@ size_t tpf_grid_bytes(const tpf_grid_desc *desc);
  * tpf_grid_bytes(desc) bytes, 256-byte aligned, owned by the caller and kept
  * alive until tpf_destroy_grid).  Uploads the scenario and runs the per-vertex
  * pre-processing (p_dmin and reference medium, Eq. pdmin; Neumann sources) on
- * stream, then synchronises the stream so the host arrays may be freed.
+ * stream, then synchronises the stream so the host arrays may be freed.  The grid
+ * belongs to the device current at this call; every later call on the grid expects
+ * that device to be current (the streams the library creates for it are created there).
  * Errors: TPF_EINVAL (descriptor), TPF_ENOMEM (arena), TPF_EDEVICE. */
 tpf_status tpf_create_grid(const tpf_grid_desc *desc, void *arena, size_t arena_bytes,
                            tpf_stream stream, tpf_grid **out);
