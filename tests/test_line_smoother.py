@@ -150,3 +150,18 @@ def test_line_smoothing_removes_the_stall_of_point_smoothing_on_layers():
 def test_unknown_smoother_is_rejected():
     with pytest.raises(ValueError):
         G.Hierarchy(sp.identity(4, format="csr"), (2, 1, 1), 2, 1, np.zeros(2, np.uint8), smoother="gauss")
+
+
+@pytest.mark.parametrize("n,dim", [((5, 4, 1), 2), ((4, 3, 5), 3)])
+def test_residual_after_a_zero_guess_sweep_needs_no_line_blocks(n, dim):
+    """After one damped line sweep from a zero guess, x = omega A_L^{-1} b, so
+    b - A x = (1 - omega) b - (A - A_L) x: the identity the library's restriction
+    residual uses to skip the line blocks of every row."""
+    A, _ = _random_stencil_matrix(n, dim, 6)
+    H = G.Hierarchy(A, n, dim, 1, np.zeros(n[0] * n[1] * n[2], np.uint8), omega=0.9, smoother="line")
+    b = np.random.default_rng(7).standard_normal(A.shape[0])
+    x = H.smooth(0, np.zeros_like(b), b, 1)
+    AL = G.line_part(A, n, dim)
+    direct = b - A @ x
+    off = (1.0 - 0.9) * b - (A - AL) @ x
+    np.testing.assert_allclose(off, direct, rtol=0, atol=1e-12 * np.abs(b).max())
